@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark of the pseudo-projection sweep on one MI355X.
+
+Workload (one "step" = one full iteration of the method on one GPU: the fused
+sweep over A -- residuals, violated-row mask, positive-slice sum y, eps test,
+and the translation of the system by that iteration's drift vector, b <- b + A v
+-- then the fixed-order reduction of y with the ModAP step x <- x - lambda
+y/||y||):
+
+  FP32 non-stationary Gaussian system, n = 8192, m = 16384, rows a_i ~ N(0,1)
+  normalised and stored FP32; hidden point z ~ U(-1,1)^n, b = A z + U(0,1);
+  drift v ~ N(0, 1e-2^2)^n per iteration; x0 = 0; lambda = 1;
+  eps = 1e-6 * ||b||_inf.
+
+The timed loop runs in tracking mode (an eps-feasible check takes no step but
+the system keeps moving), so every timed step reads all of A.
+
+Printed JSON line: `value` is the whole-job algorithmic HBM throughput of the
+timed steps, m*n*4 + 24*m bytes per step (A, b read and written, ||a_i||^2),
+divided by wall time; `roofline` is the same byte count over the sweep
+kernel's average duration (HIP events on the library's stream); time-to-feasible
+p50/p99 comes from solves of the FP64 box-plus-sum system (n=256, m=513,
+20 seeds) and of the FP32 system above; `cpu_baseline` times the CPU oracle on
+a bounded number of iterations of the same system.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "pseudo-projection sweep HBM GB/s (% of peak); p50/p99 time-to-feasible"
+COUNTERS = os.path.join(ROOT, "profiles", "sweep_f32_n8192_m16384_counters.json")
+KERNEL_SOURCES = ["paper_2003_09956_amd/csrc/sweep_wide.hpp", "paper_2003_09956_amd/csrc/modap_device.hpp",
+                  "paper_2003_09956_amd/csrc/sweep_f32.hip", "paper_2003_09956_amd/csrc/sweep_inst.inc"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=float), q)) if xs else None
+
+
+def measured_traffic(tile):
+    """HBM bytes per sweep launch from committed rocprofv3 counters, if they were
+    taken on the current kernel source and shape (else None)."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_hash") != kernel_source_hash() or c.get("tile") != tile:
+        return None
+    return c.get("bytes_per_launch")
+
+
+def time_to_feasible(P, W, seeds):
+    """FP64 stationary box-plus-sum system: solve from x0 = 400 + U(0,100)."""
+    out, iters = [], []
+    prm = P.params(lam=1.0, eps=1e-6, max_iters=100000)
+    with P.Solver(0) as s:
+        for seed in seeds:
+            sys_ = W.c1(seed)
+            s.set_system(sys_.A, sys_.b, x0=sys_.x0, dtype="f64")
+            st, code = s.solve(prm)
+            if code != 0:
+                raise RuntimeError(f"box-sum seed {seed}: solve status {code}")
+            out.append(st.seconds * 1e3)
+            iters.append(st.iters)
+    return out, iters
+
+
+def cpu_baseline(sys_, V, seconds_budget):
+    """The CPU oracle, as it is, on the same system: iterations of translate +
+    sweep + step, single thread, bounded to about `seconds_budget` seconds."""
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    oracle.solve(sys_.A, "f32", sys_.b, sys_.x0, lam=1.0, eps=1e-300, eps_relative=False,
+                 rule=0, max_steps=1, V=V[:1])
+    one = time.perf_counter() - t0
+    steps = max(1, int(seconds_budget / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    res = oracle.solve(sys_.A, "f32", sys_.b, sys_.x0, lam=1.0, eps=1e-300, eps_relative=False,
+                       rule=0, max_steps=steps, V=V[:steps])
+    dt = time.perf_counter() - t0
+    assert res.iters == steps
+    return steps, dt
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttf", action="store_true", help="skip the time-to-feasible solves")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              f"(the sweep runs on a single MI355X; row sharding across GPUs is not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2003_09956_amd as P
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    P.lib()
+
+    K, WU = args.steps, args.warmup
+    sigma, lam, eps = 1e-2, 1.0, 1e-6
+    log("generating n=8192 m=16384 FP32 system ...")
+    sys_ = W.c2(args.seed)
+    V = W.drift(sys_.n, K + WU, sigma=sigma, seed=args.seed)
+    m, n = sys_.m, sys_.n
+    bytes_per_step = m * n * 4 + 24 * m
+
+    with P.Solver(0) as s:
+        s.set_system(sys_.A, sys_.b, dtype="f32")
+        s.set_drift(V)
+        tile = s.get_tile()
+        log("tile", tile)
+        track = P.params(lam=lam, eps=eps, track=True)
+        s.iterate(WU, track)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = s.iterate(K, P.params(lam=lam, eps=eps, track=True, profile=True))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if st.sweeps != K + WU or st.profiled != K:
+            raise RuntimeError(f"timed region ran {st.sweeps - WU} sweeps, expected {K}")
+        wall = t1 - t0
+        sweep_us = st.sweep_ms * 1e3 / st.profiled
+        reduce_us = st.reduce_ms * 1e3 / st.profiled
+        feasible_steps = int(st.sweeps - st.iters)
+        log(f"timed {K} steps in {wall * 1e3:.2f} ms; sweep {sweep_us:.1f} us, reduce {reduce_us:.1f} us")
+
+        # time-to-feasible on the same moving system, from x0 = 0
+        ttf_c2 = None
+        if not args.no_ttf:
+            s.set_system(sys_.A, sys_.b, dtype="f32")
+            V2 = W.drift(n, 3000, sigma=sigma, seed=args.seed + 1)
+            s.set_drift(V2)
+            st2, code = s.solve(P.params(lam=lam, eps=eps, max_iters=3000), raise_on_stop=False)
+            ttf_c2 = {"caught": code == 0, "ms": st2.seconds * 1e3, "steps": int(st2.iters),
+                      "max_violation": st2.max_viol, "eps_abs": st2.eps_abs}
+            log("ttf n=8192", ttf_c2)
+
+    value = bytes_per_step * K / wall / 1e9
+    achieved = bytes_per_step / (sweep_us * 1e-6) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": WU,
+        "ms_per_step": round(wall * 1e3 / K, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "FP32 non-stationary Gaussian system n=8192 m=16384, "
+                               "drift N(0,1e-2^2) per coordinate per iteration, lambda=1, "
+                               "eps=1e-6*||b||inf, ModAP fixed-length step",
+                   "n": n, "m": m, "storage": "f32", "accumulate": "f32 dot, f64 scalars",
+                   "bytes_per_step": bytes_per_step, "tile": tile},
+        "pct_of_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        "iterations_per_s": round(K / wall, 1),
+        "feasible_checks_in_timed_steps": feasible_steps,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(tile),
+                     "kernel": f"sweep_wide<1,{tile['block']},{tile['lanes_per_row']},{tile['chunks']},true>",
+                     "avg_us": round(sweep_us, 3), "reduce_avg_us": round(reduce_us, 3)},
+    }
+    if not args.no_ttf:
+        ms, its = time_to_feasible(P, W, range(20))
+        line["time_to_feasible"] = {
+            "box_sum_f64_n256_m513": {"p50_ms": round(percentile(ms, 50), 3), "p99_ms": round(percentile(ms, 99), 3),
+                                      "seeds": 20, "steps_p50": percentile(its, 50)},
+            "gaussian_f32_n8192_m16384_drift": ttf_c2,
+        }
+    if not args.no_cpu_baseline:
+        steps, dt = cpu_baseline(sys_, V, args.cpu_seconds)
+        line["cpu_baseline"] = {"value": round(bytes_per_step * steps / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"{steps} iterations (translate, sweep, step) of the full n=8192 m=16384 "
+                                          f"FP32 system, {dt:.1f} s, single-threaded extended-precision oracle"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * modap.h -- C ABI of the MI355X (gfx950) pseudo-projection sweep library.
+ *
+ * The library finds an eps-feasible point of a (possibly changing) system of
+ * linear inequalities  A x <= b  with the modified pseudo-projection method
+ * (ModAP) of Sokolinsky & Sokolinskaya, "Scalable Parallel Algorithm for
+ * Solving Non-stationary Systems of Linear Inequalities":
+ *
+ *   one sweep at x:   r_i = <a_i, x> - b_i                        (section 2)
+ *                     rho+_i = max(r_i, 0)/||a_i||^2 * a_i          (eq. 7)
+ *                     y = sum_i rho+_i,  h = #{i : r_i > 0}         (section 3, Map/Reduce)
+ *                     dmax = max_i max(r_i, 0)/||a_i||             (eq. 10)
+ *   stop when         dmax <= eps_abs                               (eq. 10; see modap_params)
+ *   step              x <- x - lambda * y/||y||                     (eq. 12, ModAP)
+ *                  or x <- x - (lambda/h) * y                       (Algorithm 1, relaxed;
+ *                                                                    phi = y/h, eq. 8)
+ *   data update       translation of the feasible set by +v:  b <- b + A v,
+ *                     or replacement of rows (a_i, b_i)             (sections 1, 3, 5)
+ *
+ * Conventions for every entry point:
+ *  - Plain C types only; no exception crosses the boundary; every call returns
+ *    a modap_status (MODAP_OK = 0).  modap_last_error() gives a message.
+ *  - Ownership: caller buffers are only read (or written, for outputs) during
+ *    the call -- or, for stream-ordered inputs on the device, by work queued on
+ *    the context's stream before the call returns -- and are never retained.
+ *    Every device buffer the library uses belongs to the context.
+ *  - ptrs_on_device: 0 = caller pointers are host memory; 1 = device memory
+ *    of the context's GPU (e.g. torch.Tensor.data_ptr() of a tensor on it).
+ *  - Ordering: work is queued on the context's stream in call order.
+ *    set_system, set_x, set_drift, update_coeffs and iterate (without stats)
+ *    are asynchronous with respect to the host once host inputs are copied;
+ *    solve, eval_sweep, query and any call given a stats pointer synchronise.
+ *  - Layout: A is dense row-major, row i at A + i*lda elements, lda >= n, in
+ *    the storage type; b is m doubles; x, v are n doubles.  BF16 elements are
+ *    the upper 16 bits of an IEEE binary32 (uint16 bit patterns).
+ *  - Precision: rows are stored as given; ||a_i||^2, b, x, y, the stop test
+ *    and the step are FP64.  Dot products accumulate in FP64 for MODAP_F64
+ *    storage and in FP32 for MODAP_F32 / MODAP_BF16 storage.
+ *  - Threading: a context is used by one host thread at a time; several
+ *    contexts may share a device.
+ */
+#ifndef MODAP_H
+#define MODAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct modap_ctx modap_ctx;
+
+typedef enum {
+    MODAP_OK = 0,
+    MODAP_E_INVAL = 1,          /* bad argument: sizes, NULL, lda < n, non-finite input, lambda<=0, eps<=0 */
+    MODAP_E_ZERO_ROW = 2,       /* a row a_i is zero (section 2 assumes a_i != 0) or not finite */
+    MODAP_E_NOMEM = 3,          /* device or pinned-host allocation failed */
+    MODAP_E_DEVICE = 4,         /* HIP runtime error; the context must be destroyed */
+    MODAP_E_STATE = 5,          /* call before modap_set_system, or the context is broken */
+    MODAP_E_NOT_CONVERGED = 6,  /* solve: max_iters steps taken without reaching eps-feasibility */
+    MODAP_E_INFEASIBLE = 7,     /* a row is violated but y = 0: no step direction (cannot
+                                   happen for a feasible system: <x - z, y> > 0 for z in M) */
+    MODAP_E_NUMERIC = 8         /* a NaN or infinity appeared in the iteration */
+} modap_status;
+
+typedef enum { MODAP_F64 = 0, MODAP_F32 = 1, MODAP_BF16 = 2 } modap_dtype;
+
+typedef enum {
+    MODAP_STEP_FIXED = 0,   /* ModAP, eq. 12: x <- x - lambda*y/||y||  (step of length lambda)  */
+    MODAP_STEP_AVG = 1      /* Algorithm 1 relaxed: x <- x - (lambda/h)*y; lambda = 1 is Alg. 1 */
+} modap_step;
+
+typedef struct {
+    double lambda;          /* > 0: step length (FIXED) or relaxation (AVG) */
+    double eps;             /* > 0: stop tolerance */
+    int32_t eps_relative;   /* != 0: eps_abs = eps * max_i |b_i| of the current data; else eps_abs = eps */
+    int32_t step;           /* modap_step */
+    int64_t max_iters;      /* solve: at most this many steps in the call (>= 0) */
+    int32_t profile;        /* != 0: time every sweep and reduction with HIP events (stats) */
+    int32_t track;          /* iterate only: != 0 keeps following a changing system -- an
+                               eps-feasible check takes no step but does not stop the queued
+                               iterations, so drift keeps being applied and re-checked */
+} modap_params;
+
+typedef struct {
+    int64_t iters;          /* steps taken since modap_set_system / modap_set_x */
+    int64_t sweeps;         /* sweeps (feasibility checks) since then */
+    int32_t converged;      /* 1 if the last check found x eps-feasible */
+    int32_t state;          /* 0 running, 1 converged, 2 no direction, 3 numeric, 4 step limit, 5 bad row */
+    double max_viol;        /* last check: max_i max(r_i, 0)/||a_i|| */
+    int64_t h;              /* last check: number of violated rows */
+    double y_norm;          /* last check: ||y|| */
+    double b_inf;           /* last check: max_i |b_i| */
+    double eps_abs;         /* last check: the threshold applied */
+    double seconds;         /* host wall time of this call */
+    double hbm_bytes;       /* algorithmic bytes of the sweeps launched in this call:
+                               m*n*sizeof(A) + 16m (+ 8m when a translation is applied) each */
+    double sweep_ms;        /* profile: summed duration of the sweep kernels of this call */
+    double reduce_ms;       /* profile: summed duration of the reduction kernels of this call */
+    int64_t profiled;       /* profile: number of sweeps timed in this call */
+} modap_stats;
+
+/* Kernel shape of the sweep (see modap_set_tile).  kind 0 = one pass with a
+ * whole row on chip, kind 1 = split-row two-phase form for very long rows. */
+typedef struct {
+    int32_t kind;
+    int32_t block;          /* threads per workgroup */
+    int32_t lanes_per_row;  /* threads that share one row (64 .. block) */
+    int32_t chunks;         /* 16-byte vectors per thread per row (kind 0) or per column tile (kind 1) */
+    int32_t grid;           /* workgroups of the sweep */
+    int32_t reserved;
+} modap_tile;
+
+/* Create a context on HIP device `device`.  hip_stream: the hipStream_t to
+ * queue all work on (the caller keeps it alive for the context's life), or
+ * NULL for the device's default (null) stream, which is ordered with the
+ * default stream of PyTorch.  Errors: E_INVAL (out == NULL or no such
+ * device), E_DEVICE, E_NOMEM. */
+modap_status modap_create(int device, void *hip_stream, modap_ctx **out);
+
+/* Release every resource of the context (synchronises its stream).  NULL is a no-op. */
+void modap_destroy(modap_ctx *ctx);
+
+/* Load the system A x <= b (section 2, eq. 1) and the starting point x0
+ * (NULL = the zero vector, Step 2 of ModAP on lists).  A is m x n in `storage`
+ * with leading dimension lda; b is [m]; x0 is [n].  The library copies the data
+ * into its own row-padded layout, computes ||a_i||^2 in FP64 and synchronises.
+ * Resets iteration counters, the drift schedule and any pending update.
+ * Errors: E_INVAL (m < 1, n < 1, lda < n, NULL A or b, non-finite b or x0,
+ * bad dtype), E_ZERO_ROW (a row is zero or contains a non-finite value),
+ * E_NOMEM, E_DEVICE. */
+modap_status modap_set_system(modap_ctx *ctx, int64_t m, int64_t n, modap_dtype storage,
+                              const void *A, int64_t lda, const double *b, const double *x0,
+                              int ptrs_on_device);
+
+/* Replace the current approximation by x ([n], NULL = zero) and reset the
+ * iteration counters (checkpoint resume).  Errors: E_STATE, E_INVAL. */
+modap_status modap_set_x(modap_ctx *ctx, const double *x, int ptrs_on_device);
+
+/* Update the data between iterations (Step 6 of ModAP on lists, Step 9 of
+ * ModAPL): first, k >= 0 rows are replaced in place -- row rows[q] becomes
+ * new_rows[q*n .. q*n+n) (storage type, [k x n] row-major) and b[rows[q]]
+ * becomes new_b[q], with ||a_i||^2 refreshed; then, when translate_v != NULL,
+ * the feasible set is translated by +v: b <- b + A v.  The translation is not
+ * applied by a separate pass over A: it is carried into the next sweep, which
+ * reads A anyway.  Updates take effect at the next sweep in call order.  rows
+ * must be distinct and in [0, m).  A zero or non-finite replacement row is
+ * reported as E_ZERO_ROW by this call for host inputs, and by the next
+ * synchronising call for device inputs.  Errors: E_STATE, E_INVAL, E_ZERO_ROW. */
+modap_status modap_update_coeffs(modap_ctx *ctx, int64_t k, const int64_t *rows,
+                                 const void *new_rows, const double *new_b,
+                                 const double *translate_v, int ptrs_on_device);
+
+/* Install a drift schedule for iterate/solve: after the s-th step taken from
+ * now (s = 0, 1, ..., T-1) the system is translated by V[s] (row s of a
+ * [T x ldv] FP64 array, ldv >= n), i.e. b <- b + A V[s], fused into the next
+ * sweep.  This is the non-stationary workload of section 5 (a polytope moved
+ * by a translation between iterations).  T = 0 or V = NULL removes it.
+ * Errors: E_STATE, E_INVAL, E_NOMEM. */
+modap_status modap_set_drift(modap_ctx *ctx, int64_t T, const double *V, int64_t ldv,
+                             int ptrs_on_device);
+
+/* Queue k >= 0 iterations (ModAP on lists, Steps 3-8, each a sweep at the
+ * current x and data followed by a step, unless that sweep finds x
+ * eps-feasible, after which the remaining queued iterations do nothing).
+ * With out == NULL the call returns without waiting; with out != NULL it
+ * synchronises and fills the statistics.  Errors: E_STATE, E_INVAL; with out
+ * != NULL also E_INFEASIBLE, E_NUMERIC, E_ZERO_ROW, E_DEVICE. */
+modap_status modap_iterate(modap_ctx *ctx, const modap_params *params, int64_t k,
+                           modap_stats *out);
+
+/* Iterate until x is eps-feasible (OK), max_iters steps were taken
+ * (E_NOT_CONVERGED), no step direction exists (E_INFEASIBLE) or a NaN/Inf
+ * appears (E_NUMERIC).  The host reads the device's stop flag once per batch
+ * of queued iterations; no per-iteration synchronisation.  out may be NULL. */
+modap_status modap_solve(modap_ctx *ctx, const modap_params *params, modap_stats *out);
+
+/* One sweep at the caller's point x ([n]) on the current data (including any
+ * pending update), without changing the context's state: r ([m], optional,
+ * NULL to skip) = A x - b, y ([n], required) = sum of the positive slices,
+ * *h = number of violated rows, *max_viol = max_i max(r_i,0)/||a_i||
+ * (h and max_viol may be NULL).  x, r and y are all host or all device
+ * memory according to ptrs_on_device.  Synchronises.
+ * Errors: E_STATE, E_INVAL, E_DEVICE. */
+modap_status modap_eval_sweep(modap_ctx *ctx, const double *x, double *r, double *y,
+                              int64_t *h, double *max_viol, int ptrs_on_device);
+
+/* Read the current approximation x ([n]) and right-hand side b ([m], with
+ * pending translations applied) and the statistics; any of x, b, out may be
+ * NULL.  Synchronises.  Errors: E_STATE, E_DEVICE. */
+modap_status modap_query(modap_ctx *ctx, double *x, double *b, modap_stats *out,
+                         int ptrs_on_device);
+
+/* Force the sweep's kernel shape (used by the autotuner and by tests of
+ * every shape); tile == NULL restores the built-in choice.  Returns E_INVAL
+ * for a shape the library does not provide for the loaded system. */
+modap_status modap_set_tile(modap_ctx *ctx, const modap_tile *tile);
+
+/* The kernel shape in use for the loaded system.  Errors: E_STATE, E_INVAL. */
+modap_status modap_get_tile(modap_ctx *ctx, modap_tile *tile);
+
+/* Message for a status code (static storage). */
+const char *modap_strerror(modap_status status);
+
+/* Message describing the last failing call on ctx (valid until the next call). */
+const char *modap_last_error(modap_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MODAP_H */

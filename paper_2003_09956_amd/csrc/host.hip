@@ -1,0 +1,912 @@
+// Host half of the library: the C ABI declared in include/modap.h.
+//
+// A context owns a device copy of the system (rows padded with zeros to a
+// 16-byte multiple), its FP64 row norms, the approximation x, the last y, a
+// one-shot translation slot, an optional drift schedule, the per-workgroup
+// partials and a device control block.  One iteration is two kernels on the
+// context's stream: the fused sweep and the fixed-order reduction whose last
+// workgroup takes the stop decision and the step scale.  The host never waits
+// between iterations; solve() reads the control block once per batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "aux_kernels.hpp"
+#include "modap.h"
+#include "modap_device.hpp"
+#include "sweep_table.hpp"
+
+using namespace modap;
+
+struct modap_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int cu_count = 0;
+    std::string err;
+
+    // system
+    bool loaded = false;
+    int64_t m = 0, n = 0, ldA = 0;
+    int dt = 0;
+    size_t es = 0;
+    void *A = nullptr;
+    double *b = nullptr, *nu = nullptr, *x = nullptr, *y = nullptr, *vpend = nullptr;
+    double *V = nullptr;
+    int64_t T = 0;
+    bool vpend_maybe = false;   // a translation may be pending on the device
+
+    // kernel shape and scratch
+    modap_tile tile{};
+    bool tile_forced = false;
+    const SweepKernel *kern_nov = nullptr, *kern_v = nullptr;
+    int64_t rows_per_block = 0;
+    int64_t ldPart = 0;
+    void *part = nullptr;
+    size_t part_bytes = 0;
+    int64_t *h_part = nullptr;
+    double *dmax_part = nullptr, *binf_part = nullptr, *ynorm_part = nullptr;
+    int part_grid = 0;
+
+    Ctrl *ctl = nullptr;
+    EvalOut *eval = nullptr;
+    Ctrl *hctl = nullptr;        // pinned [2]
+    double *x_eval = nullptr, *y_eval = nullptr, *r_eval = nullptr;
+    unsigned long long *bad = nullptr;
+    int *flag = nullptr;
+
+    // staging for host-side update inputs
+    void *stage = nullptr;
+    size_t stage_bytes = 0;
+
+    std::vector<hipEvent_t> events;
+    hipEvent_t sync_ev[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int d) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != d) (void)hipSetDevice(d);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+modap_status fail(modap_ctx *c, modap_status st, const std::string &msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+modap_status hip_fail(modap_ctx *c, hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory) return fail(c, MODAP_E_NOMEM, std::string(what) + ": out of device memory");
+    return fail(c, MODAP_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(c, expr)                                            \
+    do {                                                            \
+        hipError_t e_ = (expr);                                     \
+        if (e_ != hipSuccess) return hip_fail((c), e_, #expr);      \
+    } while (0)
+
+#define LAUNCH_TRY(c, what)                                         \
+    do {                                                            \
+        hipError_t e_ = hipPeekAtLastError();                       \
+        if (e_ != hipSuccess) {                                     \
+            (void)hipGetLastError();                                \
+            return hip_fail((c), e_, what);                         \
+        }                                                           \
+    } while (0)
+
+size_t elem_size(int dt) { return dt == 0 ? 8 : dt == 1 ? 4 : 2; }
+int vec_elems(int dt) { return 16 / (int)elem_size(dt); }
+
+template <typename P>
+void free_dev(P *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+const SweepKernel *kernels_for(int dt, int *count) {
+    switch (dt) {
+        case 0: return sweep_kernels_0(count);
+        case 1: return sweep_kernels_1(count);
+        default: return sweep_kernels_2(count);
+    }
+}
+
+const SweepKernel *find_kernel(int dt, int block, int lpr, int chunks, bool has_v) {
+    int cnt = 0;
+    const SweepKernel *t = kernels_for(dt, &cnt);
+    for (int i = 0; i < cnt; ++i)
+        if (t[i].block == block && t[i].lpr == lpr && t[i].chunks == chunks && t[i].has_v == has_v) return &t[i];
+    return nullptr;
+}
+
+int64_t coverage(int dt, int lpr, int chunks) { return (int64_t)lpr * vec_elems(dt) * chunks; }
+
+// Built-in choice of the fused sweep's shape: the smallest row coverage that
+// holds a padded row; among equal coverage, about 16 elements per lane.
+bool choose_shape(int dt, int64_t ldA, modap_tile *out) {
+    int cnt = 0;
+    const SweepKernel *t = kernels_for(dt, &cnt);
+    const SweepKernel *best = nullptr;
+    int64_t best_cov = 0;
+    int best_score = INT_MAX;
+    for (int i = 0; i < cnt; ++i) {
+        if (!t[i].has_v) continue;
+        const int64_t cov = coverage(dt, t[i].lpr, t[i].chunks);
+        if (cov < ldA) continue;
+        const int epl = t[i].chunks * vec_elems(dt);
+        const int score = std::abs(epl - 16) * 4 + (t[i].block == 1024 ? 0 : t[i].block == 512 ? 1 : 2);
+        if (!best || cov < best_cov || (cov == best_cov && score < best_score)) {
+            best = &t[i];
+            best_cov = cov;
+            best_score = score;
+        }
+    }
+    if (!best) return false;
+    out->kind = 0;
+    out->block = best->block;
+    out->lanes_per_row = best->lpr;
+    out->chunks = best->chunks;
+    out->grid = 0;
+    out->reserved = 0;
+    return true;
+}
+
+// Resolve the tile into kernels, grid and scratch.
+modap_status configure(modap_ctx *c, const modap_tile &want) {
+    modap_tile t = want;
+    if (t.kind != 0) return fail(c, MODAP_E_INVAL, "only the one-pass sweep shape (kind 0) is built");
+    const SweepKernel *kv = find_kernel(c->dt, t.block, t.lanes_per_row, t.chunks, true);
+    const SweepKernel *kn = find_kernel(c->dt, t.block, t.lanes_per_row, t.chunks, false);
+    if (!kv || !kn) return fail(c, MODAP_E_INVAL, "no compiled sweep kernel of that shape for this storage type");
+    const int64_t cov = coverage(c->dt, t.lanes_per_row, t.chunks);
+    if (cov < c->ldA) return fail(c, MODAP_E_INVAL, "sweep shape does not cover a row");
+    const int ng = t.block / t.lanes_per_row;
+    int grid = t.grid;
+    if (grid <= 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kv->func, t.block, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        grid = c->cu_count * per_cu;
+    }
+    int64_t rpb = (c->m + grid - 1) / grid;
+    rpb = ((rpb + ng - 1) / ng) * ng;
+    grid = (int)((c->m + rpb - 1) / rpb);
+    const size_t acc = c->dt == 0 ? 8 : 4;
+    const size_t need = (size_t)grid * (size_t)cov * acc;
+    if (need > c->part_bytes) {
+        free_dev(c->part);
+        HIP_TRY(c, hipMalloc(&c->part, need));
+        c->part_bytes = need;
+    }
+    if (grid > c->part_grid) {
+        free_dev(c->h_part);
+        free_dev(c->dmax_part);
+        free_dev(c->binf_part);
+        HIP_TRY(c, hipMalloc(&c->h_part, sizeof(int64_t) * grid));
+        HIP_TRY(c, hipMalloc(&c->dmax_part, sizeof(double) * grid));
+        HIP_TRY(c, hipMalloc(&c->binf_part, sizeof(double) * grid));
+        c->part_grid = grid;
+    }
+    c->kern_v = kv;
+    c->kern_nov = kn;
+    c->rows_per_block = rpb;
+    c->ldPart = cov;
+    t.grid = grid;
+    c->tile = t;
+    return MODAP_OK;
+}
+
+modap_status check_ctx(modap_ctx *c, bool need_system) {
+    if (!c) return MODAP_E_INVAL;
+    if (need_system && !c->loaded) return fail(c, MODAP_E_STATE, "no system loaded (call modap_set_system first)");
+    return MODAP_OK;
+}
+
+modap_status check_params(modap_ctx *c, const modap_params *p) {
+    if (!p) return fail(c, MODAP_E_INVAL, "params is NULL");
+    if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return fail(c, MODAP_E_INVAL, "lambda must be finite and > 0");
+    if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(c, MODAP_E_INVAL, "eps must be finite and > 0");
+    if (p->step != MODAP_STEP_FIXED && p->step != MODAP_STEP_AVG) return fail(c, MODAP_E_INVAL, "unknown step rule");
+    if (p->max_iters < 0) return fail(c, MODAP_E_INVAL, "max_iters must be >= 0");
+
+    return MODAP_OK;
+}
+
+bool all_finite(const double *p, int64_t count) {
+    for (int64_t i = 0; i < count; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+modap_status ensure_stage(modap_ctx *c, size_t bytes) {
+    if (bytes <= c->stage_bytes) return MODAP_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    free_dev(c->stage);
+    HIP_TRY(c, hipMalloc(&c->stage, bytes));
+    c->stage_bytes = bytes;
+    return MODAP_OK;
+}
+
+// Copy caller data (host or device) to a device pointer, stream-ordered.
+modap_status to_device(modap_ctx *c, void *dst, const void *src, size_t bytes, int on_dev) {
+    if (bytes == 0) return MODAP_OK;
+    HIP_TRY(c, hipMemcpyAsync(dst, src, bytes, on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+    return MODAP_OK;
+}
+
+modap_status from_device(modap_ctx *c, void *dst, const void *src, size_t bytes, int on_dev) {
+    if (bytes == 0) return MODAP_OK;
+    HIP_TRY(c, hipMemcpyAsync(dst, src, bytes, on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    return MODAP_OK;
+}
+
+double sweep_bytes(const modap_ctx *c, bool with_v) {
+    return (double)c->m * (double)c->n * (double)c->es + 16.0 * (double)c->m + (with_v ? 8.0 * (double)c->m : 0.0);
+}
+
+bool translation_possible(const modap_ctx *c) { return c->vpend_maybe || (c->V && c->T > 0); }
+
+SweepArgs sweep_args(modap_ctx *c) {
+    SweepArgs a{};
+    a.A = c->A;
+    a.ldA = c->ldA;
+    a.m = c->m;
+    a.n = c->n;
+    a.b_in = c->b;
+    a.nu = c->nu;
+    a.vpend = c->vpend;
+    a.V = c->V;
+    a.ldV = c->n;
+    a.ctl = c->ctl;
+    a.part = c->part;
+    a.ldPart = c->ldPart;
+    a.h_part = c->h_part;
+    a.dmax_part = c->dmax_part;
+    a.binf_part = c->binf_part;
+    a.rows_per_block = c->rows_per_block;
+    return a;
+}
+
+ReduceArgs reduce_args(modap_ctx *c) {
+    ReduceArgs r{};
+    r.part = c->part;
+    r.ldPart = c->ldPart;
+    r.G = c->tile.grid;
+    r.acc_f64 = c->dt == 0;
+    r.n = c->n;
+    r.h_part = c->h_part;
+    r.dmax_part = c->dmax_part;
+    r.binf_part = c->binf_part;
+    r.ynorm_part = c->ynorm_part;
+    return r;
+}
+
+int reduce_grid(const modap_ctx *c) { return (int)((c->n + 63) / 64); }
+
+modap_status launch_reduce(modap_ctx *c, const ReduceArgs &r) {
+    if (r.acc_f64)
+        hipLaunchKernelGGL(reduce_y<double>, dim3(reduce_grid(c)), dim3(1024), 0, c->stream, r);
+    else
+        hipLaunchKernelGGL(reduce_y<float>, dim3(reduce_grid(c)), dim3(1024), 0, c->stream, r);
+    LAUNCH_TRY(c, "reduce_y launch");
+    return MODAP_OK;
+}
+
+hipEvent_t event_at(modap_ctx *c, size_t i) {
+    while (c->events.size() <= i) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->events.push_back(e);
+    }
+    return c->events[i];
+}
+
+// Queue one iteration: sweep at x - s*y on the current data, then the reduction.
+modap_status enqueue_iteration(modap_ctx *c, const modap_params *p, int track, size_t *ev_used, double *bytes) {
+    const bool hv = translation_possible(c);
+    SweepArgs a = sweep_args(c);
+    a.b_out = c->b;
+    a.x = c->x;
+    a.ystep = c->y;
+    a.check_status = 1;
+    const SweepKernel *k = hv ? c->kern_v : c->kern_nov;
+    if (p->profile) {
+        hipEvent_t e = event_at(c, (*ev_used)++);
+        if (!e) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
+        HIP_TRY(c, hipEventRecord(e, c->stream));
+    }
+    HIP_TRY(c, k->launch(a, c->tile.grid, c->stream));
+    if (p->profile) {
+        hipEvent_t e = event_at(c, (*ev_used)++);
+        if (!e) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
+        HIP_TRY(c, hipEventRecord(e, c->stream));
+    }
+    ReduceArgs r = reduce_args(c);
+    r.y = c->y;
+    r.x = c->x;
+    r.ctl = c->ctl;
+    r.lambda = p->lambda;
+    r.eps = p->eps;
+    r.eps_relative = p->eps_relative;
+    r.rule = p->step;
+    r.track = track;
+    modap_status st = launch_reduce(c, r);
+    if (st != MODAP_OK) return st;
+    if (p->profile) {
+        hipEvent_t e = event_at(c, (*ev_used)++);
+        if (!e) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
+        HIP_TRY(c, hipEventRecord(e, c->stream));
+    }
+    *bytes += sweep_bytes(c, hv);
+    return MODAP_OK;
+}
+
+modap_status read_ctl(modap_ctx *c, Ctrl *out) {
+    HIP_TRY(c, hipMemcpyAsync(out, c->ctl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MODAP_OK;
+}
+
+void fill_stats(modap_stats *o, const Ctrl &k) {
+    o->iters = k.steps;
+    o->sweeps = k.sweeps;
+    o->converged = k.feasible;
+    o->state = k.status;
+    o->max_viol = k.dmax;
+    o->h = k.h;
+    o->y_norm = k.ynorm;
+    o->b_inf = k.binf;
+    o->eps_abs = k.eps_abs;
+}
+
+modap_status profile_totals(modap_ctx *c, size_t ev_used, modap_stats *o) {
+    double sw = 0.0, rd = 0.0;
+    int64_t cnt = 0;
+    for (size_t i = 0; i + 2 < ev_used; i += 3) {
+        float a = 0.f, b = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&a, c->events[i], c->events[i + 1]));
+        HIP_TRY(c, hipEventElapsedTime(&b, c->events[i + 1], c->events[i + 2]));
+        sw += a;
+        rd += b;
+        ++cnt;
+    }
+    o->sweep_ms = sw;
+    o->reduce_ms = rd;
+    o->profiled = cnt;
+    return MODAP_OK;
+}
+
+modap_status status_of(modap_ctx *c, const Ctrl &k, bool solve) {
+    switch (k.status) {
+        case ST_RUNNING:
+        case ST_CONVERGED: return MODAP_OK;
+        case ST_LIMIT: return solve ? fail(c, MODAP_E_NOT_CONVERGED, "step limit reached before eps-feasibility") : MODAP_OK;
+        case ST_NO_DIRECTION: return fail(c, MODAP_E_INFEASIBLE, "a row is violated but y = 0: no step direction");
+        case ST_NUMERIC: return fail(c, MODAP_E_NUMERIC, "NaN or infinity in the iteration");
+        case ST_BAD_ROW: return fail(c, MODAP_E_ZERO_ROW, "a replaced row is zero, not finite, or out of range");
+        default: return fail(c, MODAP_E_DEVICE, "unknown device state");
+    }
+}
+
+void release_system(modap_ctx *c) {
+    free_dev(c->A);
+    free_dev(c->b);
+    free_dev(c->nu);
+    free_dev(c->x);
+    free_dev(c->y);
+    free_dev(c->vpend);
+    free_dev(c->V);
+    free_dev(c->ynorm_part);
+    free_dev(c->x_eval);
+    free_dev(c->y_eval);
+    free_dev(c->r_eval);
+    c->T = 0;
+    c->loaded = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *modap_strerror(modap_status s) {
+    switch (s) {
+        case MODAP_OK: return "ok";
+        case MODAP_E_INVAL: return "invalid argument";
+        case MODAP_E_ZERO_ROW: return "zero or non-finite row";
+        case MODAP_E_NOMEM: return "out of memory";
+        case MODAP_E_DEVICE: return "device error";
+        case MODAP_E_STATE: return "invalid state";
+        case MODAP_E_NOT_CONVERGED: return "not converged within max_iters";
+        case MODAP_E_INFEASIBLE: return "no step direction (infeasible system)";
+        case MODAP_E_NUMERIC: return "non-finite value in the iteration";
+        default: return "unknown status";
+    }
+}
+
+const char *modap_last_error(modap_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+modap_status modap_create(int device, void *hip_stream, modap_ctx **out) {
+    if (!out) return MODAP_E_INVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return MODAP_E_DEVICE;
+    if (device < 0 || device >= ndev) return MODAP_E_INVAL;
+    modap_ctx *c = new (std::nothrow) modap_ctx();
+    if (!c) return MODAP_E_NOMEM;
+    c->device = device;
+    DeviceGuard g(device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return MODAP_E_DEVICE;
+    }
+    c->cu_count = prop.multiProcessorCount;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);  // NULL: the device's default stream
+    bool ok = hipMalloc(&c->ctl, sizeof(Ctrl)) == hipSuccess && hipMalloc(&c->eval, sizeof(EvalOut)) == hipSuccess &&
+              hipMalloc(&c->bad, sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc(&c->flag, sizeof(int)) == hipSuccess &&
+              hipHostMalloc(&c->hctl, 2 * sizeof(Ctrl), hipHostMallocDefault) == hipSuccess &&
+              hipEventCreateWithFlags(&c->sync_ev[0], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->sync_ev[1], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        modap_destroy(c);
+        return MODAP_E_NOMEM;
+    }
+    Ctrl z{};
+    z.v_idx = -1;
+    z.step_limit = INT64_MAX;
+    EvalOut ez{};
+    if (hipMemcpy(c->ctl, &z, sizeof z, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->eval, &ez, sizeof ez, hipMemcpyHostToDevice) != hipSuccess) {
+        modap_destroy(c);
+        return MODAP_E_DEVICE;
+    }
+    *out = c;
+    return MODAP_OK;
+}
+
+void modap_destroy(modap_ctx *c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    release_system(c);
+    free_dev(c->part);
+    free_dev(c->h_part);
+    free_dev(c->dmax_part);
+    free_dev(c->binf_part);
+    free_dev(c->ctl);
+    free_dev(c->eval);
+    free_dev(c->bad);
+    free_dev(c->flag);
+    free_dev(c->stage);
+    if (c->hctl) (void)hipHostFree(c->hctl);
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->sync_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+modap_status modap_set_system(modap_ctx *c, int64_t m, int64_t n, modap_dtype storage, const void *A, int64_t lda,
+                              const double *b, const double *x0, int on_dev) {
+    modap_status st = check_ctx(c, false);
+    if (st) return st;
+    if (m < 1 || n < 1) return fail(c, MODAP_E_INVAL, "m and n must be >= 1");
+    if (lda < n) return fail(c, MODAP_E_INVAL, "lda < n");
+    if (!A || !b) return fail(c, MODAP_E_INVAL, "A and b are required");
+    if (storage != MODAP_F64 && storage != MODAP_F32 && storage != MODAP_BF16)
+        return fail(c, MODAP_E_INVAL, "unknown storage type");
+    if (!on_dev) {
+        if (!all_finite(b, m)) return fail(c, MODAP_E_INVAL, "b has a non-finite entry");
+        if (x0 && !all_finite(x0, n)) return fail(c, MODAP_E_INVAL, "x0 has a non-finite entry");
+    }
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    release_system(c);
+    c->dt = (int)storage;
+    c->es = elem_size(c->dt);
+    c->m = m;
+    c->n = n;
+    const int64_t v = vec_elems(c->dt);
+    c->ldA = (n + v - 1) / v * v;
+    c->vpend_maybe = false;
+    const size_t abytes = (size_t)m * (size_t)c->ldA * c->es;
+    HIP_TRY(c, hipMalloc(&c->A, abytes));
+    HIP_TRY(c, hipMalloc(&c->b, sizeof(double) * m));
+    HIP_TRY(c, hipMalloc(&c->nu, sizeof(double) * m));
+    HIP_TRY(c, hipMalloc(&c->x, sizeof(double) * n));
+    HIP_TRY(c, hipMalloc(&c->y, sizeof(double) * n));
+    HIP_TRY(c, hipMalloc(&c->vpend, sizeof(double) * n));
+    HIP_TRY(c, hipMalloc(&c->x_eval, sizeof(double) * n));
+    HIP_TRY(c, hipMalloc(&c->y_eval, sizeof(double) * n));
+    HIP_TRY(c, hipMalloc(&c->r_eval, sizeof(double) * m));
+    HIP_TRY(c, hipMalloc(&c->ynorm_part, sizeof(double) * (size_t)((n + 63) / 64)));
+    if (c->ldA != n) HIP_TRY(c, hipMemsetAsync(c->A, 0, abytes, c->stream));
+    HIP_TRY(c, hipMemcpy2DAsync(c->A, (size_t)c->ldA * c->es, A, (size_t)lda * c->es, (size_t)n * c->es, (size_t)m,
+                                on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+    if ((st = to_device(c, c->b, b, sizeof(double) * m, on_dev))) return st;
+    if (x0) {
+        if ((st = to_device(c, c->x, x0, sizeof(double) * n, on_dev))) return st;
+    } else {
+        HIP_TRY(c, hipMemsetAsync(c->x, 0, sizeof(double) * n, c->stream));
+    }
+    HIP_TRY(c, hipMemsetAsync(c->y, 0, sizeof(double) * n, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->vpend, 0, sizeof(double) * n, c->stream));
+    const unsigned long long none = ULLONG_MAX;
+    HIP_TRY(c, hipMemcpyAsync(c->bad, &none, sizeof none, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+    const int nb = (int)((m + 3) / 4);
+    switch (c->dt) {
+        case 0: hipLaunchKernelGGL(row_norms<0>, dim3(nb), dim3(256), 0, c->stream, c->A, c->ldA, m, n, c->nu, c->bad); break;
+        case 1: hipLaunchKernelGGL(row_norms<1>, dim3(nb), dim3(256), 0, c->stream, c->A, c->ldA, m, n, c->nu, c->bad); break;
+        default: hipLaunchKernelGGL(row_norms<2>, dim3(nb), dim3(256), 0, c->stream, c->A, c->ldA, m, n, c->nu, c->bad); break;
+    }
+    LAUNCH_TRY(c, "row_norms launch");
+    if (on_dev) {
+        hipLaunchKernelGGL(check_finite, dim3(64), dim3(256), 0, c->stream, c->b, m, c->flag);
+        hipLaunchKernelGGL(check_finite, dim3(64), dim3(256), 0, c->stream, c->x, n, c->flag);
+        LAUNCH_TRY(c, "check_finite launch");
+    }
+    Ctrl z{};
+    z.v_idx = -1;
+    z.step_limit = INT64_MAX;
+    HIP_TRY(c, hipMemcpyAsync(c->ctl, &z, sizeof z, hipMemcpyHostToDevice, c->stream));
+    unsigned long long bad = 0;
+    int flag = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bad, c->bad, sizeof bad, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (flag) {
+        release_system(c);
+        return fail(c, MODAP_E_INVAL, "b or x0 has a non-finite entry");
+    }
+    if (bad != ULLONG_MAX) {
+        release_system(c);
+        return fail(c, MODAP_E_ZERO_ROW, "row " + std::to_string(bad) + " is zero or not finite");
+    }
+    modap_tile t{};
+    if (c->tile_forced) {
+        t = c->tile;
+        t.grid = 0;
+    }
+    if (!c->tile_forced || configure(c, t) != MODAP_OK) {
+        if (!choose_shape(c->dt, c->ldA, &t)) {
+            release_system(c);
+            return fail(c, MODAP_E_INVAL, "rows too long for the one-pass sweep shapes");
+        }
+        c->tile_forced = false;
+        if ((st = configure(c, t))) {
+            release_system(c);
+            return st;
+        }
+    }
+    c->loaded = true;
+    c->err.clear();
+    return MODAP_OK;
+}
+
+modap_status modap_set_x(modap_ctx *c, const double *x, int on_dev) {
+    modap_status st = check_ctx(c, true);
+    if (st) return st;
+    if (x && !on_dev && !all_finite(x, c->n)) return fail(c, MODAP_E_INVAL, "x has a non-finite entry");
+    DeviceGuard g(c->device);
+    if (x) {
+        if ((st = to_device(c, c->x, x, sizeof(double) * c->n, on_dev))) return st;
+    } else {
+        HIP_TRY(c, hipMemsetAsync(c->x, 0, sizeof(double) * c->n, c->stream));
+    }
+    hipLaunchKernelGGL(ctl_restart, dim3(1), dim3(64), 0, c->stream, c->ctl);
+    LAUNCH_TRY(c, "ctl_restart launch");
+    return MODAP_OK;
+}
+
+modap_status modap_update_coeffs(modap_ctx *c, int64_t k, const int64_t *rows, const void *new_rows,
+                                 const double *new_b, const double *v, int on_dev) {
+    modap_status st = check_ctx(c, true);
+    if (st) return st;
+    if (k < 0 || k > c->m) return fail(c, MODAP_E_INVAL, "k out of range");
+    if (k > 0 && (!rows || !new_rows || !new_b)) return fail(c, MODAP_E_INVAL, "rows, new_rows and new_b are required");
+    DeviceGuard g(c->device);
+    const size_t rbytes = (size_t)k * (size_t)c->n * c->es;
+    if (k > 0 && !on_dev) {
+        std::unordered_set<int64_t> seen;
+        for (int64_t q = 0; q < k; ++q) {
+            if (rows[q] < 0 || rows[q] >= c->m) return fail(c, MODAP_E_INVAL, "row index out of range");
+            if (!seen.insert(rows[q]).second) return fail(c, MODAP_E_INVAL, "row indices must be distinct");
+            if (!std::isfinite(new_b[q])) return fail(c, MODAP_E_INVAL, "new_b has a non-finite entry");
+        }
+        for (int64_t q = 0; q < k; ++q) {
+            double s2 = 0.0;
+            for (int64_t j = 0; j < c->n; ++j) {
+                const size_t idx = (size_t)(q * c->n + j);
+                double val;
+                if (c->dt == 0) {
+                    val = reinterpret_cast<const double *>(new_rows)[idx];
+                } else if (c->dt == 1) {
+                    val = reinterpret_cast<const float *>(new_rows)[idx];
+                } else {
+                    uint32_t u = ((uint32_t)reinterpret_cast<const uint16_t *>(new_rows)[idx]) << 16;
+                    float f;
+                    std::memcpy(&f, &u, sizeof f);
+                    val = f;
+                }
+                if (!std::isfinite(val)) return fail(c, MODAP_E_ZERO_ROW, "replacement row has a non-finite entry");
+                s2 += val * val;
+            }
+            if (!(s2 > 0.0)) return fail(c, MODAP_E_ZERO_ROW, "replacement row is zero");
+        }
+    }
+    if (v && !on_dev && !all_finite(v, c->n)) return fail(c, MODAP_E_INVAL, "translation has a non-finite entry");
+    const int64_t *d_rows = rows;
+    const void *d_new = new_rows;
+    const double *d_b = new_b;
+    const double *d_v = v;
+    if (!on_dev) {
+        const size_t o1 = 0, o2 = o1 + (size_t)k * 8, o3 = (o2 + rbytes + 15) / 16 * 16, o4 = o3 + (size_t)k * 8;
+        const size_t total = o4 + (v ? (size_t)c->n * 8 : 0);
+        if ((st = ensure_stage(c, total + 16))) return st;
+        char *s = reinterpret_cast<char *>(c->stage);
+        if (k > 0) {
+            if ((st = to_device(c, s + o1, rows, (size_t)k * 8, 0))) return st;
+            if ((st = to_device(c, s + o2, new_rows, rbytes, 0))) return st;
+            if ((st = to_device(c, s + o3, new_b, (size_t)k * 8, 0))) return st;
+        }
+        if (v && (st = to_device(c, s + o4, v, (size_t)c->n * 8, 0))) return st;
+        d_rows = reinterpret_cast<const int64_t *>(s + o1);
+        d_new = s + o2;
+        d_b = reinterpret_cast<const double *>(s + o3);
+        d_v = v ? reinterpret_cast<const double *>(s + o4) : nullptr;
+    }
+    if (k > 0) {
+        switch (c->dt) {
+            case 0: hipLaunchKernelGGL(scatter_rows<0>, dim3(k), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, d_rows, d_new, d_b, c->b, c->nu, c->ctl, c->vpend); break;
+            case 1: hipLaunchKernelGGL(scatter_rows<1>, dim3(k), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, d_rows, d_new, d_b, c->b, c->nu, c->ctl, c->vpend); break;
+            default: hipLaunchKernelGGL(scatter_rows<2>, dim3(k), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, d_rows, d_new, d_b, c->b, c->nu, c->ctl, c->vpend); break;
+        }
+        LAUNCH_TRY(c, "scatter_rows launch");
+    }
+    if (d_v) {
+        hipLaunchKernelGGL(vpend_add, dim3(1), dim3(1024), 0, c->stream, c->ctl, c->vpend, d_v, c->n);
+        LAUNCH_TRY(c, "vpend_add launch");
+        c->vpend_maybe = true;
+    }
+    return MODAP_OK;
+}
+
+modap_status modap_set_drift(modap_ctx *c, int64_t T, const double *V, int64_t ldv, int on_dev) {
+    modap_status st = check_ctx(c, true);
+    if (st) return st;
+    if (T < 0) return fail(c, MODAP_E_INVAL, "T < 0");
+    if (T > 0 && V && ldv < c->n) return fail(c, MODAP_E_INVAL, "ldv < n");
+    if (T > 0 && V && !on_dev) {
+        for (int64_t s = 0; s < T; ++s)
+            if (!all_finite(V + s * ldv, c->n)) return fail(c, MODAP_E_INVAL, "drift has a non-finite entry");
+    }
+    DeviceGuard g(c->device);
+    if (c->V) {
+        hipLaunchKernelGGL(sched_to_vpend, dim3(1), dim3(1024), 0, c->stream, c->ctl, c->vpend, c->V, c->n, c->n);
+        LAUNCH_TRY(c, "sched_to_vpend launch");
+        c->vpend_maybe = true;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    free_dev(c->V);
+    c->T = 0;
+    if (T > 0 && V) {
+        HIP_TRY(c, hipMalloc(&c->V, sizeof(double) * (size_t)T * (size_t)c->n));
+        HIP_TRY(c, hipMemcpy2DAsync(c->V, sizeof(double) * c->n, V, sizeof(double) * ldv, sizeof(double) * c->n,
+                                    (size_t)T, on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+        c->T = T;
+    }
+    hipLaunchKernelGGL(ctl_set_drift, dim3(1), dim3(64), 0, c->stream, c->ctl, c->T);
+    LAUNCH_TRY(c, "ctl_set_drift launch");
+    if (on_dev && c->T > 0) {
+        HIP_TRY(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+        hipLaunchKernelGGL(check_finite, dim3(64), dim3(256), 0, c->stream, c->V, c->T * c->n, c->flag);
+        int flag = 0;
+        HIP_TRY(c, hipMemcpyAsync(&flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (flag) {
+            free_dev(c->V);
+            c->T = 0;
+            hipLaunchKernelGGL(ctl_set_drift, dim3(1), dim3(64), 0, c->stream, c->ctl, (int64_t)0);
+            return fail(c, MODAP_E_INVAL, "drift has a non-finite entry");
+        }
+    }
+    return MODAP_OK;
+}
+
+modap_status modap_iterate(modap_ctx *c, const modap_params *p, int64_t k, modap_stats *out) {
+    modap_status st = check_ctx(c, true);
+    if (st) return st;
+    if ((st = check_params(c, p))) return st;
+    if (k < 0) return fail(c, MODAP_E_INVAL, "k < 0");
+    DeviceGuard g(c->device);
+    const auto t0 = std::chrono::steady_clock::now();
+    hipLaunchKernelGGL(ctl_begin, dim3(1), dim3(64), 0, c->stream, c->ctl, (int64_t)-1);
+    LAUNCH_TRY(c, "ctl_begin launch");
+    size_t ev = 0;
+    double bytes = 0.0;
+    for (int64_t i = 0; i < k; ++i)
+        if ((st = enqueue_iteration(c, p, p->track != 0, &ev, &bytes))) return st;
+    if (!out) return MODAP_OK;
+    Ctrl kc;
+    if ((st = read_ctl(c, &kc))) return st;
+    *out = modap_stats{};
+    fill_stats(out, kc);
+    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    out->hbm_bytes = bytes;
+    if (p->profile && (st = profile_totals(c, ev, out))) return st;
+    if (!kc.vpend_valid && kc.v_idx < 0) c->vpend_maybe = false;
+    return status_of(c, kc, false);
+}
+
+modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) {
+    modap_status st = check_ctx(c, true);
+    if (st) return st;
+    if ((st = check_params(c, p))) return st;
+    DeviceGuard g(c->device);
+    const auto t0 = std::chrono::steady_clock::now();
+    hipLaunchKernelGGL(ctl_begin, dim3(1), dim3(64), 0, c->stream, c->ctl, (int64_t)p->max_iters);
+    LAUNCH_TRY(c, "ctl_begin launch");
+    const int64_t total = p->max_iters + 1;  // the last sweep checks the last step
+    int64_t queued = 0, chunk = 1;
+    int slot = 0, pending = -1;
+    size_t ev = 0;
+    double bytes = 0.0;
+    bool done = false;
+    auto observed = t0;
+    while (queued < total && !done) {
+        const int64_t cnt = std::min(chunk, total - queued);
+        for (int64_t i = 0; i < cnt; ++i)
+            if ((st = enqueue_iteration(c, p, 0, &ev, &bytes))) return st;
+        queued += cnt;
+        HIP_TRY(c, hipMemcpyAsync(&c->hctl[slot], c->ctl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipEventRecord(c->sync_ev[slot], c->stream));
+        if (pending >= 0) {
+            HIP_TRY(c, hipEventSynchronize(c->sync_ev[pending]));
+            if (c->hctl[pending].status != ST_RUNNING) {
+                done = true;
+                observed = std::chrono::steady_clock::now();
+            }
+        }
+        pending = slot;
+        slot ^= 1;
+        chunk = std::min<int64_t>(chunk * 2, 64);
+    }
+    if (!done) {
+        HIP_TRY(c, hipEventSynchronize(c->sync_ev[pending]));
+        observed = std::chrono::steady_clock::now();
+    }
+    Ctrl kc;
+    if ((st = read_ctl(c, &kc))) return st;
+    if (out) {
+        *out = modap_stats{};
+        fill_stats(out, kc);
+        out->seconds = std::chrono::duration<double>(observed - t0).count();
+        out->hbm_bytes = bytes;
+        if (p->profile && (st = profile_totals(c, ev, out))) return st;
+    }
+    if (!kc.vpend_valid && kc.v_idx < 0) c->vpend_maybe = false;
+    if (kc.status == ST_RUNNING) return fail(c, MODAP_E_NOT_CONVERGED, "step limit reached before eps-feasibility");
+    return status_of(c, kc, true);
+}
+
+modap_status modap_eval_sweep(modap_ctx *c, const double *x, double *r, double *y, int64_t *h, double *max_viol,
+                              int on_dev) {
+    modap_status st = check_ctx(c, true);
+    if (st) return st;
+    if (!x || !y) return fail(c, MODAP_E_INVAL, "x and y are required");
+    DeviceGuard g(c->device);
+    if ((st = to_device(c, c->x_eval, x, sizeof(double) * c->n, on_dev))) return st;
+    const bool hv = translation_possible(c);
+    SweepArgs a = sweep_args(c);
+    a.b_out = nullptr;
+    a.x = c->x_eval;
+    a.ystep = nullptr;
+    a.check_status = 0;
+    a.r_out = r ? c->r_eval : nullptr;
+    HIP_TRY(c, (hv ? c->kern_v : c->kern_nov)->launch(a, c->tile.grid, c->stream));
+    ReduceArgs ra = reduce_args(c);
+    ra.y = c->y_eval;
+    ra.x = nullptr;
+    ra.ctl = nullptr;
+    ra.eval = c->eval;
+    if ((st = launch_reduce(c, ra))) return st;
+    EvalOut eo;
+    HIP_TRY(c, hipMemcpyAsync(&eo, c->eval, sizeof eo, hipMemcpyDeviceToHost, c->stream));
+    if ((st = from_device(c, y, c->y_eval, sizeof(double) * c->n, on_dev))) return st;
+    if (r && (st = from_device(c, r, c->r_eval, sizeof(double) * c->m, on_dev))) return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (h) *h = eo.h;
+    if (max_viol) *max_viol = eo.dmax;
+    return MODAP_OK;
+}
+
+modap_status modap_query(modap_ctx *c, double *x, double *b, modap_stats *out, int on_dev) {
+    modap_status st = check_ctx(c, true);
+    if (st) return st;
+    DeviceGuard g(c->device);
+    if (x) {
+        hipLaunchKernelGGL(materialize_x, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, c->stream, c->ctl, c->x,
+                           c->y, c->n);
+        hipLaunchKernelGGL(ctl_clear_step, dim3(1), dim3(64), 0, c->stream, c->ctl);
+        LAUNCH_TRY(c, "materialize_x launch");
+        if ((st = from_device(c, x, c->x, sizeof(double) * c->n, on_dev))) return st;
+    }
+    if (b) {
+        if (c->vpend_maybe || c->V) {
+            hipLaunchKernelGGL(sched_to_vpend, dim3(1), dim3(1024), 0, c->stream, c->ctl, c->vpend, c->V, c->n, c->n);
+            const int nb = (int)((c->m + 3) / 4);
+            switch (c->dt) {
+                case 0: hipLaunchKernelGGL(flush_translation<0>, dim3(nb), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, c->ctl, c->vpend, c->b); break;
+                case 1: hipLaunchKernelGGL(flush_translation<1>, dim3(nb), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, c->ctl, c->vpend, c->b); break;
+                default: hipLaunchKernelGGL(flush_translation<2>, dim3(nb), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, c->ctl, c->vpend, c->b); break;
+            }
+            hipLaunchKernelGGL(ctl_clear_vpend, dim3(1), dim3(64), 0, c->stream, c->ctl);
+            LAUNCH_TRY(c, "flush_translation launch");
+        }
+        if ((st = from_device(c, b, c->b, sizeof(double) * c->m, on_dev))) return st;
+    }
+    Ctrl kc;
+    if ((st = read_ctl(c, &kc))) return st;
+    if (b) c->vpend_maybe = false;
+    if (out) {
+        *out = modap_stats{};
+        fill_stats(out, kc);
+    }
+    return MODAP_OK;
+}
+
+modap_status modap_set_tile(modap_ctx *c, const modap_tile *t) {
+    if (!c) return MODAP_E_INVAL;
+    DeviceGuard g(c->device);
+    if (!t) {
+        c->tile_forced = false;
+        if (!c->loaded) return MODAP_OK;
+        modap_tile d{};
+        if (!choose_shape(c->dt, c->ldA, &d)) return fail(c, MODAP_E_INVAL, "no built-in shape");
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return configure(c, d);
+    }
+    if (!c->loaded) {
+        c->tile = *t;
+        c->tile_forced = true;
+        return MODAP_OK;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const modap_tile keep = c->tile;
+    modap_status st = configure(c, *t);
+    if (st) {
+        const std::string msg = c->err;
+        (void)configure(c, keep);
+        return fail(c, st, msg);
+    }
+    c->tile_forced = true;
+    return MODAP_OK;
+}
+
+modap_status modap_get_tile(modap_ctx *c, modap_tile *t) {
+    modap_status st = check_ctx(c, true);
+    if (st) return st;
+    if (!t) return fail(c, MODAP_E_INVAL, "tile is NULL");
+    *t = c->tile;
+    return MODAP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,25 @@
+// Registry of the compiled sweep kernel shapes.
+#pragma once
+
+#include "modap_device.hpp"
+
+namespace modap {
+
+using SweepLaunch = hipError_t (*)(const SweepArgs &, int grid, hipStream_t stream);
+
+struct SweepKernel {
+    int dt;
+    int block;
+    int lpr;
+    int chunks;
+    bool has_v;
+    SweepLaunch launch;
+    const void *func;
+};
+
+// Defined once per storage type (sweep_f64.hip, sweep_f32.hip, sweep_bf16.hip).
+const SweepKernel *sweep_kernels_0(int *count);
+const SweepKernel *sweep_kernels_1(int *count);
+const SweepKernel *sweep_kernels_2(int *count);
+
+}  // namespace modap

@@ -1,0 +1,103 @@
+"""The C-ABI library loads and exports every entry point its header declares.
+
+CPU-only: no compute call is made here (there is no GPU in this environment);
+only calls that return before touching a device are exercised.
+"""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "modap.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2003_09956_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        from paper_2003_09956_amd import _build
+        _build.build()
+    return P.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(modap_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for verb in ("create", "destroy", "set_system", "update_coeffs", "iterate", "solve",
+                 "eval_sweep", "query", "strerror"):
+        assert f"modap_{verb}" in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    import paper_2003_09956_amd as P
+    names = declared_functions()
+    assert sorted(P.EXPORTS) == names
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    for name in names:
+        assert name in exported, name
+        assert getattr(L, name) is not None
+
+
+def test_no_torch_in_the_abi():
+    text = open(HEADER).read()
+    assert "torch" not in text.lower().replace("torch.tensor.data_ptr", "")
+    assert "extern \"C\"" in text
+
+
+def test_strerror_covers_every_status(L):
+    msgs = [L.modap_strerror(s).decode() for s in range(9)]
+    assert msgs[0] == "ok"
+    assert len(set(msgs)) == 9
+    assert L.modap_strerror(99).decode() == "unknown status"
+
+
+def test_null_context_is_rejected_without_a_device(L):
+    assert L.modap_set_system(None, 1, 1, 0, None, 1, None, None, 0) == 1
+    assert L.modap_iterate(None, None, 1, None) == 1
+    assert L.modap_solve(None, None, None) == 1
+    assert L.modap_query(None, None, None, None, 0) == 1
+    assert L.modap_eval_sweep(None, None, None, None, None, None, 0) == 1
+    assert L.modap_update_coeffs(None, 0, None, None, None, None, 0) == 1
+    assert L.modap_set_drift(None, 0, None, 0, 0) == 1
+    assert L.modap_set_x(None, None, 0) == 1
+    assert L.modap_get_tile(None, None) == 1
+    assert L.modap_last_error(None).decode() == "null context"
+    L.modap_destroy(None)
+
+
+def test_create_fails_cleanly_without_gpu(L):
+    from conftest import gpu_available
+    if gpu_available():
+        pytest.skip("a GPU is present")
+    ctx = C.c_void_p()
+    assert L.modap_create(0, None, C.byref(ctx)) in (4, 1)
+    assert not ctx.value
+    assert L.modap_create(0, None, None) == 1
+
+
+def test_binding_has_no_cpu_fallback(tmp_path, monkeypatch):
+    """The Python binding raises when the library is missing; it never computes on the CPU."""
+    import paper_2003_09956_amd as P
+    monkeypatch.setattr(P, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(P, "_lib", None)
+    with pytest.raises(ImportError):
+        P.lib()
+
+
+def test_product_never_imports_the_oracle():
+    """Only tests, the smoke check and the benchmark's CPU leg may use oracle/."""
+    pkg = os.path.join(ROOT, "paper_2003_09956_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".inc", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower(), f

@@ -1,0 +1,441 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Every comparison takes the same seeded inputs and the same point x on both
+sides; tolerances are those of tests/parity.py.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from parity import TOL, TOL_BF16_VS_F64, check_sweep, fejer_gap, weighted_abs_rows
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    import paper_2003_09956_amd as P
+    P.lib()
+    return P
+
+
+def probe_point(sys_, scale, seed):
+    rng = np.random.default_rng(seed)
+    return sys_.z + rng.normal(scale=scale, size=sys_.n)
+
+
+SHAPES = [(1, 1), (2, 3), (5, 17), (63, 127), (64, 64), (65, 200), (256, 513), (1000, 700),
+          (2049, 300), (4096, 1100), (8192, 600), (12000, 257), (16384, 260)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n,m", SHAPES)
+def test_eval_sweep_matches_oracle(P, dtype, n, m):
+    if dtype == "f64" and n > 8192:
+        pytest.skip("FP64 rows beyond 8192 use the split-row form")
+    say(f"eval_sweep dtype={dtype} n={n} m={m}")
+    sys_ = W.gaussian(n, m, seed=n * 7 + m, dtype=dtype)
+    x = probe_point(sys_, 2.0 / np.sqrt(n) + 0.05, seed=m)
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype=dtype)
+        g = s.eval_sweep(x)
+        say("  tile", s.get_tile())
+    o = oracle.sweep(sys_.A, dtype, sys_.b, x)
+    check_sweep(sys_.A, dtype, o, g.y, g.h, g.max_viol, g.r, label=f"{dtype} {n}x{m}")
+
+
+ALL_SHAPES = {
+    "f64": [(256, 64, 1), (256, 64, 2), (256, 64, 4), (256, 256, 2), (256, 256, 4), (256, 256, 8),
+            (512, 512, 2), (512, 512, 4), (512, 512, 8), (1024, 1024, 2), (1024, 1024, 4)],
+    "f32": [(256, 64, 1), (256, 64, 2), (256, 64, 4), (256, 256, 2), (256, 256, 4), (256, 256, 8),
+            (512, 512, 2), (512, 512, 4), (512, 512, 8), (1024, 1024, 2)],
+    "bf16": [(256, 64, 1), (256, 64, 2), (256, 64, 4), (256, 256, 2), (256, 256, 4),
+             (512, 512, 2), (512, 512, 4), (1024, 1024, 2), (1024, 1024, 4)],
+}
+VEC = {"f64": 2, "f32": 4, "bf16": 8}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_every_kernel_shape_and_grid(P, dtype):
+    """Each compiled sweep shape that covers the row, at two grid sizes, gives
+    the oracle's sweep; a ragged n and m exercise the masked tails."""
+    n, m = 203, 997
+    sys_ = W.gaussian(n, m, seed=17, dtype=dtype)
+    x = probe_point(sys_, 0.2, seed=3)
+    o = oracle.sweep(sys_.A, dtype, sys_.b, x)
+    ys = []
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype=dtype)
+        for (blk, lpr, ch) in ALL_SHAPES[dtype]:
+            if lpr * VEC[dtype] * ch < n:
+                continue
+            for grid in (0, 7):
+                say(f"shape dtype={dtype} block={blk} lpr={lpr} chunks={ch} grid={grid}")
+                s.set_tile(blk, lpr, ch, grid)
+                g = s.eval_sweep(x)
+                check_sweep(sys_.A, dtype, o, g.y, g.h, g.max_viol, g.r,
+                            label=f"{dtype} {blk}/{lpr}/{ch}/{grid}")
+                ys.append(g.y)
+    assert len(ys) >= 4
+
+
+def test_box_sum_closed_form_on_gpu(P):
+    """The box-plus-sum system's sweep has a closed form (independent of the oracle)."""
+    sys_ = W.c1(seed=0)
+    xs = [sys_.x0, np.random.default_rng(1).uniform(-50, 250, sys_.n), np.full(sys_.n, 100.0)]
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype="f64")
+        for x in xs:
+            say("box_sum closed form")
+            g = s.eval_sweep(x)
+            agg = x.sum() - 200.0 * (sys_.n - 1)
+            y = np.maximum(x - 200, 0) - np.maximum(-x, 0) + max(agg, 0) / sys_.n
+            h = int(np.sum(x > 200) + np.sum(x < 0) + (agg > 0))
+            d = max(np.max(np.maximum(x - 200, 0)), np.max(np.maximum(-x, 0)), max(agg, 0) / 16.0)
+            assert g.h == h
+            np.testing.assert_allclose(g.y, y, rtol=1e-13, atol=1e-12)
+            assert g.max_viol == pytest.approx(d, rel=1e-13, abs=1e-12)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_translation_is_fused_into_the_next_sweep(P, dtype):
+    """Data update b <- b + A v (section 5's translation) applied by the sweep."""
+    n, m = 777, 1500
+    sys_ = W.gaussian(n, m, seed=5, dtype=dtype)
+    rng = np.random.default_rng(5)
+    v1, v2 = rng.normal(scale=0.3, size=n), rng.normal(scale=0.3, size=n)
+    x = probe_point(sys_, 0.3, seed=9)
+    b2 = oracle.translate(sys_.A, dtype, oracle.translate(sys_.A, dtype, sys_.b, v1), v2)
+    o = oracle.sweep(sys_.A, dtype, b2, x)
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype=dtype)
+        say(f"translation dtype={dtype}")
+        s.update_coeffs(translate=v1)
+        s.update_coeffs(translate=v2)
+        g = s.eval_sweep(x)
+        check_sweep(sys_.A, dtype, o, g.y, g.h, g.max_viol, g.r, label="translated")
+        _, bq, _ = s.query(want_x=False, want_b=True)
+    # b read back: FP64 flush of the pending translation
+    scale = np.abs(W.stored_to_f64(sys_.A, dtype)) @ (np.abs(v1) + np.abs(v2)) + np.abs(sys_.b)
+    assert np.max(np.abs(bq - b2) / scale) <= 1e-13
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_row_replacement_in_place(P, dtype):
+    """Coefficient updates: rows replaced in place with norms refreshed; a
+    translation queued before the replacement does not move the new rows."""
+    n, m = 300, 800
+    sys_ = W.gaussian(n, m, seed=8, dtype=dtype)
+    v = np.random.default_rng(8).normal(scale=0.2, size=n)
+    idx, rows, bb = W.replacement_rows(sys_, 40, seed=8)
+    A2, b2 = oracle.replace_rows(sys_.A, dtype, oracle.translate(sys_.A, dtype, sys_.b, v), idx, rows, bb)
+    x = probe_point(sys_, 0.4, seed=2)
+    o = oracle.sweep(A2, dtype, b2, x)
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype=dtype)
+        say(f"row replacement dtype={dtype}")
+        s.update_coeffs(translate=v)
+        s.update_coeffs(idx, rows, bb)
+        g = s.eval_sweep(x)
+    check_sweep(A2, dtype, o, g.y, g.h, g.max_viol, g.r, label="replaced")
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_each_step_matches_oracle_step(P, rule, dtype):
+    """x_{k+1} from x_k: the GPU's step (eq. 12 or Algorithm 1) against the
+    oracle's step from the GPU's own x_k, for several consecutive iterations."""
+    n, m = 500, 1400
+    sys_ = W.gaussian(n, m, seed=21, dtype=dtype)
+    x0 = sys_.z + np.random.default_rng(4).normal(scale=1.0, size=n)
+    lam = 0.5
+    prm = P.params(lam=lam, eps=1e-9, step=rule)
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, x0=x0, dtype=dtype)
+        x = x0.copy()
+        for k in range(6):
+            say(f"step k={k} rule={rule} dtype={dtype}")
+            st = s.iterate(1, prm)
+            x1, _, _ = s.query()
+            o = oracle.sweep(sys_.A, dtype, sys_.b, x)
+            xo, status = oracle.step(o.y, o.h, rule, lam, x)
+            assert status == 0 and st.iters == k + 1
+            tol = TOL[dtype]
+            near = o.r > -tol * o.t
+            s_y = np.linalg.norm(weighted_abs_rows(sys_.A, dtype, np.where(near, o.t / o.nu, 0)))
+            denom = np.linalg.norm(o.y) if rule == 0 else o.h
+            bound = tol * (np.linalg.norm(x) + lam * s_y / denom)
+            assert np.linalg.norm(x1 - xo) <= bound, (k, np.linalg.norm(x1 - xo), bound)
+            x = x1
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_solve_box_sum_fp64_reaches_feasibility_like_oracle(P, seed):
+    """Plain FP64 stationary box-plus-sum system (n=256, m=513, lambda=1,
+    eps = 1e-6 * ||b||inf): the GPU solve stops at an eps-feasible point after
+    the same number of ModAP steps as the oracle."""
+    sys_ = W.c1(seed)
+    ores = oracle.solve(sys_.A, "f64", sys_.b, sys_.x0, lam=1.0, eps=1e-6, rule=0, max_steps=20000)
+    assert ores.status == 0
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, x0=sys_.x0, dtype="f64")
+        say(f"solve c1 seed={seed}")
+        st, code = s.solve(P.params(lam=1.0, eps=1e-6, max_iters=20000))
+        x, _, _ = s.query()
+    assert code == 0 and st.converged == 1
+    o = oracle.sweep(sys_.A, "f64", sys_.b, x)
+    assert o.dmax <= 1e-6 * o.binf * (1 + 1e-12)
+    assert st.iters == ores.iters
+    np.testing.assert_allclose(x, ores.x, rtol=0, atol=1e-9 * np.abs(ores.x).max())
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_drift_schedule_steps_match_oracle(P, dtype):
+    """Non-stationary iteration (section 5: the polytope is translated between
+    iterations): after step k the system moves by V[k], fused into sweep k+1.
+    Each GPU step is compared with the oracle's step from the GPU's own x_k on
+    the oracle's data b_k = b_0 + A (V[0] + ... + V[k-1])."""
+    n, m = 256, 700
+    sys_ = W.gaussian(n, m, seed=33, dtype=dtype)
+    V = W.drift(n, 40, sigma=1e-3, seed=33)
+    lam, tol = 0.05, TOL[dtype]
+    prm = P.params(lam=lam, eps=1e-9)
+    b = sys_.b.copy()
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype=dtype)
+        s.set_drift(V)
+        x = sys_.x0.copy()
+        for k in range(12):
+            say(f"drift step k={k} dtype={dtype}")
+            s.iterate(1, prm)
+            x1, _, st = s.query()
+            o = oracle.sweep(sys_.A, dtype, b, x)
+            xo, status = oracle.step(o.y, o.h, 0, lam, x)
+            assert status == 0 and st.iters == k + 1
+            near = o.r > -tol * o.t
+            s_y = np.linalg.norm(weighted_abs_rows(sys_.A, dtype, np.where(near, o.t / o.nu, 0)))
+            bound = tol * (np.linalg.norm(x) + lam * s_y / np.linalg.norm(o.y))
+            assert np.linalg.norm(x1 - xo) <= bound, (k, np.linalg.norm(x1 - xo), bound)
+            b = oracle.translate(sys_.A, dtype, b, V[k])
+            x = x1
+        _, bq, _ = s.query(want_x=False, want_b=True)
+    scale = np.abs(W.stored_to_f64(sys_.A, dtype)) @ np.abs(V[:12]).sum(axis=0) + np.abs(sys_.b)
+    assert np.max(np.abs(bq - b) / scale) <= tol
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_solve_with_drift_reaches_feasibility(P, dtype):
+    """ModAP catches a translating polytope (section 2, eq. 12): the solve stops
+    at a point that is eps-feasible for the data current at the stop, and that
+    data is the initial system translated by the first `iters` drift vectors.
+    (Step counts are not compared: the fixed-length iteration near a moving
+    boundary is chaotic -- a 1e-15 change of x0 changes the oracle's own count.)"""
+    n, m = 256, 700
+    sys_ = W.gaussian(n, m, seed=33, dtype=dtype)
+    V = W.drift(n, 400, sigma=1e-3, seed=33)
+    ores = oracle.solve(sys_.A, dtype, sys_.b, sys_.x0, lam=0.05, eps=1e-6, rule=0,
+                        max_steps=400, V=V)
+    assert ores.status == 0
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype=dtype)
+        s.set_drift(V)
+        say(f"solve with drift dtype={dtype}")
+        st, code = s.solve(P.params(lam=0.05, eps=1e-6, max_iters=400))
+        x, bq, _ = s.query(want_b=True)
+    assert code == 0 and st.converged == 1
+    assert 0.5 * ores.iters <= st.iters <= 2 * ores.iters
+    b = sys_.b.copy()
+    for k in range(st.iters):
+        b = oracle.translate(sys_.A, dtype, b, V[k])
+    scale = np.abs(W.stored_to_f64(sys_.A, dtype)) @ np.abs(V[:st.iters]).sum(axis=0) + np.abs(sys_.b)
+    assert np.max(np.abs(bq - b) / scale) <= TOL[dtype]
+    o = oracle.sweep(sys_.A, dtype, b, x)
+    assert o.dmax <= 1e-6 * o.binf + TOL[dtype] * np.max(o.t / np.sqrt(o.nu))
+
+
+def test_translation_in_wavefront_row_shape(P):
+    """The translation path in the one-wavefront-per-row shape (short rows)."""
+    n, m = 200, 900
+    sys_ = W.gaussian(n, m, seed=44, dtype="f64")
+    v = np.random.default_rng(44).normal(scale=0.5, size=n)
+    x = probe_point(sys_, 0.3, seed=44)
+    o = oracle.sweep(sys_.A, "f64", oracle.translate(sys_.A, "f64", sys_.b, v), x)
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype="f64")
+        for shape in [(256, 64, 2), (256, 64, 4), (256, 256, 2)]:
+            say(f"wave-shape translation {shape}")
+            s.set_tile(*shape)
+            s.update_coeffs(translate=v)
+            g = s.eval_sweep(x)
+            check_sweep(sys_.A, "f64", o, g.y, g.h, g.max_viol, g.r, label=str(shape))
+            s.update_coeffs(translate=-v)
+
+
+def test_full_size_fp32_sweep_c2(P):
+    """n=8192, m=16384 FP32 (the benchmark's system): full element-wise parity
+    of one sweep, with a translation pending, and the launch shape bench.py uses."""
+    sys_ = W.c2(0)
+    rng = np.random.default_rng(0)
+    x = rng.normal(scale=0.05, size=sys_.n)
+    v = rng.normal(scale=1e-2, size=sys_.n)
+    say("c2 full-size sweep")
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype="f32")
+        s.update_coeffs(translate=v)
+        g = s.eval_sweep(x)
+        tile = s.get_tile()
+    b2 = oracle.translate(sys_.A, "f32", sys_.b, v)
+    o = oracle.sweep(sys_.A, "f32", b2, x)
+    err = check_sweep(sys_.A, "f32", o, g.y, g.h, g.max_viol, g.r, label="c2")
+    say("  c2 errors", err, tile)
+    assert fejer_gap(sys_.A, "f32", x, sys_.z + v, g.y, g.r) >= -1e-6 * np.abs(g.y).sum()
+
+
+@pytest.mark.timeout(900)
+def test_full_size_bf16_sweep_c3(P):
+    """n=16384, m=65536 BF16 storage (2 GiB): full parity of one sweep against
+    the oracle on the same stored bytes, and against the FP64 system the BF16
+    rows were rounded from (quantisation, 5e-3)."""
+    sys_ = W.c3(0)
+    x = np.random.default_rng(1).normal(scale=0.03, size=sys_.n)
+    say("c3 full-size sweep")
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype="bf16")
+        g = s.eval_sweep(x)
+    o = oracle.sweep(sys_.A, "bf16", sys_.b, x)
+    err = check_sweep(sys_.A, "bf16", o, g.y, g.h, g.max_viol, g.r, label="c3")
+    say("  c3 errors", err)
+
+
+def test_bf16_quantisation_against_fp64_original(P):
+    """BF16-stored rows against the unrounded FP64 rows (same b, same x): the
+    per-sweep error stays within 5e-3 on the condition scale."""
+    n, m = 4096, 8192
+    s64 = W.gaussian(n, m, seed=4, dtype="f64")
+    A16 = W.encode(s64.A, "bf16")
+    x = probe_point(s64, 0.05, seed=4)
+    o = oracle.sweep(s64.A, "f64", s64.b, x)
+    with P.Solver() as s:
+        s.set_system(A16, s64.b, dtype="bf16")
+        say("bf16 vs fp64 original")
+        g = s.eval_sweep(x)
+    err = check_sweep(s64.A, "f64", o, g.y, g.h, g.max_viol, g.r, tol=TOL_BF16_VS_F64, label="bf16-vs-f64")
+    say("  quantisation error", err)
+
+
+def test_deterministic_results(P):
+    """Fixed-order reductions: repeated sweeps and repeated iterations are bitwise equal."""
+    sys_ = W.gaussian(3000, 5000, seed=2, dtype="f32")
+    x = probe_point(sys_, 0.05, seed=2)
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype="f32")
+        say("determinism")
+        g1 = s.eval_sweep(x)
+        g2 = s.eval_sweep(x)
+        assert np.array_equal(g1.y, g2.y) and np.array_equal(g1.r, g2.r)
+        prm = P.params(lam=0.2, eps=1e-12)
+        s.set_x(x)
+        s.iterate(25, prm)
+        xa, _, sa = s.query()
+        s.set_x(x)
+        s.iterate(25, prm)
+        xb, _, sb = s.query()
+    assert np.array_equal(xa, xb) and sa.iters == sb.iters > 0
+
+
+def test_checkpoint_resume(P):
+    """k iterations, read x, restart from it: the same as an uninterrupted run."""
+    sys_ = W.gaussian(400, 900, seed=12, dtype="f64")
+    prm = P.params(lam=0.3, eps=1e-12)
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype="f64")
+        say("checkpoint")
+        s.iterate(20, prm)
+        xfull, _, _ = s.query()
+        s.set_x(None)
+        s.iterate(8, prm)
+        xmid, _, _ = s.query()
+        s.set_x(xmid)
+        s.iterate(12, prm)
+        xres, _, _ = s.query()
+    assert np.array_equal(xfull, xres)
+
+
+def test_feasible_start_is_a_fixed_point(P):
+    sys_ = W.gaussian(128, 300, seed=1, dtype="f32")
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, x0=sys_.z, dtype="f32")
+        say("fixed point")
+        st, code = s.solve(P.params())
+        x, _, _ = s.query()
+    assert code == 0 and st.iters == 0 and st.h == 0
+    assert np.array_equal(x, sys_.z)
+
+
+def test_error_paths(P):
+    with P.Solver() as s:
+        say("errors")
+        with pytest.raises(P.ModapError) as e:
+            s.iterate(1, P.params())
+        assert e.value.status == 5                      # before set_system
+        A = np.array([[1.0, 0.0], [0.0, 0.0]])
+        with pytest.raises(P.ModapError) as e:
+            s.set_system(A, np.zeros(2), dtype="f64")
+        assert e.value.status == 2                      # zero row
+        with pytest.raises(P.ModapError) as e:
+            s.set_system(np.eye(2), np.array([0.0, np.nan]), dtype="f64")
+        assert e.value.status == 1                      # non-finite b
+        A = np.array([[np.inf, 1.0], [1.0, 1.0]])
+        with pytest.raises(P.ModapError) as e:
+            s.set_system(A, np.zeros(2), dtype="f64")
+        assert e.value.status == 2                      # non-finite row
+        # x <= -1 and -x <= -1: infeasible; at x = 0 both rows are violated and y = 0
+        s.set_system(np.array([[1.0], [-1.0]]), np.array([-1.0, -1.0]), dtype="f64")
+        st, code = s.solve(P.params(), raise_on_stop=False)
+        assert code == 7 and st.state == 2
+        # step limit
+        sys_ = W.c1(0)
+        s.set_system(sys_.A, sys_.b, x0=sys_.x0, dtype="f64")
+        st, code = s.solve(P.params(max_iters=10), raise_on_stop=False)
+        assert code == 6 and st.iters == 10
+        # bad replacement rows
+        with pytest.raises(P.ModapError) as e:
+            s.update_coeffs(np.array([3]), np.zeros((1, sys_.n)), np.array([1.0]))
+        assert e.value.status == 2
+        with pytest.raises(P.ModapError) as e:
+            s.update_coeffs(np.array([3, 3]), np.ones((2, sys_.n)), np.array([1.0, 1.0]))
+        assert e.value.status == 1
+        with pytest.raises(P.ModapError):
+            s.iterate(1, P.params(lam=-1.0))
+        with pytest.raises(P.ModapError):
+            s.set_tile(256, 64, 3)                      # no such compiled shape
+
+
+def test_device_pointers_and_profile(P):
+    """The same calls with torch device tensors (ptrs_on_device = 1), and the
+    per-kernel HIP-event timing used by the benchmark."""
+    import torch
+    sys_ = W.gaussian(1024, 4096, seed=3, dtype="f32")
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(sys_.A).to(dev)
+    b = torch.from_numpy(sys_.b).to(dev)
+    x = torch.from_numpy(probe_point(sys_, 0.1, 3)).to(dev)
+    with P.Solver() as s:
+        say("device pointers")
+        s.set_system(A, b, dtype="f32")
+        g = s.eval_sweep(x)
+        torch.cuda.synchronize()
+        o = oracle.sweep(sys_.A, "f32", sys_.b, x.cpu().numpy())
+        check_sweep(sys_.A, "f32", o, g.y.cpu().numpy(), g.h, g.max_viol, g.r.cpu().numpy())
+        st = s.iterate(10, P.params(lam=0.1, eps=1e-12, profile=True))
+        assert st.profiled == 10 and st.sweep_ms > 0 and st.reduce_ms > 0
