@@ -76,7 +76,8 @@ typedef struct {
     int32_t eps_relative;   /* != 0: eps_abs = eps * max_i |b_i| of the current data; else eps_abs = eps */
     int32_t step;           /* modap_step */
     int64_t max_iters;      /* solve: at most this many steps in the call (>= 0) */
-    int32_t profile;        /* != 0: time every sweep and reduction with HIP events (stats) */
+    int32_t profile;        /* k > 0: time every k-th iteration's kernels with HIP events recorded
+                               by their dispatches (stats); 0: no timing */
     int32_t track;          /* iterate only: != 0 keeps following a changing system -- an
                                eps-feasible check takes no step but does not stop the queued
                                iterations, so drift keeps being applied and re-checked */
@@ -96,7 +97,8 @@ typedef struct {
     double hbm_bytes;       /* algorithmic bytes of the sweeps launched in this call:
                                m*n*sizeof(A) + 16m (+ 8m when a translation is applied) each */
     double sweep_ms;        /* profile: summed duration of the sweep kernels of this call */
-    double reduce_ms;       /* profile: summed duration of the reduction kernels of this call */
+    double reduce_ms;       /* profile: summed time from the start of each reduction of y to the
+                               end of the kernel that takes the stop decision and the step */
     int64_t profiled;       /* profile: number of sweeps timed in this call */
 } modap_stats;
 
@@ -107,8 +109,9 @@ typedef struct {
     int32_t block;          /* threads per workgroup */
     int32_t lanes_per_row;  /* threads that share one row (64 .. block) */
     int32_t chunks;         /* 16-byte vectors per thread per row (kind 0) or per column tile (kind 1) */
-    int32_t grid;           /* workgroups of the sweep */
-    int32_t reserved;
+    int32_t grid;           /* workgroups of the sweep (0 on input: the library's choice) */
+    int32_t rows_per_step;  /* rows each row group loads per step; the next step's rows are
+                               in flight while the current ones are reduced */
 } modap_tile;
 
 /* Create a context on HIP device `device`.  hip_stream: the hipStream_t to
@@ -198,6 +201,15 @@ modap_status modap_set_tile(modap_ctx *ctx, const modap_tile *tile);
 
 /* The kernel shape in use for the loaded system.  Errors: E_STATE, E_INVAL. */
 modap_status modap_get_tile(modap_ctx *ctx, modap_tile *tile);
+
+/* Autotuner: time every compiled sweep shape that covers the loaded rows, at
+ * several grid sizes, with `reps` stateless sweeps each (the context's state
+ * is not changed), keep the fastest and return it in *best (may be NULL).
+ * When the environment variable MODAP_TUNE_CACHE names a file, results are
+ * appended to it (one line per storage type, padded row length and m) and
+ * modap_set_system uses a cached shape for the same key.  Synchronises.
+ * Errors: E_STATE, E_INVAL (reps < 1), E_DEVICE. */
+modap_status modap_autotune(modap_ctx *ctx, int reps, modap_tile *best);
 
 /* Message for a status code (static storage). */
 const char *modap_strerror(modap_status status);

@@ -31,7 +31,7 @@ STATE_NAMES = {0: "running", 1: "converged", 2: "no_direction", 3: "numeric", 4:
 # every symbol declared in include/modap.h
 EXPORTS = ["modap_create", "modap_destroy", "modap_set_system", "modap_set_x", "modap_update_coeffs",
            "modap_set_drift", "modap_iterate", "modap_solve", "modap_eval_sweep", "modap_query",
-           "modap_set_tile", "modap_get_tile", "modap_strerror", "modap_last_error"]
+           "modap_set_tile", "modap_get_tile", "modap_autotune", "modap_strerror", "modap_last_error"]
 
 
 class Params(C.Structure):
@@ -55,10 +55,10 @@ class Stats(C.Structure):
 
 class Tile(C.Structure):
     _fields_ = [("kind", C.c_int32), ("block", C.c_int32), ("lanes_per_row", C.c_int32),
-                ("chunks", C.c_int32), ("grid", C.c_int32), ("reserved", C.c_int32)]
+                ("chunks", C.c_int32), ("grid", C.c_int32), ("rows_per_step", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class ModapError(RuntimeError):
@@ -92,6 +92,7 @@ def lib():
         L.modap_query.argtypes = [vp, dp, dp, C.POINTER(Stats), i32]
         L.modap_set_tile.argtypes = [vp, C.POINTER(Tile)]
         L.modap_get_tile.argtypes = [vp, C.POINTER(Tile)]
+        L.modap_autotune.argtypes = [vp, i32, C.POINTER(Tile)]
         L.modap_strerror.argtypes = [i32]
         L.modap_strerror.restype = C.c_char_p
         L.modap_last_error.argtypes = [vp]
@@ -103,10 +104,11 @@ def lib():
     return _lib
 
 
-def params(lam=1.0, eps=1e-6, eps_relative=True, step=STEP_FIXED, max_iters=100000, profile=False,
+def params(lam=1.0, eps=1e-6, eps_relative=True, step=STEP_FIXED, max_iters=100000, profile=0,
            track=False):
+    """profile: 0 = no timing, k = time every k-th iteration (True = every iteration)."""
     return Params(float(lam), float(eps), int(bool(eps_relative)), int(step), int(max_iters),
-                  int(bool(profile)), int(bool(track)))
+                  int(profile), int(bool(track)))
 
 
 def _is_torch(a):
@@ -294,12 +296,18 @@ class Solver:
         self._check(lib().modap_query(self._ctx, px, pb, C.byref(out), 0))
         return x, b, out
 
-    def set_tile(self, block=None, lanes_per_row=None, chunks=None, grid=0, kind=0):
+    def set_tile(self, block=None, lanes_per_row=None, chunks=None, grid=0, rows_per_step=1, kind=0):
         if block is None:
             self._check(lib().modap_set_tile(self._ctx, None))
             return
-        t = Tile(int(kind), int(block), int(lanes_per_row), int(chunks), int(grid), 0)
+        t = Tile(int(kind), int(block), int(lanes_per_row), int(chunks), int(grid), int(rows_per_step))
         self._check(lib().modap_set_tile(self._ctx, C.byref(t)))
+
+    def autotune(self, reps=5):
+        """Time every compiled sweep shape for the loaded system and keep the fastest."""
+        t = Tile()
+        self._check(lib().modap_autotune(self._ctx, int(reps), C.byref(t)))
+        return t.as_dict()
 
     def get_tile(self):
         t = Tile()

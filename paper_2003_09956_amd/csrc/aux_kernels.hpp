@@ -1,6 +1,7 @@
-// Kernels around the sweep: row norms, the reduction of the partial y with
-// the stop test and the step, control-block updates, in-place row
-// replacement and the flush of a pending translation.
+// Kernels around the sweep: row norms, the fixed-order reduction of the
+// partial y, the stage kernel that settles each iteration, control-block
+// updates made between calls, in-place row replacement and the flush of a
+// pending translation.
 #pragma once
 
 #include "modap_device.hpp"
@@ -48,187 +49,226 @@ __global__ void check_finite(const double *p, int64_t count, int *flag) {
     }
 }
 
-// Sum of the workgroup partials of y in a fixed order (FP64), with the
-// iteration's decision taken by the last workgroup to finish:
-//   eps-feasible (eq. 10)      -> converged, no step
-//   otherwise                  -> s = lambda/||y|| (eq. 12) or lambda/h (Alg. 1)
-// In iteration mode the pending step of the previous iteration is first made
-// permanent: x <- x - s_prev * y_prev, column by column, before y is replaced.
+// Column sums of the workgroup partials of y, in a fixed order, in FP64.
+// Workgroup b writes its share of ||y||^2 to ynp[b]; workgroup 0 also forms
+// the totals of h, dmax and binf.  The stop test and the step are taken from
+// these by the stage kernel.
 template <typename Acc>
 __global__ __launch_bounds__(1024) void reduce_y(const ReduceArgs a) {
-    constexpr int COLS = 64;
-    constexpr int RG = 16;
-    Ctrl *ctl = a.ctl;
-    if (ctl && ctl->status != ST_RUNNING) return;
-    const double s_prev = ctl ? ctl->s : 0.0;
+    constexpr int COLS = 64;                    // columns per workgroup
+    constexpr int VW = 16 / (int)sizeof(Acc);   // columns per 16-byte load
+    constexpr int LPRR = COLS / VW;             // lanes per partial row
+    constexpr int RPW = 64 / LPRR;              // partial rows per wavefront load
+    constexpr int RG = 16 * RPW;                // row groups per workgroup
+    constexpr int U = 8;                        // loads in flight per lane
+    if (a.iterate && a.ctl->st[slot_of(a.j - 1)].status != ST_RUNNING) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int rg = tid >> 6;
-    const int64_t col = (int64_t)blockIdx.x * COLS + lane;
-    const Acc *part = reinterpret_cast<const Acc *>(a.part);
+    const int rg = (tid >> 6) * RPW + lane / LPRR;
+    const int cl = lane % LPRR;
+    // ldPart is a multiple of 64 and covers every workgroup's columns
+    const Acc *pc = reinterpret_cast<const Acc *>(a.part) + (int64_t)blockIdx.x * COLS + cl * VW;
 
-    double acc = 0.0;
-    if (col < a.n) {
-        for (int g = rg; g < a.G; g += RG) acc += (double)part[(int64_t)g * a.ldPart + col];
+    // Batches of U independent 16-byte loads (partial rows rg, rg+RG, ...),
+    // each batch summed in order, batches in order: a fixed order for a given G.
+    double acc[VW];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) acc[k] = 0.0;
+    for (int g0 = rg; g0 < a.G; g0 += U * RG) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int g = min(g0 + u * RG, a.G - 1);
+            v[u] = *reinterpret_cast<const uint4 *>(pc + (int64_t)g * a.ldPart);
+        }
+#pragma unroll
+        for (int k = 0; k < VW; ++k) {
+            double bsum = 0.0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                Acc e[VW];
+                __builtin_memcpy(e, &v[u], 16);
+                if (g0 + u * RG < a.G) bsum += (double)e[k];
+            }
+            acc[k] += bsum;
+        }
     }
     __shared__ double sh[RG][COLS];
-    sh[rg][lane] = acc;
-    __syncthreads();
-    if (rg == 0) {
-        double yv = 0.0;
 #pragma unroll
-        for (int r = 0; r < RG; ++r) yv += sh[r][lane];
+    for (int k = 0; k < VW; ++k) sh[rg][cl * VW + k] = acc[k];
+    __syncthreads();
+    if (tid < 64) {
+        const int64_t col = (int64_t)blockIdx.x * COLS + tid;
+        double yv = 0.0;
+#pragma unroll 8
+        for (int r = 0; r < RG; ++r) yv += sh[r][tid];
         double sq = 0.0;
         if (col < a.n) {
-            if (ctl && a.x && s_prev != 0.0) a.x[col] = step_point(a.x[col], s_prev, a.y[col]);
             a.y[col] = yv;
             sq = yv * yv;
         }
         sq = wave_sum(sq);
-        if (lane == 0) a.ynorm_part[blockIdx.x] = sq;
+        if (tid == 0) a.ynp[blockIdx.x] = sq;
     }
+    if (blockIdx.x != 0) return;
 
-    // Elect the last workgroup (release our writes, then count).
-    __shared__ int is_last;
-    unsigned *ticket = ctl ? &ctl->ticket : &a.eval->ticket;
-    if (tid == 0) {
-        __threadfence();
-        const unsigned t = atomicAdd(ticket, 1u);
-        is_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-
+    const int wv = tid >> 6;
     int64_t h = 0;
-    double dm = 0.0, bm = 0.0, ys = 0.0;
+    double dm = 0.0, bm = 0.0;
     for (int g = tid; g < a.G; g += 1024) {
         h += a.h_part[g];
         dm = max_nan(dm, a.dmax_part[g]);
         bm = max_nan(bm, a.binf_part[g]);
     }
-    for (int b = tid; b < (int)gridDim.x; b += 1024) ys += a.ynorm_part[b];
-    // fixed-order reduction: butterfly within each wavefront, then wavefronts in order
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         h += __shfl_xor(h, o, 64);
         dm = max_nan(dm, __shfl_xor(dm, o, 64));
         bm = max_nan(bm, __shfl_xor(bm, o, 64));
-        ys += __shfl_xor(ys, o, 64);
     }
     __shared__ int64_t hw[16];
-    __shared__ double dw[16], bw[16], yw[16];
+    __shared__ double dw[16], bw[16];
     if (lane == 0) {
-        hw[rg] = h;
-        dw[rg] = dm;
-        bw[rg] = bm;
-        yw[rg] = ys;
+        hw[wv] = h;
+        dw[wv] = dm;
+        bw[wv] = bm;
     }
     __syncthreads();
     if (tid != 0) return;
-    h = 0;
-    dm = 0.0;
-    bm = 0.0;
-    ys = 0.0;
+    Totals t{};
     for (int w = 0; w < 16; ++w) {
-        h += hw[w];
-        dm = max_nan(dm, dw[w]);
-        bm = max_nan(bm, bw[w]);
-        ys += yw[w];
+        t.h += hw[w];
+        t.dmax = max_nan(t.dmax, dw[w]);
+        t.binf = max_nan(t.binf, bw[w]);
     }
-    const double ynorm = sqrt(ys);
-    if (!ctl) {
-        a.eval->h = h;
-        a.eval->dmax = dm;
-        a.eval->binf = bm;
-        a.eval->ynorm = ynorm;
-        a.eval->ticket = 0u;
+    *a.tot = t;
+}
+
+// Settle iteration j after its check: every workgroup takes the decision
+// from the check's totals (the same arithmetic in every workgroup),
+// workgroup 0 records it in slot j & 1, and each workgroup, for its columns,
+// makes the step permanent in FP64 (x <- x - s*y, eq. 12 or Algorithm 1) and
+// writes the working vectors of the next sweep in the accumulation type:
+// x, and the translation due before the next check (drift row v_idx).
+template <typename Acc>
+__global__ __launch_bounds__(256) void stage_iter(const StageArgs a) {
+    const State p = a.ctl->st[slot_of(a.j - 1)];
+    if (p.status != ST_RUNNING) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->st[slot_of(a.j)] = p;
         return;
     }
-    const double eps_abs = a.eps_relative ? a.eps * bm : a.eps;
-    ctl->sweeps += 1;
-    ctl->dmax = dm;
-    ctl->binf = bm;
-    ctl->ynorm = ynorm;
-    ctl->h = h;
-    ctl->eps_abs = eps_abs;
-    ctl->vpend_valid = 0;
-    ctl->s = 0.0;
-    ctl->v_idx = -1;
-    ctl->feasible = dm <= eps_abs;
-    if (dm <= eps_abs) {
-        if (a.track) {
-            // no step; the data keep changing and the next sweep checks again
-            if (ctl->sched_pos < ctl->sched_len) ctl->v_idx = ctl->sched_pos++;
-        } else {
-            ctl->status = ST_CONVERGED;
+    __shared__ State sst;
+    if (threadIdx.x < 64) {
+        const double yn = ynorm_of(a.ynp, a.R, threadIdx.x);
+        const State cur = decide(p, *a.tot, yn, a.dp, a.ctl->step_limit, a.ctl->sched_len);
+        if (threadIdx.x == 0) {
+            sst = cur;
+            if (blockIdx.x == 0) a.ctl->st[slot_of(a.j)] = cur;
         }
-    } else if (!isfinite(dm) || !isfinite(ynorm) || !isfinite(bm)) {
-        ctl->status = ST_NUMERIC;
-    } else if (ctl->steps >= ctl->step_limit) {
-        ctl->status = ST_LIMIT;
-    } else if (!(ynorm > 0.0) || h == 0) {
-        ctl->status = ST_NO_DIRECTION;
-    } else {
-        ctl->s = a.rule == 0 ? a.lambda / ynorm : a.lambda / (double)h;
-        ctl->steps += 1;
-        if (ctl->sched_pos < ctl->sched_len) ctl->v_idx = ctl->sched_pos++;
     }
-    ctl->ticket = 0u;
+    __syncthreads();
+    const double s = sst.s;
+    const double *vrow = (a.V && sst.v_idx >= 0) ? a.V + sst.v_idx * a.ldV : nullptr;
+    Acc *wx = reinterpret_cast<Acc *>(a.work);
+    Acc *wv = wx + a.ldA;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        double xv = a.x[j];
+        if (s != 0.0) {
+            xv = step_point(xv, s, a.y[j]);
+            a.x[j] = xv;
+        }
+        wx[j] = (Acc)xv;
+        wv[j] = vrow ? (Acc)vrow[j] : (Acc)0;
+    }
 }
+
+// Working vectors for the first sweep of a call (or an evaluation) from the
+// committed state in slot (j-1)&1: x as it is, and the pending translation
+// (one-shot part plus the drift row due).
+template <typename Acc>
+__global__ __launch_bounds__(256) void prime_work(const StageArgs a) {
+    const State &p = a.ctl->st[slot_of(a.j - 1)];
+    const bool use_p = p.vpend_valid != 0;
+    const double *vrow = (a.V && p.v_idx >= 0) ? a.V + p.v_idx * a.ldV : nullptr;
+    Acc *wx = reinterpret_cast<Acc *>(a.work);
+    Acc *wv = wx + a.ldA;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (use_p ? a.vpend[j] : 0.0) + (vrow ? vrow[j] : 0.0);
+        wx[j] = (Acc)a.x[j];
+        wv[j] = (Acc)v;
+    }
+}
+
+// The control kernels below run between calls as a single thread (or a
+// single workgroup) on the committed state in slot `sl`.
 
 // Start of an iterate/solve call: a stop that came from a previous call's
 // tolerance, step limit or missing direction is re-examined by the next sweep.
-__global__ void ctl_begin(Ctrl *c, int64_t max_steps) {
+__global__ void ctl_begin(Ctrl *c, int sl, int64_t max_steps) {
     if (threadIdx.x != 0) return;
-    const int32_t st = c->status;
-    if (st == ST_CONVERGED || st == ST_LIMIT || st == ST_NO_DIRECTION) c->status = ST_RUNNING;
-    c->step_limit = max_steps < 0 ? INT64_MAX : c->steps + max_steps;
+    State &s = c->st[sl];
+    if (s.status == ST_CONVERGED || s.status == ST_LIMIT || s.status == ST_NO_DIRECTION) s.status = ST_RUNNING;
+    c->step_limit = max_steps < 0 ? INT64_MAX : s.steps + max_steps;
+}
+
+// A fresh state (set_system): both slots.
+__global__ void ctl_init(Ctrl *c) {
+    if (threadIdx.x != 0) return;
+    State s{};
+    s.v_idx = -1;
+    s.status = ST_RUNNING;
+    c->st[0] = s;
+    c->st[1] = s;
+    c->step_limit = INT64_MAX;
+    c->sched_len = 0;
 }
 
 // A new approximation: counters restart, no step is pending.
-__global__ void ctl_restart(Ctrl *c) {
+__global__ void ctl_restart(Ctrl *c, int sl) {
     if (threadIdx.x != 0) return;
-    if (c->status != ST_BAD_ROW) c->status = ST_RUNNING;
-    c->s = 0.0;
-    c->steps = 0;
-    c->sweeps = 0;
-    c->dmax = c->binf = c->ynorm = c->eps_abs = 0.0;
-    c->h = 0;
-    c->feasible = 0;
+    State &s = c->st[sl];
+    if (s.status != ST_BAD_ROW) s.status = ST_RUNNING;
+    s.s = 0.0;
+    s.steps = 0;
+    s.sweeps = 0;
+    s.dmax = s.binf = s.ynorm = s.eps_abs = 0.0;
+    s.h = 0;
+    s.feasible = 0;
 }
 
 // One-shot translation: vpend <- (pending ? vpend : 0) + v.  A single
 // workgroup, so the pending flag is read before it is set.
-__global__ __launch_bounds__(1024) void vpend_add(Ctrl *c, double *vpend, const double *v, int64_t n) {
-    const int valid = c->vpend_valid;
+__global__ __launch_bounds__(1024) void vpend_add(Ctrl *c, int sl, double *vpend, const double *v, int64_t n) {
+    const int valid = c->st[sl].vpend_valid;
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) vpend[j] = valid ? vpend[j] + v[j] : v[j];
     __syncthreads();
-    if (threadIdx.x == 0) c->vpend_valid = 1;
+    if (threadIdx.x == 0) c->st[sl].vpend_valid = 1;
 }
 
 // Move a drift-schedule translation that is due at the next sweep into the
-// one-shot slot (used before the schedule buffer is replaced).
-__global__ __launch_bounds__(1024) void sched_to_vpend(Ctrl *c, double *vpend, const double *V,
+// one-shot slot (used before the schedule buffer is replaced or b is read).
+__global__ __launch_bounds__(1024) void sched_to_vpend(Ctrl *c, int sl, double *vpend, const double *V,
                                                        int64_t ldV, int64_t n) {
-    const int64_t idx = c->v_idx;
-    const int valid = c->vpend_valid;
+    const int64_t idx = c->st[sl].v_idx;
+    const int valid = c->st[sl].vpend_valid;
     if (idx >= 0 && V) {
         for (int64_t j = threadIdx.x; j < n; j += blockDim.x)
             vpend[j] = (valid ? vpend[j] : 0.0) + V[idx * ldV + j];
     }
     __syncthreads();
     if (threadIdx.x == 0 && idx >= 0) {
-        c->vpend_valid = V ? 1 : valid;
-        c->v_idx = -1;
+        c->st[sl].vpend_valid = V ? 1 : valid;
+        c->st[sl].v_idx = -1;
     }
 }
 
-__global__ void ctl_set_drift(Ctrl *c, int64_t T) {
+__global__ void ctl_set_drift(Ctrl *c, int sl, int64_t T) {
     if (threadIdx.x != 0) return;
     c->sched_len = T;
-    c->sched_pos = 0;
-    c->v_idx = -1;
+    c->st[sl].sched_pos = 0;
+    c->st[sl].v_idx = -1;
 }
 
 // Row replacement in place (one workgroup per replaced row): copy the new
@@ -238,15 +278,15 @@ template <int DT>
 __global__ __launch_bounds__(256) void scatter_rows(void *A, int64_t ldA, int64_t m, int64_t n,
                                                     const int64_t *rows, const void *new_rows,
                                                     const double *new_b, double *b, double *nu,
-                                                    Ctrl *ctl, const double *vpend) {
+                                                    Ctrl *ctl, int sl, const double *vpend) {
     using T = typename Store<DT>::T;
     const int64_t q = blockIdx.x;
     const int64_t i = rows[q];
     if (i < 0 || i >= m) {
-        if (threadIdx.x == 0) ctl->status = ST_BAD_ROW;
+        if (threadIdx.x == 0) ctl->st[sl].status = ST_BAD_ROW;
         return;
     }
-    const int valid = ctl->vpend_valid;
+    const int valid = ctl->st[sl].vpend_valid;
     T *dst = reinterpret_cast<T *>(A) + i * ldA;
     const T *src = reinterpret_cast<const T *>(new_rows) + q * n;
     double s2 = 0.0, sv = 0.0;
@@ -270,17 +310,16 @@ __global__ __launch_bounds__(256) void scatter_rows(void *A, int64_t ldA, int64_
         const double tv = ((pv[0] + pv[1]) + pv[2]) + pv[3];
         nu[i] = t2;
         b[i] = valid ? new_b[q] - tv : new_b[q];
-        if (!(t2 > 0.0) || !isfinite(t2) || !isfinite(new_b[q])) ctl->status = ST_BAD_ROW;
+        if (!(t2 > 0.0) || !isfinite(t2) || !isfinite(new_b[q])) ctl->st[sl].status = ST_BAD_ROW;
     }
 }
 
 // Apply a pending one-shot translation to b with a pass of its own (used when
 // b is read back): b_i += <a_i, vpend>, FP64, one wavefront per row.
 template <int DT>
-__global__ __launch_bounds__(256) void flush_translation(const void *A, int64_t ldA, int64_t m,
-                                                         int64_t n, const Ctrl *ctl,
-                                                         const double *vpend, double *b) {
-    if (!ctl->vpend_valid) return;
+__global__ __launch_bounds__(256) void flush_translation(const void *A, int64_t ldA, int64_t m, int64_t n,
+                                                         const Ctrl *ctl, int sl, const double *vpend, double *b) {
+    if (!ctl->st[sl].vpend_valid) return;
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= m) return;
@@ -290,21 +329,8 @@ __global__ __launch_bounds__(256) void flush_translation(const void *A, int64_t 
     if (lane == 0) b[row] += s;
 }
 
-__global__ void ctl_clear_vpend(Ctrl *c) {
-    if (threadIdx.x == 0) c->vpend_valid = 0;
-}
-
-// Make a pending step permanent (used when x is read back): x <- x - s*y.
-__global__ void materialize_x(const Ctrl *c, double *x, const double *y, int64_t n) {
-    const double s = c->s;
-    if (s == 0.0) return;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
-         j += (int64_t)gridDim.x * blockDim.x)
-        x[j] = step_point(x[j], s, y[j]);
-}
-
-__global__ void ctl_clear_step(Ctrl *c) {
-    if (threadIdx.x == 0) c->s = 0.0;
+__global__ void ctl_clear_vpend(Ctrl *c, int sl) {
+    if (threadIdx.x == 0) c->st[sl].vpend_valid = 0;
 }
 
 }  // namespace modap

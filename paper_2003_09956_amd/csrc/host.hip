@@ -3,10 +3,13 @@
 // A context owns a device copy of the system (rows padded with zeros to a
 // 16-byte multiple), its FP64 row norms, the approximation x, the last y, a
 // one-shot translation slot, an optional drift schedule, the per-workgroup
-// partials and a device control block.  One iteration is two kernels on the
-// context's stream: the fused sweep and the fixed-order reduction whose last
-// workgroup takes the stop decision and the step scale.  The host never waits
-// between iterations; solve() reads the control block once per batch.
+// partials, the working vectors of the next sweep and a device control block.
+// One iteration is three kernels on the context's stream: the fused sweep,
+// the fixed-order reduction of y, and the stage kernel that takes the stop
+// decision and the step and writes the next sweep's working vectors.  The
+// host never waits between iterations; solve() reads the control block once
+// per batch.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +17,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <unordered_set>
@@ -29,7 +33,6 @@ using namespace modap;
 struct modap_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    bool own_stream = false;
     int cu_count = 0;
     std::string err;
 
@@ -43,6 +46,7 @@ struct modap_ctx {
     double *V = nullptr;
     int64_t T = 0;
     bool vpend_maybe = false;   // a translation may be pending on the device
+    int64_t jn = 0;             // index of the next iteration; state of jn-1 is committed
 
     // kernel shape and scratch
     modap_tile tile{};
@@ -53,12 +57,15 @@ struct modap_ctx {
     void *part = nullptr;
     size_t part_bytes = 0;
     int64_t *h_part = nullptr;
-    double *dmax_part = nullptr, *binf_part = nullptr, *ynorm_part = nullptr;
+    double *dmax_part = nullptr, *binf_part = nullptr;
     int part_grid = 0;
+    double *ynp = nullptr;
+    Totals *tot = nullptr;
+    void *work = nullptr;        // [2 x ldA] accumulation type: x and v of the next sweep
+    void *work_eval = nullptr;
 
     Ctrl *ctl = nullptr;
-    EvalOut *eval = nullptr;
-    Ctrl *hctl = nullptr;        // pinned [2]
+    State *hst = nullptr;        // pinned [2]
     double *x_eval = nullptr, *y_eval = nullptr, *r_eval = nullptr;
     unsigned long long *bad = nullptr;
     int *flag = nullptr;
@@ -111,6 +118,7 @@ modap_status hip_fail(modap_ctx *c, hipError_t e, const char *what) {
     } while (0)
 
 size_t elem_size(int dt) { return dt == 0 ? 8 : dt == 1 ? 4 : 2; }
+size_t acc_size(int dt) { return dt == 0 ? 8 : 4; }
 int vec_elems(int dt) { return 16 / (int)elem_size(dt); }
 
 template <typename P>
@@ -127,18 +135,21 @@ const SweepKernel *kernels_for(int dt, int *count) {
     }
 }
 
-const SweepKernel *find_kernel(int dt, int block, int lpr, int chunks, bool has_v) {
+const SweepKernel *find_kernel(int dt, int block, int lpr, int chunks, int rs, bool has_v) {
     int cnt = 0;
     const SweepKernel *t = kernels_for(dt, &cnt);
     for (int i = 0; i < cnt; ++i)
-        if (t[i].block == block && t[i].lpr == lpr && t[i].chunks == chunks && t[i].has_v == has_v) return &t[i];
+        if (t[i].block == block && t[i].lpr == lpr && t[i].chunks == chunks && t[i].rs == rs &&
+            t[i].has_v == has_v)
+            return &t[i];
     return nullptr;
 }
 
 int64_t coverage(int dt, int lpr, int chunks) { return (int64_t)lpr * vec_elems(dt) * chunks; }
 
 // Built-in choice of the fused sweep's shape: the smallest row coverage that
-// holds a padded row; among equal coverage, about 16 elements per lane.
+// holds a padded row; among equal coverage, about 16 elements per lane, then
+// the larger workgroup, then two rows per step.
 bool choose_shape(int dt, int64_t ldA, modap_tile *out) {
     int cnt = 0;
     const SweepKernel *t = kernels_for(dt, &cnt);
@@ -150,7 +161,8 @@ bool choose_shape(int dt, int64_t ldA, modap_tile *out) {
         const int64_t cov = coverage(dt, t[i].lpr, t[i].chunks);
         if (cov < ldA) continue;
         const int epl = t[i].chunks * vec_elems(dt);
-        const int score = std::abs(epl - 16) * 4 + (t[i].block == 1024 ? 0 : t[i].block == 512 ? 1 : 2);
+        const int score = std::abs(epl - 16) * 16 + (t[i].block == 1024 ? 0 : t[i].block == 512 ? 4 : 8) +
+                          (t[i].rs == 2 ? 0 : t[i].rs == 1 ? 1 : 2);
         if (!best || cov < best_cov || (cov == best_cov && score < best_score)) {
             best = &t[i];
             best_cov = cov;
@@ -163,7 +175,7 @@ bool choose_shape(int dt, int64_t ldA, modap_tile *out) {
     out->lanes_per_row = best->lpr;
     out->chunks = best->chunks;
     out->grid = 0;
-    out->reserved = 0;
+    out->rows_per_step = best->rs;
     return true;
 }
 
@@ -171,12 +183,13 @@ bool choose_shape(int dt, int64_t ldA, modap_tile *out) {
 modap_status configure(modap_ctx *c, const modap_tile &want) {
     modap_tile t = want;
     if (t.kind != 0) return fail(c, MODAP_E_INVAL, "only the one-pass sweep shape (kind 0) is built");
-    const SweepKernel *kv = find_kernel(c->dt, t.block, t.lanes_per_row, t.chunks, true);
-    const SweepKernel *kn = find_kernel(c->dt, t.block, t.lanes_per_row, t.chunks, false);
+    if (t.rows_per_step <= 0) t.rows_per_step = 1;
+    const SweepKernel *kv = find_kernel(c->dt, t.block, t.lanes_per_row, t.chunks, t.rows_per_step, true);
+    const SweepKernel *kn = find_kernel(c->dt, t.block, t.lanes_per_row, t.chunks, t.rows_per_step, false);
     if (!kv || !kn) return fail(c, MODAP_E_INVAL, "no compiled sweep kernel of that shape for this storage type");
     const int64_t cov = coverage(c->dt, t.lanes_per_row, t.chunks);
     if (cov < c->ldA) return fail(c, MODAP_E_INVAL, "sweep shape does not cover a row");
-    const int ng = t.block / t.lanes_per_row;
+    const int per_step = (t.block / t.lanes_per_row) * t.rows_per_step;
     int grid = t.grid;
     if (grid <= 0) {
         int per_cu = 0;
@@ -185,7 +198,7 @@ modap_status configure(modap_ctx *c, const modap_tile &want) {
         grid = c->cu_count * per_cu;
     }
     int64_t rpb = (c->m + grid - 1) / grid;
-    rpb = ((rpb + ng - 1) / ng) * ng;
+    rpb = ((rpb + per_step - 1) / per_step) * per_step;
     grid = (int)((c->m + rpb - 1) / rpb);
     const size_t acc = c->dt == 0 ? 8 : 4;
     const size_t need = (size_t)grid * (size_t)cov * acc;
@@ -224,7 +237,7 @@ modap_status check_params(modap_ctx *c, const modap_params *p) {
     if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(c, MODAP_E_INVAL, "eps must be finite and > 0");
     if (p->step != MODAP_STEP_FIXED && p->step != MODAP_STEP_AVG) return fail(c, MODAP_E_INVAL, "unknown step rule");
     if (p->max_iters < 0) return fail(c, MODAP_E_INVAL, "max_iters must be >= 0");
-
+    if (p->profile < 0) return fail(c, MODAP_E_INVAL, "profile must be >= 0");
     return MODAP_OK;
 }
 
@@ -262,6 +275,20 @@ double sweep_bytes(const modap_ctx *c, bool with_v) {
 
 bool translation_possible(const modap_ctx *c) { return c->vpend_maybe || (c->V && c->T > 0); }
 
+int reduce_grid(const modap_ctx *c) { return (int)((c->n + 63) / 64); }
+
+int last_slot(const modap_ctx *c) { return (int)((c->jn - 1) & 1); }
+
+Decide decide_params(const modap_params *p, int track) {
+    Decide d{};
+    d.lambda = p->lambda;
+    d.eps = p->eps;
+    d.eps_relative = p->eps_relative;
+    d.rule = p->step;
+    d.track = track;
+    return d;
+}
+
 SweepArgs sweep_args(modap_ctx *c) {
     SweepArgs a{};
     a.A = c->A;
@@ -270,9 +297,7 @@ SweepArgs sweep_args(modap_ctx *c) {
     a.n = c->n;
     a.b_in = c->b;
     a.nu = c->nu;
-    a.vpend = c->vpend;
-    a.V = c->V;
-    a.ldV = c->n;
+    a.work = c->work;
     a.ctl = c->ctl;
     a.part = c->part;
     a.ldPart = c->ldPart;
@@ -293,13 +318,20 @@ ReduceArgs reduce_args(modap_ctx *c) {
     r.h_part = c->h_part;
     r.dmax_part = c->dmax_part;
     r.binf_part = c->binf_part;
-    r.ynorm_part = c->ynorm_part;
+    r.tot = c->tot;
+    r.ynp = c->ynp;
     return r;
 }
 
-int reduce_grid(const modap_ctx *c) { return (int)((c->n + 63) / 64); }
-
-modap_status launch_reduce(modap_ctx *c, const ReduceArgs &r) {
+modap_status launch_reduce(modap_ctx *c, const ReduceArgs &r, hipEvent_t e0 = nullptr) {
+    if (e0) {
+        ReduceArgs copy = r;
+        void *args[] = {&copy};
+        const void *f = r.acc_f64 ? reinterpret_cast<const void *>(&reduce_y<double>)
+                                  : reinterpret_cast<const void *>(&reduce_y<float>);
+        HIP_TRY(c, hipExtLaunchKernel(f, dim3(reduce_grid(c)), dim3(1024), args, 0, c->stream, e0, nullptr, 0));
+        return MODAP_OK;
+    }
     if (r.acc_f64)
         hipLaunchKernelGGL(reduce_y<double>, dim3(reduce_grid(c)), dim3(1024), 0, c->stream, r);
     else
@@ -317,53 +349,99 @@ hipEvent_t event_at(modap_ctx *c, size_t i) {
     return c->events[i];
 }
 
-// Queue one iteration: sweep at x - s*y on the current data, then the reduction.
-modap_status enqueue_iteration(modap_ctx *c, const modap_params *p, int track, size_t *ev_used, double *bytes) {
+// Profiling: events 4i..4i+3 of iteration i mark the sweep's start and end
+// and the reduction's start and the stage kernel's end, recorded by the
+// kernel dispatches themselves.
+bool profile_events(modap_ctx *c, size_t first, hipEvent_t (&e)[4]) {
+    for (int k = 0; k < 4; ++k) {
+        e[k] = event_at(c, first + k);
+        if (!e[k]) return false;
+    }
+    return true;
+}
+
+StageArgs stage_args(modap_ctx *c, const modap_params *p, int track, int64_t j) {
+    StageArgs g{};
+    g.ctl = c->ctl;
+    g.j = j;
+    g.tot = c->tot;
+    g.ynp = c->ynp;
+    g.R = reduce_grid(c);
+    if (p) g.dp = decide_params(p, track);
+    g.x = c->x;
+    g.y = c->y;
+    g.vpend = c->vpend;
+    g.V = c->V;
+    g.ldV = c->ldA;
+    g.n = c->n;
+    g.ldA = c->ldA;
+    g.work = c->work;
+    return g;
+}
+
+int stage_grid(const modap_ctx *c) { return (int)std::min<int64_t>(1024, (c->n + 255) / 256); }
+
+// Working vectors of the next sweep from the committed state (call start).
+modap_status enqueue_prime(modap_ctx *c, void *work, const double *x) {
+    StageArgs g = stage_args(c, nullptr, 0, c->jn);
+    g.x = const_cast<double *>(x);
+    g.work = work;
+    if (c->dt == 0)
+        hipLaunchKernelGGL(prime_work<double>, dim3(stage_grid(c)), dim3(256), 0, c->stream, g);
+    else
+        hipLaunchKernelGGL(prime_work<float>, dim3(stage_grid(c)), dim3(256), 0, c->stream, g);
+    LAUNCH_TRY(c, "prime_work launch");
+    return MODAP_OK;
+}
+
+// Queue one iteration: the sweep at the current x on the current data, the
+// reduction of y, and the stage kernel (decision, step, next working vectors).
+modap_status enqueue_iteration(modap_ctx *c, const modap_params *p, int track, int64_t i, size_t *ev_used,
+                               double *bytes) {
     const bool hv = translation_possible(c);
+    const int64_t j = c->jn;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (p->profile > 0 && i % p->profile == 0) {
+        if (!profile_events(c, *ev_used, ev)) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
+        *ev_used += 4;
+    }
     SweepArgs a = sweep_args(c);
     a.b_out = c->b;
-    a.x = c->x;
-    a.ystep = c->y;
+    a.j = j;
     a.check_status = 1;
     const SweepKernel *k = hv ? c->kern_v : c->kern_nov;
-    if (p->profile) {
-        hipEvent_t e = event_at(c, (*ev_used)++);
-        if (!e) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
-        HIP_TRY(c, hipEventRecord(e, c->stream));
-    }
-    HIP_TRY(c, k->launch(a, c->tile.grid, c->stream));
-    if (p->profile) {
-        hipEvent_t e = event_at(c, (*ev_used)++);
-        if (!e) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
-        HIP_TRY(c, hipEventRecord(e, c->stream));
-    }
+    modap_status st;
+    HIP_TRY(c, k->launch(a, c->tile.grid, c->stream, ev[0], ev[1]));
     ReduceArgs r = reduce_args(c);
     r.y = c->y;
-    r.x = c->x;
     r.ctl = c->ctl;
-    r.lambda = p->lambda;
-    r.eps = p->eps;
-    r.eps_relative = p->eps_relative;
-    r.rule = p->step;
-    r.track = track;
-    modap_status st = launch_reduce(c, r);
-    if (st != MODAP_OK) return st;
-    if (p->profile) {
-        hipEvent_t e = event_at(c, (*ev_used)++);
-        if (!e) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
-        HIP_TRY(c, hipEventRecord(e, c->stream));
+    r.j = j;
+    r.iterate = 1;
+    if ((st = launch_reduce(c, r, ev[2]))) return st;
+    StageArgs g = stage_args(c, p, track, j);
+    const void *sf = c->dt == 0 ? reinterpret_cast<const void *>(&stage_iter<double>)
+                                : reinterpret_cast<const void *>(&stage_iter<float>);
+    if (ev[3]) {
+        void *args[] = {&g};
+        HIP_TRY(c, hipExtLaunchKernel(sf, dim3(stage_grid(c)), dim3(256), args, 0, c->stream, nullptr, ev[3], 0));
+    } else if (c->dt == 0) {
+        hipLaunchKernelGGL(stage_iter<double>, dim3(stage_grid(c)), dim3(256), 0, c->stream, (const StageArgs)g);
+    } else {
+        hipLaunchKernelGGL(stage_iter<float>, dim3(stage_grid(c)), dim3(256), 0, c->stream, (const StageArgs)g);
     }
+    LAUNCH_TRY(c, "stage_iter launch");
+    c->jn = j + 1;
     *bytes += sweep_bytes(c, hv);
     return MODAP_OK;
 }
 
-modap_status read_ctl(modap_ctx *c, Ctrl *out) {
-    HIP_TRY(c, hipMemcpyAsync(out, c->ctl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+modap_status read_state(modap_ctx *c, State *out) {
+    HIP_TRY(c, hipMemcpyAsync(out, &c->ctl->st[last_slot(c)], sizeof(State), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return MODAP_OK;
 }
 
-void fill_stats(modap_stats *o, const Ctrl &k) {
+void fill_stats(modap_stats *o, const State &k) {
     o->iters = k.steps;
     o->sweeps = k.sweeps;
     o->converged = k.feasible;
@@ -378,10 +456,10 @@ void fill_stats(modap_stats *o, const Ctrl &k) {
 modap_status profile_totals(modap_ctx *c, size_t ev_used, modap_stats *o) {
     double sw = 0.0, rd = 0.0;
     int64_t cnt = 0;
-    for (size_t i = 0; i + 2 < ev_used; i += 3) {
+    for (size_t i = 0; i + 3 < ev_used; i += 4) {
         float a = 0.f, b = 0.f;
         HIP_TRY(c, hipEventElapsedTime(&a, c->events[i], c->events[i + 1]));
-        HIP_TRY(c, hipEventElapsedTime(&b, c->events[i + 1], c->events[i + 2]));
+        HIP_TRY(c, hipEventElapsedTime(&b, c->events[i + 2], c->events[i + 3]));
         sw += a;
         rd += b;
         ++cnt;
@@ -392,7 +470,7 @@ modap_status profile_totals(modap_ctx *c, size_t ev_used, modap_stats *o) {
     return MODAP_OK;
 }
 
-modap_status status_of(modap_ctx *c, const Ctrl &k, bool solve) {
+modap_status status_of(modap_ctx *c, const State &k, bool solve) {
     switch (k.status) {
         case ST_RUNNING:
         case ST_CONVERGED: return MODAP_OK;
@@ -412,12 +490,80 @@ void release_system(modap_ctx *c) {
     free_dev(c->y);
     free_dev(c->vpend);
     free_dev(c->V);
-    free_dev(c->ynorm_part);
+    free_dev(c->ynp);
+    free_dev(c->work);
+    free_dev(c->work_eval);
     free_dev(c->x_eval);
     free_dev(c->y_eval);
     free_dev(c->r_eval);
     c->T = 0;
     c->loaded = false;
+}
+
+modap_status launch_scatter(modap_ctx *c, int64_t k, const int64_t *rows, const void *new_rows, const double *nb) {
+    const int sl = last_slot(c);
+    switch (c->dt) {
+        case 0: hipLaunchKernelGGL(scatter_rows<0>, dim3(k), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, rows, new_rows, nb, c->b, c->nu, c->ctl, sl, (const double *)c->vpend); break;
+        case 1: hipLaunchKernelGGL(scatter_rows<1>, dim3(k), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, rows, new_rows, nb, c->b, c->nu, c->ctl, sl, (const double *)c->vpend); break;
+        default: hipLaunchKernelGGL(scatter_rows<2>, dim3(k), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, rows, new_rows, nb, c->b, c->nu, c->ctl, sl, (const double *)c->vpend); break;
+    }
+    LAUNCH_TRY(c, "scatter_rows launch");
+    return MODAP_OK;
+}
+
+modap_status launch_flush(modap_ctx *c) {
+    const int sl = last_slot(c);
+    const int nb = (int)((c->m + 3) / 4);
+    hipLaunchKernelGGL(sched_to_vpend, dim3(1), dim3(1024), 0, c->stream, c->ctl, sl, c->vpend, (const double *)c->V,
+                       c->ldA, c->n);
+    switch (c->dt) {
+        case 0: hipLaunchKernelGGL(flush_translation<0>, dim3(nb), dim3(256), 0, c->stream, (const void *)c->A, c->ldA, c->m, c->n, (const Ctrl *)c->ctl, sl, (const double *)c->vpend, c->b); break;
+        case 1: hipLaunchKernelGGL(flush_translation<1>, dim3(nb), dim3(256), 0, c->stream, (const void *)c->A, c->ldA, c->m, c->n, (const Ctrl *)c->ctl, sl, (const double *)c->vpend, c->b); break;
+        default: hipLaunchKernelGGL(flush_translation<2>, dim3(nb), dim3(256), 0, c->stream, (const void *)c->A, c->ldA, c->m, c->n, (const Ctrl *)c->ctl, sl, (const double *)c->vpend, c->b); break;
+    }
+    hipLaunchKernelGGL(ctl_clear_vpend, dim3(1), dim3(64), 0, c->stream, c->ctl, sl);
+    LAUNCH_TRY(c, "flush_translation launch");
+    return MODAP_OK;
+}
+
+
+// Tuning cache: lines "dt ldA m block lanes_per_row chunks rows_per_step grid".
+const char *tune_cache_path() {
+    const char *p = std::getenv("MODAP_TUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+
+bool cache_lookup(const modap_ctx *c, modap_tile *t) {
+    const char *path = tune_cache_path();
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    long long dt, lda, m;
+    int blk, lpr, ch, rs, grid;
+    bool found = false;
+    while (std::fscanf(f, "%lld %lld %lld %d %d %d %d %d", &dt, &lda, &m, &blk, &lpr, &ch, &rs, &grid) == 8) {
+        if (dt == c->dt && lda == c->ldA && m == c->m) {  // the last matching line wins
+            t->kind = 0;
+            t->block = blk;
+            t->lanes_per_row = lpr;
+            t->chunks = ch;
+            t->rows_per_step = rs;
+            t->grid = grid;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const modap_ctx *c, const modap_tile &t) {
+    const char *path = tune_cache_path();
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%d %lld %lld %d %d %d %d %d\n", c->dt, (long long)c->ldA, (long long)c->m, t.block,
+                 t.lanes_per_row, t.chunks, t.rows_per_step, t.grid);
+    std::fclose(f);
 }
 
 }  // namespace
@@ -458,22 +604,19 @@ modap_status modap_create(int device, void *hip_stream, modap_ctx **out) {
     }
     c->cu_count = prop.multiProcessorCount;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);  // NULL: the device's default stream
-    bool ok = hipMalloc(&c->ctl, sizeof(Ctrl)) == hipSuccess && hipMalloc(&c->eval, sizeof(EvalOut)) == hipSuccess &&
+    bool ok = hipMalloc(&c->ctl, sizeof(Ctrl)) == hipSuccess && hipMalloc(&c->tot, sizeof(Totals)) == hipSuccess &&
               hipMalloc(&c->bad, sizeof(unsigned long long)) == hipSuccess &&
               hipMalloc(&c->flag, sizeof(int)) == hipSuccess &&
-              hipHostMalloc(&c->hctl, 2 * sizeof(Ctrl), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&c->hst, 2 * sizeof(State), hipHostMallocDefault) == hipSuccess &&
               hipEventCreateWithFlags(&c->sync_ev[0], hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&c->sync_ev[1], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         modap_destroy(c);
         return MODAP_E_NOMEM;
     }
-    Ctrl z{};
-    z.v_idx = -1;
-    z.step_limit = INT64_MAX;
-    EvalOut ez{};
-    if (hipMemcpy(c->ctl, &z, sizeof z, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->eval, &ez, sizeof ez, hipMemcpyHostToDevice) != hipSuccess) {
+    hipLaunchKernelGGL(ctl_init, dim3(1), dim3(64), 0, c->stream, c->ctl);
+    if (hipPeekAtLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipGetLastError();
         modap_destroy(c);
         return MODAP_E_DEVICE;
     }
@@ -484,22 +627,21 @@ modap_status modap_create(int device, void *hip_stream, modap_ctx **out) {
 void modap_destroy(modap_ctx *c) {
     if (!c) return;
     DeviceGuard g(c->device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     release_system(c);
     free_dev(c->part);
     free_dev(c->h_part);
     free_dev(c->dmax_part);
     free_dev(c->binf_part);
     free_dev(c->ctl);
-    free_dev(c->eval);
+    free_dev(c->tot);
     free_dev(c->bad);
     free_dev(c->flag);
     free_dev(c->stage);
-    if (c->hctl) (void)hipHostFree(c->hctl);
+    if (c->hst) (void)hipHostFree(c->hst);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->sync_ev)
         if (e) (void)hipEventDestroy(e);
-    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
@@ -526,47 +668,53 @@ modap_status modap_set_system(modap_ctx *c, int64_t m, int64_t n, modap_dtype st
     const int64_t v = vec_elems(c->dt);
     c->ldA = (n + v - 1) / v * v;
     c->vpend_maybe = false;
+    c->jn = 0;
     const size_t abytes = (size_t)m * (size_t)c->ldA * c->es;
     HIP_TRY(c, hipMalloc(&c->A, abytes));
     HIP_TRY(c, hipMalloc(&c->b, sizeof(double) * m));
     HIP_TRY(c, hipMalloc(&c->nu, sizeof(double) * m));
-    HIP_TRY(c, hipMalloc(&c->x, sizeof(double) * n));
-    HIP_TRY(c, hipMalloc(&c->y, sizeof(double) * n));
-    HIP_TRY(c, hipMalloc(&c->vpend, sizeof(double) * n));
-    HIP_TRY(c, hipMalloc(&c->x_eval, sizeof(double) * n));
-    HIP_TRY(c, hipMalloc(&c->y_eval, sizeof(double) * n));
+    // x, y, the one-shot translation and the evaluation point are padded with
+    // zeros to ldA so that the sweep reads whole 16-byte vectors of them.
+    const size_t vbytes = sizeof(double) * (size_t)c->ldA;
+    HIP_TRY(c, hipMalloc(&c->x, vbytes));
+    HIP_TRY(c, hipMalloc(&c->y, vbytes));
+    HIP_TRY(c, hipMalloc(&c->vpend, vbytes));
+    HIP_TRY(c, hipMalloc(&c->x_eval, vbytes));
+    HIP_TRY(c, hipMalloc(&c->y_eval, vbytes));
+    const size_t wbytes = 2 * acc_size(c->dt) * (size_t)c->ldA;
+    HIP_TRY(c, hipMalloc(&c->work, wbytes));
+    HIP_TRY(c, hipMalloc(&c->work_eval, wbytes));
+    HIP_TRY(c, hipMemsetAsync(c->work, 0, wbytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->work_eval, 0, wbytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->x, 0, vbytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->x_eval, 0, vbytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->y_eval, 0, vbytes, c->stream));
     HIP_TRY(c, hipMalloc(&c->r_eval, sizeof(double) * m));
-    HIP_TRY(c, hipMalloc(&c->ynorm_part, sizeof(double) * (size_t)((n + 63) / 64)));
+    HIP_TRY(c, hipMalloc(&c->ynp, sizeof(double) * (size_t)reduce_grid(c)));
     if (c->ldA != n) HIP_TRY(c, hipMemsetAsync(c->A, 0, abytes, c->stream));
     HIP_TRY(c, hipMemcpy2DAsync(c->A, (size_t)c->ldA * c->es, A, (size_t)lda * c->es, (size_t)n * c->es, (size_t)m,
                                 on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
     if ((st = to_device(c, c->b, b, sizeof(double) * m, on_dev))) return st;
-    if (x0) {
-        if ((st = to_device(c, c->x, x0, sizeof(double) * n, on_dev))) return st;
-    } else {
-        HIP_TRY(c, hipMemsetAsync(c->x, 0, sizeof(double) * n, c->stream));
-    }
-    HIP_TRY(c, hipMemsetAsync(c->y, 0, sizeof(double) * n, c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->vpend, 0, sizeof(double) * n, c->stream));
+    if (x0 && (st = to_device(c, c->x, x0, sizeof(double) * n, on_dev))) return st;
+    HIP_TRY(c, hipMemsetAsync(c->y, 0, vbytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->vpend, 0, vbytes, c->stream));
     const unsigned long long none = ULLONG_MAX;
     HIP_TRY(c, hipMemcpyAsync(c->bad, &none, sizeof none, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
     const int nb = (int)((m + 3) / 4);
     switch (c->dt) {
-        case 0: hipLaunchKernelGGL(row_norms<0>, dim3(nb), dim3(256), 0, c->stream, c->A, c->ldA, m, n, c->nu, c->bad); break;
-        case 1: hipLaunchKernelGGL(row_norms<1>, dim3(nb), dim3(256), 0, c->stream, c->A, c->ldA, m, n, c->nu, c->bad); break;
-        default: hipLaunchKernelGGL(row_norms<2>, dim3(nb), dim3(256), 0, c->stream, c->A, c->ldA, m, n, c->nu, c->bad); break;
+        case 0: hipLaunchKernelGGL(row_norms<0>, dim3(nb), dim3(256), 0, c->stream, (const void *)c->A, c->ldA, m, n, c->nu, c->bad); break;
+        case 1: hipLaunchKernelGGL(row_norms<1>, dim3(nb), dim3(256), 0, c->stream, (const void *)c->A, c->ldA, m, n, c->nu, c->bad); break;
+        default: hipLaunchKernelGGL(row_norms<2>, dim3(nb), dim3(256), 0, c->stream, (const void *)c->A, c->ldA, m, n, c->nu, c->bad); break;
     }
     LAUNCH_TRY(c, "row_norms launch");
     if (on_dev) {
-        hipLaunchKernelGGL(check_finite, dim3(64), dim3(256), 0, c->stream, c->b, m, c->flag);
-        hipLaunchKernelGGL(check_finite, dim3(64), dim3(256), 0, c->stream, c->x, n, c->flag);
+        hipLaunchKernelGGL(check_finite, dim3(64), dim3(256), 0, c->stream, (const double *)c->b, m, c->flag);
+        hipLaunchKernelGGL(check_finite, dim3(64), dim3(256), 0, c->stream, (const double *)c->x, n, c->flag);
         LAUNCH_TRY(c, "check_finite launch");
     }
-    Ctrl z{};
-    z.v_idx = -1;
-    z.step_limit = INT64_MAX;
-    HIP_TRY(c, hipMemcpyAsync(c->ctl, &z, sizeof z, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(ctl_init, dim3(1), dim3(64), 0, c->stream, c->ctl);
+    LAUNCH_TRY(c, "ctl_init launch");
     unsigned long long bad = 0;
     int flag = 0;
     HIP_TRY(c, hipMemcpyAsync(&bad, c->bad, sizeof bad, hipMemcpyDeviceToHost, c->stream));
@@ -581,11 +729,14 @@ modap_status modap_set_system(modap_ctx *c, int64_t m, int64_t n, modap_dtype st
         return fail(c, MODAP_E_ZERO_ROW, "row " + std::to_string(bad) + " is zero or not finite");
     }
     modap_tile t{};
+    bool ok = false;
     if (c->tile_forced) {
         t = c->tile;
         t.grid = 0;
+        ok = configure(c, t) == MODAP_OK;
     }
-    if (!c->tile_forced || configure(c, t) != MODAP_OK) {
+    if (!ok && cache_lookup(c, &t)) ok = configure(c, t) == MODAP_OK;
+    if (!ok) {
         if (!choose_shape(c->dt, c->ldA, &t)) {
             release_system(c);
             return fail(c, MODAP_E_INVAL, "rows too long for the one-pass sweep shapes");
@@ -609,9 +760,9 @@ modap_status modap_set_x(modap_ctx *c, const double *x, int on_dev) {
     if (x) {
         if ((st = to_device(c, c->x, x, sizeof(double) * c->n, on_dev))) return st;
     } else {
-        HIP_TRY(c, hipMemsetAsync(c->x, 0, sizeof(double) * c->n, c->stream));
+        HIP_TRY(c, hipMemsetAsync(c->x, 0, sizeof(double) * c->ldA, c->stream));
     }
-    hipLaunchKernelGGL(ctl_restart, dim3(1), dim3(64), 0, c->stream, c->ctl);
+    hipLaunchKernelGGL(ctl_restart, dim3(1), dim3(64), 0, c->stream, c->ctl, last_slot(c));
     LAUNCH_TRY(c, "ctl_restart launch");
     return MODAP_OK;
 }
@@ -673,16 +824,9 @@ modap_status modap_update_coeffs(modap_ctx *c, int64_t k, const int64_t *rows, c
         d_b = reinterpret_cast<const double *>(s + o3);
         d_v = v ? reinterpret_cast<const double *>(s + o4) : nullptr;
     }
-    if (k > 0) {
-        switch (c->dt) {
-            case 0: hipLaunchKernelGGL(scatter_rows<0>, dim3(k), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, d_rows, d_new, d_b, c->b, c->nu, c->ctl, c->vpend); break;
-            case 1: hipLaunchKernelGGL(scatter_rows<1>, dim3(k), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, d_rows, d_new, d_b, c->b, c->nu, c->ctl, c->vpend); break;
-            default: hipLaunchKernelGGL(scatter_rows<2>, dim3(k), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, d_rows, d_new, d_b, c->b, c->nu, c->ctl, c->vpend); break;
-        }
-        LAUNCH_TRY(c, "scatter_rows launch");
-    }
+    if (k > 0 && (st = launch_scatter(c, k, d_rows, d_new, d_b))) return st;
     if (d_v) {
-        hipLaunchKernelGGL(vpend_add, dim3(1), dim3(1024), 0, c->stream, c->ctl, c->vpend, d_v, c->n);
+        hipLaunchKernelGGL(vpend_add, dim3(1), dim3(1024), 0, c->stream, c->ctl, last_slot(c), c->vpend, d_v, c->n);
         LAUNCH_TRY(c, "vpend_add launch");
         c->vpend_maybe = true;
     }
@@ -699,8 +843,10 @@ modap_status modap_set_drift(modap_ctx *c, int64_t T, const double *V, int64_t l
             if (!all_finite(V + s * ldv, c->n)) return fail(c, MODAP_E_INVAL, "drift has a non-finite entry");
     }
     DeviceGuard g(c->device);
+    const int sl = last_slot(c);
     if (c->V) {
-        hipLaunchKernelGGL(sched_to_vpend, dim3(1), dim3(1024), 0, c->stream, c->ctl, c->vpend, c->V, c->n, c->n);
+        hipLaunchKernelGGL(sched_to_vpend, dim3(1), dim3(1024), 0, c->stream, c->ctl, sl, c->vpend,
+                           (const double *)c->V, c->ldA, c->n);
         LAUNCH_TRY(c, "sched_to_vpend launch");
         c->vpend_maybe = true;
     }
@@ -708,26 +854,29 @@ modap_status modap_set_drift(modap_ctx *c, int64_t T, const double *V, int64_t l
     free_dev(c->V);
     c->T = 0;
     if (T > 0 && V) {
-        HIP_TRY(c, hipMalloc(&c->V, sizeof(double) * (size_t)T * (size_t)c->n));
-        HIP_TRY(c, hipMemcpy2DAsync(c->V, sizeof(double) * c->n, V, sizeof(double) * ldv, sizeof(double) * c->n,
+        // rows padded with zeros to ldA, like x
+        const size_t vb = sizeof(double) * (size_t)T * (size_t)c->ldA;
+        HIP_TRY(c, hipMalloc(&c->V, vb));
+        HIP_TRY(c, hipMemsetAsync(c->V, 0, vb, c->stream));
+        HIP_TRY(c, hipMemcpy2DAsync(c->V, sizeof(double) * c->ldA, V, sizeof(double) * ldv, sizeof(double) * c->n,
                                     (size_t)T, on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
         c->T = T;
     }
-    hipLaunchKernelGGL(ctl_set_drift, dim3(1), dim3(64), 0, c->stream, c->ctl, c->T);
-    LAUNCH_TRY(c, "ctl_set_drift launch");
     if (on_dev && c->T > 0) {
         HIP_TRY(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
-        hipLaunchKernelGGL(check_finite, dim3(64), dim3(256), 0, c->stream, c->V, c->T * c->n, c->flag);
+        hipLaunchKernelGGL(check_finite, dim3(64), dim3(256), 0, c->stream, (const double *)c->V, c->T * c->ldA, c->flag);
         int flag = 0;
         HIP_TRY(c, hipMemcpyAsync(&flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         if (flag) {
             free_dev(c->V);
             c->T = 0;
-            hipLaunchKernelGGL(ctl_set_drift, dim3(1), dim3(64), 0, c->stream, c->ctl, (int64_t)0);
+            hipLaunchKernelGGL(ctl_set_drift, dim3(1), dim3(64), 0, c->stream, c->ctl, sl, (int64_t)0);
             return fail(c, MODAP_E_INVAL, "drift has a non-finite entry");
         }
     }
+    hipLaunchKernelGGL(ctl_set_drift, dim3(1), dim3(64), 0, c->stream, c->ctl, sl, c->T);
+    LAUNCH_TRY(c, "ctl_set_drift launch");
     return MODAP_OK;
 }
 
@@ -738,15 +887,17 @@ modap_status modap_iterate(modap_ctx *c, const modap_params *p, int64_t k, modap
     if (k < 0) return fail(c, MODAP_E_INVAL, "k < 0");
     DeviceGuard g(c->device);
     const auto t0 = std::chrono::steady_clock::now();
-    hipLaunchKernelGGL(ctl_begin, dim3(1), dim3(64), 0, c->stream, c->ctl, (int64_t)-1);
+    hipLaunchKernelGGL(ctl_begin, dim3(1), dim3(64), 0, c->stream, c->ctl, last_slot(c), (int64_t)-1);
     LAUNCH_TRY(c, "ctl_begin launch");
+    if ((st = enqueue_prime(c, c->work, c->x))) return st;
     size_t ev = 0;
     double bytes = 0.0;
+    const int track = p->track != 0;
     for (int64_t i = 0; i < k; ++i)
-        if ((st = enqueue_iteration(c, p, p->track != 0, &ev, &bytes))) return st;
+        if ((st = enqueue_iteration(c, p, track, i, &ev, &bytes))) return st;
     if (!out) return MODAP_OK;
-    Ctrl kc;
-    if ((st = read_ctl(c, &kc))) return st;
+    State kc;
+    if ((st = read_state(c, &kc))) return st;
     *out = modap_stats{};
     fill_stats(out, kc);
     out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -762,8 +913,9 @@ modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) 
     if ((st = check_params(c, p))) return st;
     DeviceGuard g(c->device);
     const auto t0 = std::chrono::steady_clock::now();
-    hipLaunchKernelGGL(ctl_begin, dim3(1), dim3(64), 0, c->stream, c->ctl, (int64_t)p->max_iters);
+    hipLaunchKernelGGL(ctl_begin, dim3(1), dim3(64), 0, c->stream, c->ctl, last_slot(c), (int64_t)p->max_iters);
     LAUNCH_TRY(c, "ctl_begin launch");
+    if ((st = enqueue_prime(c, c->work, c->x))) return st;
     const int64_t total = p->max_iters + 1;  // the last sweep checks the last step
     int64_t queued = 0, chunk = 1;
     int slot = 0, pending = -1;
@@ -774,13 +926,14 @@ modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) 
     while (queued < total && !done) {
         const int64_t cnt = std::min(chunk, total - queued);
         for (int64_t i = 0; i < cnt; ++i)
-            if ((st = enqueue_iteration(c, p, 0, &ev, &bytes))) return st;
+            if ((st = enqueue_iteration(c, p, 0, queued + i, &ev, &bytes))) return st;
         queued += cnt;
-        HIP_TRY(c, hipMemcpyAsync(&c->hctl[slot], c->ctl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(&c->hst[slot], &c->ctl->st[last_slot(c)], sizeof(State), hipMemcpyDeviceToHost,
+                                  c->stream));
         HIP_TRY(c, hipEventRecord(c->sync_ev[slot], c->stream));
         if (pending >= 0) {
             HIP_TRY(c, hipEventSynchronize(c->sync_ev[pending]));
-            if (c->hctl[pending].status != ST_RUNNING) {
+            if (c->hst[pending].status != ST_RUNNING) {
                 done = true;
                 observed = std::chrono::steady_clock::now();
             }
@@ -793,8 +946,8 @@ modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) 
         HIP_TRY(c, hipEventSynchronize(c->sync_ev[pending]));
         observed = std::chrono::steady_clock::now();
     }
-    Ctrl kc;
-    if ((st = read_ctl(c, &kc))) return st;
+    State kc;
+    if ((st = read_state(c, &kc))) return st;
     if (out) {
         *out = modap_stats{};
         fill_stats(out, kc);
@@ -814,27 +967,27 @@ modap_status modap_eval_sweep(modap_ctx *c, const double *x, double *r, double *
     if (!x || !y) return fail(c, MODAP_E_INVAL, "x and y are required");
     DeviceGuard g(c->device);
     if ((st = to_device(c, c->x_eval, x, sizeof(double) * c->n, on_dev))) return st;
+    if ((st = enqueue_prime(c, c->work_eval, c->x_eval))) return st;
     const bool hv = translation_possible(c);
     SweepArgs a = sweep_args(c);
     a.b_out = nullptr;
-    a.x = c->x_eval;
-    a.ystep = nullptr;
+    a.work = c->work_eval;
     a.check_status = 0;
+    a.j = c->jn;
     a.r_out = r ? c->r_eval : nullptr;
-    HIP_TRY(c, (hv ? c->kern_v : c->kern_nov)->launch(a, c->tile.grid, c->stream));
+    HIP_TRY(c, (hv ? c->kern_v : c->kern_nov)->launch(a, c->tile.grid, c->stream, nullptr, nullptr));
     ReduceArgs ra = reduce_args(c);
     ra.y = c->y_eval;
-    ra.x = nullptr;
     ra.ctl = nullptr;
-    ra.eval = c->eval;
+    ra.iterate = 0;
     if ((st = launch_reduce(c, ra))) return st;
-    EvalOut eo;
-    HIP_TRY(c, hipMemcpyAsync(&eo, c->eval, sizeof eo, hipMemcpyDeviceToHost, c->stream));
+    Totals to;
+    HIP_TRY(c, hipMemcpyAsync(&to, c->tot, sizeof to, hipMemcpyDeviceToHost, c->stream));
     if ((st = from_device(c, y, c->y_eval, sizeof(double) * c->n, on_dev))) return st;
     if (r && (st = from_device(c, r, c->r_eval, sizeof(double) * c->m, on_dev))) return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (h) *h = eo.h;
-    if (max_viol) *max_viol = eo.dmax;
+    if (h) *h = to.h;
+    if (max_viol) *max_viol = to.dmax;
     return MODAP_OK;
 }
 
@@ -842,29 +995,17 @@ modap_status modap_query(modap_ctx *c, double *x, double *b, modap_stats *out, i
     modap_status st = check_ctx(c, true);
     if (st) return st;
     DeviceGuard g(c->device);
-    if (x) {
-        hipLaunchKernelGGL(materialize_x, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, c->stream, c->ctl, c->x,
-                           c->y, c->n);
-        hipLaunchKernelGGL(ctl_clear_step, dim3(1), dim3(64), 0, c->stream, c->ctl);
-        LAUNCH_TRY(c, "materialize_x launch");
-        if ((st = from_device(c, x, c->x, sizeof(double) * c->n, on_dev))) return st;
-    }
+    const int sl = last_slot(c);
+    (void)sl;
+    if (x && (st = from_device(c, x, c->x, sizeof(double) * c->n, on_dev))) return st;
     if (b) {
         if (c->vpend_maybe || c->V) {
-            hipLaunchKernelGGL(sched_to_vpend, dim3(1), dim3(1024), 0, c->stream, c->ctl, c->vpend, c->V, c->n, c->n);
-            const int nb = (int)((c->m + 3) / 4);
-            switch (c->dt) {
-                case 0: hipLaunchKernelGGL(flush_translation<0>, dim3(nb), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, c->ctl, c->vpend, c->b); break;
-                case 1: hipLaunchKernelGGL(flush_translation<1>, dim3(nb), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, c->ctl, c->vpend, c->b); break;
-                default: hipLaunchKernelGGL(flush_translation<2>, dim3(nb), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, c->ctl, c->vpend, c->b); break;
-            }
-            hipLaunchKernelGGL(ctl_clear_vpend, dim3(1), dim3(64), 0, c->stream, c->ctl);
-            LAUNCH_TRY(c, "flush_translation launch");
+            if ((st = launch_flush(c))) return st;
         }
         if ((st = from_device(c, b, c->b, sizeof(double) * c->m, on_dev))) return st;
     }
-    Ctrl kc;
-    if ((st = read_ctl(c, &kc))) return st;
+    State kc;
+    if ((st = read_state(c, &kc))) return st;
     if (b) c->vpend_maybe = false;
     if (out) {
         *out = modap_stats{};
@@ -898,6 +1039,67 @@ modap_status modap_set_tile(modap_ctx *c, const modap_tile *t) {
         return fail(c, st, msg);
     }
     c->tile_forced = true;
+    return MODAP_OK;
+}
+
+modap_status modap_autotune(modap_ctx *c, int reps, modap_tile *best) {
+    modap_status st = check_ctx(c, true);
+    if (st) return st;
+    if (reps < 1) return fail(c, MODAP_E_INVAL, "reps < 1");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const modap_tile keep = c->tile;
+    const bool hv = translation_possible(c);
+    hipEvent_t e0 = event_at(c, 0), e1 = event_at(c, 1);
+    if (!e0 || !e1) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
+    if ((st = enqueue_prime(c, c->work_eval, c->x))) return st;
+    int cnt = 0;
+    const SweepKernel *tab = kernels_for(c->dt, &cnt);
+    modap_tile win = keep;
+    float win_ms = 1e30f;
+    std::vector<float> times;
+    for (int i = 0; i < cnt; ++i) {
+        if (tab[i].has_v != hv) continue;
+        if (coverage(c->dt, tab[i].lpr, tab[i].chunks) < c->ldA) continue;
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tab[i].func, tab[i].block, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        for (int mult = 1; mult <= std::max(2, per_cu); ++mult) {
+            modap_tile t{0, tab[i].block, tab[i].lpr, tab[i].chunks, c->cu_count * mult, tab[i].rs};
+            if (mult > 1 && mult != per_cu && mult != 2) continue;
+            if (configure(c, t) != MODAP_OK) continue;
+            SweepArgs a = sweep_args(c);
+            a.b_out = nullptr;
+            a.work = c->work_eval;
+            a.check_status = 0;
+            a.j = c->jn;
+            const SweepKernel *k = hv ? c->kern_v : c->kern_nov;
+            HIP_TRY(c, k->launch(a, c->tile.grid, c->stream, nullptr, nullptr));  // warm-up
+            times.clear();
+            for (int r = 0; r < reps; ++r) {
+                HIP_TRY(c, k->launch(a, c->tile.grid, c->stream, e0, e1));
+                HIP_TRY(c, hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+                times.push_back(ms);
+            }
+            std::sort(times.begin(), times.end());
+            const float med = times[times.size() / 2];
+            if (med < win_ms) {
+                win_ms = med;
+                win = c->tile;
+            }
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    if ((st = configure(c, win))) {
+        (void)configure(c, keep);
+        return st;
+    }
+    c->tile_forced = true;
+    cache_store(c, c->tile);
+    if (best) *best = c->tile;
     return MODAP_OK;
 }
 

@@ -16,41 +16,55 @@ enum : int32_t {
     ST_BAD_ROW = 5,
 };
 
-// Device-resident control block of one context.  Every kernel of an
-// iteration reads it; only the last workgroup of the reduction writes it, so
-// the host never has to synchronise between iterations.
-struct alignas(128) Ctrl {
-    int32_t status;       // ST_*
-    int32_t vpend_valid;  // a one-shot translation waits in vpend
-    int64_t steps;        // steps taken
+// The iteration state after one feasibility check and its decision.
+struct alignas(16) State {
     int64_t sweeps;       // checks done
-    int64_t step_limit;   // no step is taken once steps reaches this
-    int64_t v_idx;        // drift schedule row applied by the next sweep (-1: none)
-    int64_t sched_pos;    // next drift schedule row
-    int64_t sched_len;    // rows in the drift schedule
-    double s;             // pending step: the next sweep works at x - s*y
-    double dmax;          // last check
-    double binf;
-    double ynorm;
-    double eps_abs;
-    int64_t h;
-    uint32_t ticket;      // last-workgroup election in the reduction
-    int32_t feasible;     // the last check found x eps-feasible
-    int64_t pad1[2];
+    int64_t steps;        // steps taken
+    int64_t sched_pos;    // next drift-schedule row
+    int64_t v_idx;        // drift-schedule row applied by the next sweep (-1: none)
+    double s;             // step scale of the last step (x <- x - s*y)
+    double dmax;          // last check: max_i max(r_i,0)/||a_i||
+    double binf;          // last check: max_i |b_i|
+    double ynorm;         // last check: ||y||
+    double eps_abs;       // last check: threshold applied
+    int64_t h;            // last check: violated rows
+    int32_t status;       // ST_*
+    int32_t feasible;     // last check found x eps-feasible
+    int32_t vpend_valid;  // a one-shot translation waits for the next sweep
+    int32_t pad;
 };
 
-// Per-sweep outputs of a stateless evaluation.
-struct alignas(64) EvalOut {
+// Device-resident control block of one context.  The state after iteration
+// j lives in slot j & 1: the stage kernel of iteration j reads slot (j-1)&1
+// and writes slot j&1, and kernel boundaries order every write before its
+// readers, so no device-wide fence is needed anywhere.
+struct alignas(128) Ctrl {
+    State st[2];
+    int64_t step_limit;   // no step is taken once steps reaches this (set per call)
+    int64_t sched_len;    // rows in the drift schedule
+    int64_t pad[14];
+};
+
+// Totals of the sweep's per-workgroup scalars, formed by the reduction.
+struct alignas(32) Totals {
     int64_t h;
     double dmax;
     double binf;
-    double ynorm;
-    uint32_t ticket;
-    uint32_t pad;
+    double pad;
+};
+
+// Parameters of the decision taken after every check.
+struct Decide {
+    double lambda;
+    double eps;
+    int32_t eps_relative;
+    int32_t rule;         // 0 fixed length (eq. 12), 1 relaxed average (Alg. 1)
+    int32_t track;        // an eps-feasible check does not stop the iteration
+    int32_t pad;
 };
 
 // Storage traits: 16-byte vector loads of VEC elements; Acc = dot-product
-// accumulator; X = register copy of x and v.
+// accumulator and the type of the working vectors x and v of a sweep.
 template <int DT> struct Store;
 template <> struct Store<0> {  // IEEE binary64
     using T = double;
@@ -75,13 +89,10 @@ struct SweepArgs {
     const double *b_in;     // [m]
     double *b_out;          // [m] or null; written (may alias b_in) only when a translation applies
     const double *nu;       // [m] ||a_i||^2
-    const double *x;        // [n]
-    const double *ystep;    // [n] or null: the sweep works at x - ctl->s * ystep
-    const double *vpend;    // [n] one-shot translation, used when ctl->vpend_valid
-    const double *V;        // drift schedule [T x ldV] or null; row ctl->v_idx when >= 0
-    int64_t ldV;
-    const Ctrl *ctl;
-    int32_t check_status;   // 1: do nothing unless ctl->status == ST_RUNNING
+    const void *work;       // [2 x ldA] Acc: the working point x and the translation v
+    const Ctrl *ctl;        // state slot (j-1)&1: whether to run, whether v applies
+    int64_t j;
+    int32_t check_status;   // 1: do nothing unless the state is ST_RUNNING
     int32_t pad;
     double *r_out;          // [m] or null
     void *part;             // [grid x ldPart] Acc partial sums of y
@@ -98,22 +109,38 @@ struct ReduceArgs {
     int32_t G;
     int32_t acc_f64;
     int64_t n;
-    double *y;              // [n] out (iteration mode: also the previous y, read first)
-    double *x;              // [n] iteration mode: x <- x - s*y_prev (materialise the pending step)
-    Ctrl *ctl;              // iteration mode when non-null
-    EvalOut *eval;          // evaluation mode when ctl is null
+    double *y;              // [n] out
+    const Ctrl *ctl;        // iteration mode: state slot (j-1)&1 (skip when stopped)
+    int64_t j;
+    int32_t iterate;
+    int32_t pad;
     const int64_t *h_part;
     const double *dmax_part;
     const double *binf_part;
-    double *ynorm_part;     // [gridDim.x]
-    double lambda, eps;
-    int32_t eps_relative;
-    int32_t rule;           // 0 fixed length (eq. 12), 1 relaxed average (Alg. 1)
-    int32_t track;          // an eps-feasible check does not stop the iteration
-    int32_t pad;
+    Totals *tot;            // out (workgroup 0)
+    double *ynp;            // out [gridDim.x]
 };
 
-// x - s*y with one rounding, so every kernel forms the same value.
+struct StageArgs {
+    Ctrl *ctl;
+    int64_t j;              // iteration whose check is settled (stage) / next iteration (prime)
+    const Totals *tot;
+    const double *ynp;
+    int32_t R;
+    int32_t pad;
+    Decide dp;
+    double *x;              // [ldA] FP64 approximation (stage: x <- x - s*y)
+    const double *y;        // [ldA]
+    const double *vpend;    // [ldA] one-shot translation
+    const double *V;        // drift schedule [T x ldV] or null
+    int64_t ldV;
+    int64_t n, ldA;
+    void *work;             // out [2 x ldA] Acc
+};
+
+__device__ __forceinline__ int slot_of(int64_t j) { return (int)(j & 1); }
+
+// x - s*y with one rounding.
 __device__ __forceinline__ double step_point(double x, double s, double y) {
     return __fma_rn(-s, y, x);
 }
@@ -128,6 +155,56 @@ __device__ __forceinline__ T wave_sum(T v) {
 // NaN-propagating maximum (fmax would drop a NaN).
 __device__ __forceinline__ double max_nan(double a, double b) {
     return (b > a || b != b) ? b : a;
+}
+
+// ||y|| from its per-workgroup parts, in a fixed order.  Called by a whole
+// wavefront; every lane returns the same value, in every workgroup.
+__device__ __forceinline__ double ynorm_of(const double *ynp, int R, int lane) {
+    double s = 0.0;
+    for (int r = lane; r < R; r += 64) s += ynp[r];
+    s = wave_sum(s);
+    return sqrt(s);
+}
+
+// The decision after a check (eq. 10 test, then eq. 12 or Algorithm 1 step).
+__device__ __forceinline__ State decide(const State &p, const Totals &t, double ynorm, const Decide &d,
+                                        int64_t step_limit, int64_t sched_len) {
+    State s = p;
+    if (p.status != ST_RUNNING) return s;
+    s.sweeps = p.sweeps + 1;
+    s.vpend_valid = 0;
+    s.dmax = t.dmax;
+    s.binf = t.binf;
+    s.h = t.h;
+    s.ynorm = ynorm;
+    s.eps_abs = d.eps_relative ? d.eps * t.binf : d.eps;
+    s.s = 0.0;
+    s.v_idx = -1;
+    s.feasible = t.dmax <= s.eps_abs;
+    if (s.feasible) {
+        if (d.track) {
+            if (p.sched_pos < sched_len) {
+                s.v_idx = p.sched_pos;
+                s.sched_pos = p.sched_pos + 1;
+            }
+        } else {
+            s.status = ST_CONVERGED;
+        }
+    } else if (!isfinite(t.dmax) || !isfinite(ynorm) || !isfinite(t.binf)) {
+        s.status = ST_NUMERIC;
+    } else if (p.steps >= step_limit) {
+        s.status = ST_LIMIT;
+    } else if (!(ynorm > 0.0) || t.h == 0) {
+        s.status = ST_NO_DIRECTION;
+    } else {
+        s.s = d.rule == 0 ? d.lambda / ynorm : d.lambda / (double)t.h;
+        s.steps = p.steps + 1;
+        if (p.sched_pos < sched_len) {
+            s.v_idx = p.sched_pos;
+            s.sched_pos = p.sched_pos + 1;
+        }
+    }
+    return s;
 }
 
 }  // namespace modap

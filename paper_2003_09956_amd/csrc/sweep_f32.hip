@@ -1,8 +1,12 @@
 // Fused sweep shapes for IEEE binary32 storage (16-byte vector = 4 elements).
+// Every shape listed compiles without register spills.
 #define MODAP_DT 1
-#define MODAP_SHAPES                                                                     \
-    MODAP_SHAPE(256, 64, 1), MODAP_SHAPE(256, 64, 2), MODAP_SHAPE(256, 64, 4),           \
-    MODAP_SHAPE(256, 256, 2), MODAP_SHAPE(256, 256, 4), MODAP_SHAPE(256, 256, 8),        \
-    MODAP_SHAPE(512, 512, 2), MODAP_SHAPE(512, 512, 4), MODAP_SHAPE(512, 512, 8),        \
-    MODAP_SHAPE(1024, 1024, 2)
+#define MODAP_SHAPES                                                                             \
+    MODAP_SHAPE(256, 64, 1, 1), MODAP_SHAPE(256, 64, 2, 1), MODAP_SHAPE(256, 64, 4, 1),          \
+    MODAP_SHAPE(256, 64, 1, 2), MODAP_SHAPE(256, 64, 2, 2), MODAP_SHAPE(256, 64, 4, 2),          \
+    MODAP_SHAPE(256, 256, 2, 1), MODAP_SHAPE(256, 256, 4, 1), MODAP_SHAPE(256, 256, 8, 1),       \
+    MODAP_SHAPE(256, 256, 2, 2), MODAP_SHAPE(256, 256, 4, 2), MODAP_SHAPE(256, 256, 2, 4),       \
+    MODAP_SHAPE(512, 512, 2, 1), MODAP_SHAPE(512, 512, 4, 1), MODAP_SHAPE(512, 512, 8, 1),       \
+    MODAP_SHAPE(512, 512, 2, 2), MODAP_SHAPE(512, 512, 4, 2), MODAP_SHAPE(512, 512, 2, 4),       \
+    MODAP_SHAPE(1024, 1024, 2, 1)
 #include "sweep_inst.inc"

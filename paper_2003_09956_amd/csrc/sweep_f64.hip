@@ -1,8 +1,11 @@
 // Fused sweep shapes for IEEE binary64 storage (16-byte vector = 2 elements).
+// Every shape listed compiles without register spills.
 #define MODAP_DT 0
-#define MODAP_SHAPES                                                                     \
-    MODAP_SHAPE(256, 64, 1), MODAP_SHAPE(256, 64, 2), MODAP_SHAPE(256, 64, 4),           \
-    MODAP_SHAPE(256, 256, 2), MODAP_SHAPE(256, 256, 4), MODAP_SHAPE(256, 256, 8),        \
-    MODAP_SHAPE(512, 512, 2), MODAP_SHAPE(512, 512, 4), MODAP_SHAPE(512, 512, 8),        \
-    MODAP_SHAPE(1024, 1024, 2), MODAP_SHAPE(1024, 1024, 4)
+#define MODAP_SHAPES                                                                             \
+    MODAP_SHAPE(256, 64, 1, 1), MODAP_SHAPE(256, 64, 2, 1), MODAP_SHAPE(256, 64, 4, 1),          \
+    MODAP_SHAPE(256, 64, 1, 2), MODAP_SHAPE(256, 64, 2, 2), MODAP_SHAPE(256, 64, 4, 2),          \
+    MODAP_SHAPE(256, 256, 2, 1), MODAP_SHAPE(256, 256, 4, 1), MODAP_SHAPE(256, 256, 8, 1),       \
+    MODAP_SHAPE(256, 256, 2, 2), MODAP_SHAPE(256, 256, 4, 2),                                    \
+    MODAP_SHAPE(512, 512, 2, 1), MODAP_SHAPE(512, 512, 4, 1), MODAP_SHAPE(512, 512, 8, 1),       \
+    MODAP_SHAPE(512, 512, 2, 2), MODAP_SHAPE(512, 512, 4, 2)
 #include "sweep_inst.inc"

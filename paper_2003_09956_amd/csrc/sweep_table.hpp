@@ -5,13 +5,16 @@
 
 namespace modap {
 
-using SweepLaunch = hipError_t (*)(const SweepArgs &, int grid, hipStream_t stream);
+// Launch on `stream`; when e0/e1 are given, they record the kernel's start
+// and end as part of its dispatch (no separate event packets).
+using SweepLaunch = hipError_t (*)(const SweepArgs &, int grid, hipStream_t stream, hipEvent_t e0, hipEvent_t e1);
 
 struct SweepKernel {
     int dt;
     int block;
     int lpr;
     int chunks;
+    int rs;
     bool has_v;
     SweepLaunch launch;
     const void *func;

@@ -9,22 +9,38 @@
 //   y   += (r_i/||a_i||^2) a_i   if r_i > 0   (while the row is still in registers)
 //   h   += [r_i > 0],  dmax = max r_i/||a_i||,  binf = max |b'_i|
 //
+// x and v come from the working vectors written once per iteration by the
+// stage kernel, in the accumulation type.
+//
 // Thread shape: LPR lanes (a multiple of the 64-wide wavefront) share a row;
-// a workgroup of BLOCK lanes works on BLOCK/LPR rows at a time.  Lane l of a
-// row group owns the columns c*LPR*VEC + l*VEC + [0, VEC) for chunk c < C, so
-// each wavefront load of a chunk is 64 contiguous 16-byte vectors (1 KiB).  The
-// lane's slices of x, v and of the partial y stay in registers for the whole
-// sweep; the next row's vectors are loaded while the current row is reduced.
-// Dot products are reduced across the wavefront with a butterfly (identical in
-// every lane) and across the wavefronts of a row group through LDS, in a fixed
-// order, so the result does not depend on timing.  Each workgroup owns a
-// contiguous band of rows and writes one partial y; a second kernel sums the
-// partials in a fixed order.
+// a workgroup of BLOCK lanes holds BLOCK/LPR row groups, and each row group
+// takes RS consecutive rows per step.  The row is cut into C chunks of LPR*VEC
+// columns; lane l owns VEC consecutive columns of every chunk, so each
+// wavefront load of a chunk is 64 contiguous 16-byte vectors (1 KiB).  The
+// chunks are visited in an order rotated by the workgroup index, so that the
+// workgroups do not all read the same part of the working vectors at once.
+// The lane's slices of x, v and of the partial y stay in registers for the
+// whole sweep; the next step's rows are loaded (non-temporally: A is read once
+// per sweep) while the current ones are reduced, so 2*RS rows per row group
+// are in flight.  Dot products are reduced across the wavefront with a
+// butterfly (the same value in every lane) and across the wavefronts of a row
+// group through LDS, in a fixed order, so results do not depend on timing.
+// Each workgroup owns a contiguous band of rows and writes one partial y; the
+// reduction kernel sums the partials in a fixed order.
 #pragma once
 
 #include "modap_device.hpp"
 
 namespace modap {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Rows of A are read exactly once per sweep: stream them past the caches
+// (non-temporal) so that the working vectors, b and the partials keep theirs.
+__device__ __forceinline__ uint4 load_stream(const char *p) {
+    const u32x4 t = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    return make_uint4(t.x, t.y, t.z, t.w);
+}
 
 template <int DT>
 __device__ __forceinline__ void unpack(const uint4 &u, typename Store<DT>::Acc (&o)[Store<DT>::VEC]);
@@ -54,7 +70,7 @@ __device__ __forceinline__ void unpack<2>(const uint4 &u, float (&o)[8]) {
     o[7] = __uint_as_float(u.w & 0xffff0000u);
 }
 
-template <int DT, int BLOCK, int LPR, int C, bool HAS_V>
+template <int DT, int BLOCK, int LPR, int C, int RS, bool HAS_V>
 __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
     using S = Store<DT>;
     using Acc = typename S::Acc;
@@ -64,129 +80,168 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
     constexpr int WPG = LPR / 64;     // wavefronts per row group
     constexpr int NW = BLOCK / 64;
     constexpr int CW = LPR * VEC;     // columns per chunk
+    constexpr int AV = 16 / (int)sizeof(Acc);  // working-vector elements per 16-byte load
     static_assert(LPR % 64 == 0 && BLOCK % LPR == 0, "row groups are whole wavefronts");
+    static_assert(VEC % AV == 0, "a lane's columns are whole 16-byte vectors of the working vectors");
 
-    const Ctrl *ctl = a.ctl;
-    if (a.check_status && ctl->status != ST_RUNNING) return;
+    const State &st = a.ctl->st[slot_of(a.j - 1)];
+    const int32_t status = st.status;
+    if (a.check_status && status != ST_RUNNING) return;
+    const bool apply_v = HAS_V && (st.vpend_valid || st.v_idx >= 0);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int grp = tid / LPR;
     const int gl = tid % LPR;
+    const int rot = (int)(blockIdx.x % C);
 
-    const double s = a.ystep ? ctl->s : 0.0;
-    const double *vp = nullptr;
-    const double *vs = nullptr;
-    if (HAS_V) {
-        if (a.vpend && ctl->vpend_valid) vp = a.vpend;
-        if (a.V && ctl->v_idx >= 0) vs = a.V + ctl->v_idx * a.ldV;
-    }
-    const bool apply_v = HAS_V && (vp != nullptr || vs != nullptr);
+    // first column of register chunk c (chunks visited in rotated order)
+    auto col_of = [&](int c) -> int64_t {
+        const int cc = c + rot < C ? c + rot : c + rot - C;
+        return (int64_t)cc * CW + gl * VEC;
+    };
 
-    // Stage this lane's slices of the working point x - s*y and of v.
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
+    const int64_t r1 = min(a.m, r0 + a.rows_per_block);
+    constexpr int ROWS_PER_STEP = NG * RS;
+    const int64_t nsteps = r1 > r0 ? (r1 - r0 + ROWS_PER_STEP - 1) / ROWS_PER_STEP : 0;
+    const char *Ab = reinterpret_cast<const char *>(a.A);
+    const int64_t row_bytes = a.ldA * (int64_t)sizeof(T);
+
+    auto row_of = [&](int64_t t, int q) -> int64_t { return r0 + (t * NG + grp) * RS + q; };
+    // Loads are issued unconditionally (addresses clamped into the row band and
+    // the padded row) so that no branch separates them; rows past the band
+    // and columns past the padded row are discarded afterwards.
+    auto load_rows = [&](uint4 (&buf)[RS][C], double (&bi)[RS], double (&nui)[RS], int64_t t) {
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+            const int64_t row = min(row_of(t, q), r1 - 1);
+            const char *rp = Ab + row * row_bytes;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                buf[q][c] = load_stream(rp + min(col_of(c), a.ldA - VEC) * (int64_t)sizeof(T));
+            bi[q] = a.b_in[row];
+            nui[q] = a.nu[row];
+        }
+    };
+    auto mask_cols = [&](uint4 (&buf)[RS][C]) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (col_of(c) >= a.ldA) {
+#pragma unroll
+                for (int q = 0; q < RS; ++q) buf[q][c] = make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+    };
+
+    // This lane's slices of the working point x and of v (padded with zeros
+    // to ldA), then the first rows.
     Acc xr[C][VEC];
     Acc vr[C][VEC];
     Acc yacc[C][VEC];
+    const Acc *wx = reinterpret_cast<const Acc *>(a.work);
+    const Acc *wv = wx + a.ldA;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
+        const int64_t col = min(col_of(c), a.ldA - VEC);
+#pragma unroll
+        for (int e = 0; e < VEC; e += AV) {
+            const uint4 ux = *reinterpret_cast<const uint4 *>(wx + col + e);
+            __builtin_memcpy(&xr[c][e], &ux, 16);
+            if (HAS_V) {
+                const uint4 uv = *reinterpret_cast<const uint4 *>(wv + col + e);
+                __builtin_memcpy(&vr[c][e], &uv, 16);
+            } else {
+#pragma unroll
+                for (int k = 0; k < AV; ++k) vr[c][e + k] = (Acc)0;
+            }
+        }
+    }
+    uint4 bufA[RS][C], bufB[RS][C];
+    double bA[RS], nA[RS], bB[RS], nB[RS];
+    if (nsteps > 0) load_rows(bufA, bA, nA, 0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const bool in = col_of(c) < a.ldA;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            const int64_t col = (int64_t)c * CW + gl * VEC + e;
-            double xv = 0.0, vv = 0.0;
-            if (col < a.n) {
-                xv = a.x[col];
-                if (s != 0.0) xv = step_point(xv, s, a.ystep[col]);
-                if (HAS_V) {
-                    if (vp) vv += vp[col];
-                    if (vs) vv += vs[col];
-                }
+            if (!in) {
+                xr[c][e] = (Acc)0;
+                vr[c][e] = (Acc)0;
             }
-            xr[c][e] = (Acc)xv;
-            vr[c][e] = (Acc)vv;
             yacc[c][e] = (Acc)0;
         }
     }
 
-    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
-    const int64_t r1 = min(a.m, r0 + a.rows_per_block);
-    const int64_t nsteps = r1 > r0 ? (r1 - r0 + NG - 1) / NG : 0;
-    const char *Ab = reinterpret_cast<const char *>(a.A);
-    const int64_t row_bytes = a.ldA * (int64_t)sizeof(T);
-
     int64_t h = 0;
     double dmax = 0.0, binf = 0.0;
+    __shared__ Acc red[2][NW][RS][2];
 
-    __shared__ Acc red[2][NW][2];
-
-    auto load_row = [&](uint4 (&buf)[C], double &bi, double &nui, int64_t row) {
-        if (row < r1) {
-            const char *rp = Ab + row * row_bytes;
+    auto process = [&](const uint4 (&buf)[RS][C], const double (&bi)[RS], const double (&nui)[RS], int64_t t) {
+        Acc dot[RS], tdot[RS];
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+            dot[q] = (Acc)0;
+            tdot[q] = (Acc)0;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                const int64_t col = (int64_t)c * CW + gl * VEC;
-                if (col < a.ldA)
-                    buf[c] = *reinterpret_cast<const uint4 *>(rp + col * (int64_t)sizeof(T));
-                else
-                    buf[c] = make_uint4(0u, 0u, 0u, 0u);
-            }
-            bi = a.b_in[row];
-            nui = a.nu[row];
-        } else {
+                Acc av[VEC];
+                unpack<DT>(buf[q][c], av);
 #pragma unroll
-            for (int c = 0; c < C; ++c) buf[c] = make_uint4(0u, 0u, 0u, 0u);
-            bi = 0.0;
-            nui = 1.0;
-        }
-    };
-
-    auto process = [&](const uint4 (&buf)[C], double bi, double nui, int64_t row, int64_t t) {
-        Acc dot = (Acc)0, tdot = (Acc)0;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            Acc av[VEC];
-            unpack<DT>(buf[c], av);
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                dot = fma(xr[c][e], av[e], dot);
-                if (HAS_V) tdot = fma(vr[c][e], av[e], tdot);
+                for (int e = 0; e < VEC; ++e) {
+                    dot[q] = fma(xr[c][e], av[e], dot[q]);
+                    if (HAS_V) tdot[q] = fma(vr[c][e], av[e], tdot[q]);
+                }
             }
         }
-        dot = wave_sum(dot);
-        if (HAS_V) tdot = wave_sum(tdot);
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+            dot[q] = wave_sum(dot[q]);
+            if (HAS_V) tdot[q] = wave_sum(tdot[q]);
+        }
         if (WPG > 1) {
             const int pp = (int)(t & 1);
             if (lane == 0) {
-                red[pp][wave][0] = dot;
-                red[pp][wave][1] = tdot;
+#pragma unroll
+                for (int q = 0; q < RS; ++q) {
+                    red[pp][wave][q][0] = dot[q];
+                    red[pp][wave][q][1] = tdot[q];
+                }
             }
             __syncthreads();
-            Acc d = (Acc)0, td = (Acc)0;
 #pragma unroll
-            for (int w = 0; w < WPG; ++w) {
-                d += red[pp][grp * WPG + w][0];
-                if (HAS_V) td += red[pp][grp * WPG + w][1];
+            for (int q = 0; q < RS; ++q) {
+                Acc d = (Acc)0, td = (Acc)0;
+#pragma unroll
+                for (int w = 0; w < WPG; ++w) {
+                    d += red[pp][grp * WPG + w][q][0];
+                    if (HAS_V) td += red[pp][grp * WPG + w][q][1];
+                }
+                dot[q] = d;
+                tdot[q] = td;
             }
-            dot = d;
-            tdot = td;
         }
-        if (row < r1) {
-            double bb = bi;
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+            const int64_t row = row_of(t, q);
+            if (row >= r1) continue;
+            double bb = bi[q];
             if (apply_v) {
-                bb += (double)tdot;
+                bb += (double)tdot[q];
                 if (a.b_out && gl == 0) a.b_out[row] = bb;
             }
-            const double r = (double)dot - bb;
+            const double r = (double)dot[q] - bb;
             if (a.r_out && gl == 0) a.r_out[row] = r;
             binf = max_nan(binf, fabs(bb));
             if (r > 0.0) {
                 ++h;
-                dmax = max_nan(dmax, r / sqrt(nui));
-                const Acc w = (Acc)(r / nui);
+                dmax = max_nan(dmax, r / sqrt(nui[q]));
+                const Acc w = (Acc)(r / nui[q]);
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     Acc av[VEC];
-                    unpack<DT>(buf[c], av);
+                    unpack<DT>(buf[q][c], av);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) yacc[c][e] = fma(w, av[e], yacc[c][e]);
                 }
@@ -196,33 +251,36 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
         }
     };
 
-    uint4 bufA[C], bufB[C];
-    double bA = 0.0, nA = 1.0, bB = 0.0, nB = 1.0;
-    if (nsteps > 0) load_row(bufA, bA, nA, r0 + grp);
     for (int64_t t = 0; t < nsteps; t += 2) {
-        const int64_t rowA = r0 + grp + t * NG;
-        if (t + 1 < nsteps) load_row(bufB, bB, nB, rowA + NG);
-        process(bufA, bA, nA, rowA, t);
+        if (t + 1 < nsteps) load_rows(bufB, bB, nB, t + 1);
+        mask_cols(bufA);
+        process(bufA, bA, nA, t);
         if (t + 1 < nsteps) {
-            if (t + 2 < nsteps) load_row(bufA, bA, nA, rowA + 2 * NG);
-            process(bufB, bB, nB, rowA + NG, t + 1);
+            if (t + 2 < nsteps) load_rows(bufA, bA, nA, t + 2);
+            mask_cols(bufB);
+            process(bufB, bB, nB, t + 1);
         }
     }
 
-    // Partial y of this workgroup.
+    // Partial y of this workgroup (the chunk columns past ldA are zero in
+    // yacc and lie inside the covered width ldPart).
     Acc *part = reinterpret_cast<Acc *>(a.part) + (int64_t)blockIdx.x * a.ldPart;
     if (NG == 1) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) part[(int64_t)c * CW + gl * VEC + e] = yacc[c][e];
+            for (int e = 0; e < VEC; e += AV) {
+                uint4 w;
+                __builtin_memcpy(&w, &yacc[c][e], 16);
+                *reinterpret_cast<uint4 *>(part + col_of(c) + e) = w;
+            }
         }
     } else {
         __shared__ Acc ysh[NG][C * CW];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) ysh[grp][c * CW + gl * VEC + e] = yacc[c][e];
+            for (int e = 0; e < VEC; ++e) ysh[grp][col_of(c) + e] = yacc[c][e];
         }
         __syncthreads();
         for (int col = tid; col < C * CW; col += BLOCK) {

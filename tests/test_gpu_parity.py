@@ -55,12 +55,17 @@ def test_eval_sweep_matches_oracle(P, dtype, n, m):
 
 
 ALL_SHAPES = {
-    "f64": [(256, 64, 1), (256, 64, 2), (256, 64, 4), (256, 256, 2), (256, 256, 4), (256, 256, 8),
-            (512, 512, 2), (512, 512, 4), (512, 512, 8), (1024, 1024, 2), (1024, 1024, 4)],
-    "f32": [(256, 64, 1), (256, 64, 2), (256, 64, 4), (256, 256, 2), (256, 256, 4), (256, 256, 8),
-            (512, 512, 2), (512, 512, 4), (512, 512, 8), (1024, 1024, 2)],
-    "bf16": [(256, 64, 1), (256, 64, 2), (256, 64, 4), (256, 256, 2), (256, 256, 4),
-             (512, 512, 2), (512, 512, 4), (1024, 1024, 2), (1024, 1024, 4)],
+    "f64": [(256, 64, 1, 1), (256, 64, 2, 1), (256, 64, 4, 1), (256, 64, 1, 2), (256, 64, 2, 2),
+            (256, 64, 4, 2), (256, 256, 2, 1), (256, 256, 4, 1), (256, 256, 8, 1), (256, 256, 2, 2),
+            (256, 256, 4, 2), (512, 512, 2, 1), (512, 512, 4, 1), (512, 512, 8, 1), (512, 512, 2, 2),
+            (512, 512, 4, 2)],
+    "f32": [(256, 64, 1, 1), (256, 64, 2, 1), (256, 64, 4, 1), (256, 64, 1, 2), (256, 64, 2, 2),
+            (256, 64, 4, 2), (256, 256, 2, 1), (256, 256, 4, 1), (256, 256, 8, 1), (256, 256, 2, 2),
+            (256, 256, 4, 2), (256, 256, 2, 4), (512, 512, 2, 1), (512, 512, 4, 1), (512, 512, 8, 1),
+            (512, 512, 2, 2), (512, 512, 4, 2), (512, 512, 2, 4), (1024, 1024, 2, 1)],
+    "bf16": [(256, 64, 1, 1), (256, 64, 2, 1), (256, 64, 4, 1), (256, 64, 1, 2), (256, 64, 2, 2),
+             (256, 256, 2, 1), (256, 256, 4, 1), (256, 256, 2, 2), (512, 512, 2, 1), (512, 512, 4, 1),
+             (512, 512, 2, 2)],
 }
 VEC = {"f64": 2, "f32": 4, "bf16": 8}
 
@@ -76,15 +81,15 @@ def test_every_kernel_shape_and_grid(P, dtype):
     ys = []
     with P.Solver() as s:
         s.set_system(sys_.A, sys_.b, dtype=dtype)
-        for (blk, lpr, ch) in ALL_SHAPES[dtype]:
+        for (blk, lpr, ch, rs) in ALL_SHAPES[dtype]:
             if lpr * VEC[dtype] * ch < n:
                 continue
             for grid in (0, 7):
-                say(f"shape dtype={dtype} block={blk} lpr={lpr} chunks={ch} grid={grid}")
-                s.set_tile(blk, lpr, ch, grid)
+                say(f"shape dtype={dtype} block={blk} lpr={lpr} chunks={ch} rows/step={rs} grid={grid}")
+                s.set_tile(blk, lpr, ch, grid, rs)
                 g = s.eval_sweep(x)
                 check_sweep(sys_.A, dtype, o, g.y, g.h, g.max_viol, g.r,
-                            label=f"{dtype} {blk}/{lpr}/{ch}/{grid}")
+                            label=f"{dtype} {blk}/{lpr}/{ch}/{rs}/{grid}")
                 ys.append(g.y)
     assert len(ys) >= 4
 
@@ -272,7 +277,7 @@ def test_translation_in_wavefront_row_shape(P):
     o = oracle.sweep(sys_.A, "f64", oracle.translate(sys_.A, "f64", sys_.b, v), x)
     with P.Solver() as s:
         s.set_system(sys_.A, sys_.b, dtype="f64")
-        for shape in [(256, 64, 2), (256, 64, 4), (256, 256, 2)]:
+        for shape in [(256, 64, 2, 0, 1), (256, 64, 4, 0, 2), (256, 256, 2, 0, 1)]:
             say(f"wave-shape translation {shape}")
             s.set_tile(*shape)
             s.update_coeffs(translate=v)
@@ -439,3 +444,32 @@ def test_device_pointers_and_profile(P):
         check_sweep(sys_.A, "f32", o, g.y.cpu().numpy(), g.h, g.max_viol, g.r.cpu().numpy())
         st = s.iterate(10, P.params(lam=0.1, eps=1e-12, profile=True))
         assert st.profiled == 10 and st.sweep_ms > 0 and st.reduce_ms > 0
+        st = s.iterate(10, P.params(lam=0.1, eps=1e-12, profile=3))
+        assert st.profiled == 4 and st.sweep_ms > 0
+
+
+def test_autotune_keeps_parity_and_caches(P, tmp_path, monkeypatch):
+    """The autotuner picks a compiled shape that covers the row, leaves the
+    state untouched, records it in the cache file, and set_system reuses it."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("MODAP_TUNE_CACHE", str(cache))
+    sys_ = W.gaussian(3000, 4000, seed=6, dtype="f32")
+    x = probe_point(sys_, 0.1, seed=6)
+    o = oracle.sweep(sys_.A, "f32", sys_.b, x)
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype="f32")
+        say("autotune")
+        best = s.autotune(3)
+        assert best["lanes_per_row"] * 4 * best["chunks"] >= 3000 and best["grid"] > 0
+        assert s.get_tile() == best
+        g = s.eval_sweep(x)
+        check_sweep(sys_.A, "f32", o, g.y, g.h, g.max_viol, g.r, label="autotuned")
+        _, _, st = s.query()
+        assert st.sweeps == 0 and st.iters == 0
+    line = cache.read_text().split()
+    assert [int(v) for v in line[:3]] == [1, 3000, 4000]
+    with P.Solver() as s2:
+        s2.set_system(sys_.A, sys_.b, dtype="f32")
+        t2 = s2.get_tile()
+        assert (t2["block"], t2["lanes_per_row"], t2["chunks"], t2["rows_per_step"], t2["grid"]) == \
+               (best["block"], best["lanes_per_row"], best["chunks"], best["rows_per_step"], best["grid"])
