@@ -39,7 +39,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 PROFILE_EVERY = 10      # one iteration in ten carries HIP events on its kernel dispatches
 METRIC = "pseudo-projection sweep HBM GB/s (% of peak); p50/p99 time-to-feasible"
-COUNTERS = os.path.join(ROOT, "profiles", "sweep_f32_n8192_m16384_counters.json")
 KERNEL_SOURCES = ["paper_2003_09956_amd/csrc/sweep_wide.hpp", "paper_2003_09956_amd/csrc/modap_device.hpp",
                   "paper_2003_09956_amd/csrc/sweep_f32.hip", "paper_2003_09956_amd/csrc/sweep_inst.inc"]
 
@@ -61,17 +60,25 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if xs else None
 
 
+def counters_path(tile: str) -> str:
+    """Committed rocprofv3 counter summary of the sweep at one tile
+    (block,lanes_per_row,chunks,rows_per_step,grid)."""
+    return os.path.join(ROOT, "profiles", f"sweep_wide_f32_n8192_m16384_tile{tile.replace(',', '-')}_counters.txt")
+
+
 def measured_traffic(tile):
-    """HBM bytes per sweep launch from committed rocprofv3 counters, if they were
-    taken on the current kernel source and shape (else None)."""
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of known size), if
+    one was taken on the current kernel source at this shape; else None."""
+    want = f"{tile['block']},{tile['lanes_per_row']},{tile['chunks']},{tile['rows_per_step']},{tile['grid']}"
     try:
-        with open(COUNTERS) as f:
-            c = json.load(f)
-    except (OSError, ValueError):
+        with open(counters_path(want)) as f:
+            kv = dict(l.split(" = ", 1) for l in f.read().splitlines() if " = " in l and not l.startswith("#"))
+    except OSError:
         return None
-    if c.get("source_hash") != kernel_source_hash() or c.get("tile") != tile:
+    if kv.get("source_hash") != kernel_source_hash() or kv.get("tile") != want:
         return None
-    return c.get("bytes_per_launch")
+    return int(float(kv["bytes_per_launch"]))
 
 
 def time_to_feasible(P, W, seeds):
@@ -117,6 +124,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttf", action="store_true", help="skip the time-to-feasible solves")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--tile", type=str, default=None,
+                    help="force the sweep shape block,lanes_per_row,chunks,rows_per_step,grid (skips the autotuner)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes five times (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -133,6 +144,15 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.copy_calibration:
+        nbytes = args.copy_calibration // 16 * 16
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "launches": 5}), flush=True)
+        return
     P.lib()
 
     K, WU = args.steps, args.warmup
@@ -146,10 +166,18 @@ def main():
     with P.Solver(0) as s:
         s.set_system(sys_.A, sys_.b, dtype="f32")
         s.set_drift(V)
-        tile = s.autotune(5)
-        log("tile (autotuned)", tile)
-        track = P.params(lam=lam, eps=eps, track=True)
-        s.iterate(WU, track)
+        if args.tile:
+            blk, lpr, ch, rs, grid = (int(v) for v in args.tile.split(","))
+            s.set_tile(blk, lpr, ch, grid, rs)
+            tile = s.get_tile()
+            log("tile (forced)", tile)
+        else:
+            tile = s.autotune(5)
+            log("tile (autotuned)", tile)
+        # the warm-up also profiles, as many iterations as the timed region
+        # will, so that the profiling events exist before the clock starts
+        n_prof = (K + PROFILE_EVERY - 1) // PROFILE_EVERY
+        s.iterate(WU, P.params(lam=lam, eps=eps, track=True, profile=max(1, WU // max(n_prof, 1))))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = s.iterate(K, P.params(lam=lam, eps=eps, track=True, profile=PROFILE_EVERY))

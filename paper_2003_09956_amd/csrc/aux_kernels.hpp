@@ -115,7 +115,7 @@ __global__ __launch_bounds__(1024) void reduce_y(const ReduceArgs a) {
     const int wv = tid >> 6;
     int64_t h = 0;
     double dm = 0.0, bm = 0.0;
-    for (int g = tid; g < a.G; g += 1024) {
+    for (int g = tid; g < a.Gs; g += 1024) {
         h += a.h_part[g];
         dm = max_nan(dm, a.dmax_part[g]);
         bm = max_nan(bm, a.binf_part[g]);

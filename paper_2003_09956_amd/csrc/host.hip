@@ -25,6 +25,7 @@
 
 #include "aux_kernels.hpp"
 #include "modap.h"
+#include "sweep_split.hpp"
 #include "modap_device.hpp"
 #include "sweep_table.hpp"
 
@@ -52,6 +53,14 @@ struct modap_ctx {
     modap_tile tile{};
     bool tile_forced = false;
     const SweepKernel *kern_nov = nullptr, *kern_v = nullptr;
+    // split-row two-phase form (tile kind 1)
+    const SplitKernels *skern = nullptr;
+    int ntiles = 0;
+    int64_t rows_per_band = 0;
+    int finish_blocks = 0;
+    void *pdot = nullptr;
+    size_t pdot_bytes = 0;
+    double *wrow = nullptr;
     int64_t rows_per_block = 0;
     int64_t ldPart = 0;
     void *part = nullptr;
@@ -147,6 +156,16 @@ const SweepKernel *find_kernel(int dt, int block, int lpr, int chunks, int rs, b
 
 int64_t coverage(int dt, int lpr, int chunks) { return (int64_t)lpr * vec_elems(dt) * chunks; }
 
+const SplitKernels *split_for(int dt) {
+    switch (dt) {
+        case 0: return split_kernels_0();
+        case 1: return split_kernels_1();
+        default: return split_kernels_2();
+    }
+}
+
+constexpr int64_t kMaxBandRows = 4096;  // rows per band of the split-row form (its row list)
+
 // Built-in choice of the fused sweep's shape: the smallest row coverage that
 // holds a padded row; among equal coverage, about 16 elements per lane, then
 // the larger workgroup, then two rows per step.
@@ -169,7 +188,16 @@ bool choose_shape(int dt, int64_t ldA, modap_tile *out) {
             best_score = score;
         }
     }
-    if (!best) return false;
+    if (!best) {
+        const SplitKernels *sk = split_for(dt);
+        out->kind = 1;
+        out->block = sk->block;
+        out->lanes_per_row = sk->block;
+        out->chunks = sk->chunks;
+        out->grid = 0;
+        out->rows_per_step = 1;
+        return true;
+    }
     out->kind = 0;
     out->block = best->block;
     out->lanes_per_row = best->lpr;
@@ -179,10 +207,67 @@ bool choose_shape(int dt, int64_t ldA, modap_tile *out) {
     return true;
 }
 
+modap_status ensure_scalar_parts(modap_ctx *c, int count) {
+    if (count <= c->part_grid) return MODAP_OK;
+    free_dev(c->h_part);
+    free_dev(c->dmax_part);
+    free_dev(c->binf_part);
+    HIP_TRY(c, hipMalloc(&c->h_part, sizeof(int64_t) * count));
+    HIP_TRY(c, hipMalloc(&c->dmax_part, sizeof(double) * count));
+    HIP_TRY(c, hipMalloc(&c->binf_part, sizeof(double) * count));
+    c->part_grid = count;
+    return MODAP_OK;
+}
+
+modap_status ensure_part(modap_ctx *c, size_t need) {
+    if (need <= c->part_bytes) return MODAP_OK;
+    free_dev(c->part);
+    HIP_TRY(c, hipMalloc(&c->part, need));
+    c->part_bytes = need;
+    return MODAP_OK;
+}
+
+// Split-row form: column tiles of 256*VEC*C columns, row bands of at most
+// kMaxBandRows rows; grid = number of row bands (0: about two workgroups per
+// compute unit over bands x tiles).
+modap_status configure_split(modap_ctx *c, modap_tile t) {
+    const SplitKernels *sk = split_for(c->dt);
+    if (t.block != sk->block || t.lanes_per_row != sk->block || t.chunks != sk->chunks)
+        return fail(c, MODAP_E_INVAL, "no compiled split-row kernel of that shape for this storage type");
+    const int64_t tw = (int64_t)sk->block * vec_elems(c->dt) * sk->chunks;
+    const int ntiles = (int)((c->ldA + tw - 1) / tw);
+    int64_t bands = t.grid > 0 ? t.grid : std::max<int64_t>(1, (2 * c->cu_count + ntiles - 1) / ntiles);
+    int64_t rpb = (c->m + bands - 1) / bands;
+    rpb = std::min(rpb, kMaxBandRows);
+    bands = (c->m + rpb - 1) / rpb;
+    const size_t acc = acc_size(c->dt);
+    modap_status st;
+    if ((st = ensure_part(c, (size_t)bands * (size_t)ntiles * (size_t)tw * acc))) return st;
+    const size_t pd = 2 * (size_t)ntiles * (size_t)c->m * acc;
+    if (pd > c->pdot_bytes) {
+        free_dev(c->pdot);
+        HIP_TRY(c, hipMalloc(&c->pdot, pd));
+        c->pdot_bytes = pd;
+    }
+    if (!c->wrow) HIP_TRY(c, hipMalloc(&c->wrow, sizeof(double) * (size_t)c->m));
+    c->finish_blocks = (int)((c->m + 255) / 256);
+    if ((st = ensure_scalar_parts(c, c->finish_blocks))) return st;
+    c->skern = sk;
+    c->ntiles = ntiles;
+    c->rows_per_band = rpb;
+    c->ldPart = (int64_t)ntiles * tw;
+    t.grid = (int)bands;
+    t.rows_per_step = 1;
+    c->tile = t;
+    c->kern_v = c->kern_nov = nullptr;
+    return MODAP_OK;
+}
+
 // Resolve the tile into kernels, grid and scratch.
 modap_status configure(modap_ctx *c, const modap_tile &want) {
     modap_tile t = want;
-    if (t.kind != 0) return fail(c, MODAP_E_INVAL, "only the one-pass sweep shape (kind 0) is built");
+    if (t.kind == 1) return configure_split(c, t);
+    if (t.kind != 0) return fail(c, MODAP_E_INVAL, "tile kind must be 0 (one pass) or 1 (split rows)");
     if (t.rows_per_step <= 0) t.rows_per_step = 1;
     const SweepKernel *kv = find_kernel(c->dt, t.block, t.lanes_per_row, t.chunks, t.rows_per_step, true);
     const SweepKernel *kn = find_kernel(c->dt, t.block, t.lanes_per_row, t.chunks, t.rows_per_step, false);
@@ -200,22 +285,11 @@ modap_status configure(modap_ctx *c, const modap_tile &want) {
     int64_t rpb = (c->m + grid - 1) / grid;
     rpb = ((rpb + per_step - 1) / per_step) * per_step;
     grid = (int)((c->m + rpb - 1) / rpb);
-    const size_t acc = c->dt == 0 ? 8 : 4;
-    const size_t need = (size_t)grid * (size_t)cov * acc;
-    if (need > c->part_bytes) {
-        free_dev(c->part);
-        HIP_TRY(c, hipMalloc(&c->part, need));
-        c->part_bytes = need;
-    }
-    if (grid > c->part_grid) {
-        free_dev(c->h_part);
-        free_dev(c->dmax_part);
-        free_dev(c->binf_part);
-        HIP_TRY(c, hipMalloc(&c->h_part, sizeof(int64_t) * grid));
-        HIP_TRY(c, hipMalloc(&c->dmax_part, sizeof(double) * grid));
-        HIP_TRY(c, hipMalloc(&c->binf_part, sizeof(double) * grid));
-        c->part_grid = grid;
-    }
+    const size_t acc = acc_size(c->dt);
+    modap_status st;
+    if ((st = ensure_part(c, (size_t)grid * (size_t)cov * acc))) return st;
+    if ((st = ensure_scalar_parts(c, grid))) return st;
+    c->skern = nullptr;
     c->kern_v = kv;
     c->kern_nov = kn;
     c->rows_per_block = rpb;
@@ -308,11 +382,48 @@ SweepArgs sweep_args(modap_ctx *c) {
     return a;
 }
 
+// Launch the sweep of the configured form (events: start/end of its kernels).
+modap_status launch_sweep(modap_ctx *c, const SweepArgs &a, bool hv, hipEvent_t e0, hipEvent_t e1) {
+    if (!c->skern) {
+        HIP_TRY(c, (hv ? c->kern_v : c->kern_nov)->launch(a, c->tile.grid, c->stream, e0, e1));
+        return MODAP_OK;
+    }
+    SplitArgs s{};
+    s.A = a.A;
+    s.ldA = a.ldA;
+    s.m = a.m;
+    s.n = a.n;
+    s.b_in = a.b_in;
+    s.b_out = a.b_out;
+    s.nu = a.nu;
+    s.work = a.work;
+    s.ctl = a.ctl;
+    s.j = a.j;
+    s.check_status = a.check_status;
+    s.ntiles = c->ntiles;
+    s.rows_per_band = c->rows_per_band;
+    s.pdot = c->pdot;
+    s.w = c->wrow;
+    s.r_out = a.r_out;
+    s.part = c->part;
+    s.ldPart = c->ldPart;
+    s.h_part = c->h_part;
+    s.dmax_part = c->dmax_part;
+    s.binf_part = c->binf_part;
+    if (e0) HIP_TRY(c, hipEventRecord(e0, c->stream));
+    HIP_TRY(c, c->skern->dot(s, c->tile.grid, c->ntiles, hv, c->stream));
+    HIP_TRY(c, c->skern->finish(s, c->finish_blocks, hv, c->stream));
+    HIP_TRY(c, c->skern->axpy(s, c->tile.grid, c->ntiles, c->stream));
+    if (e1) HIP_TRY(c, hipEventRecord(e1, c->stream));
+    return MODAP_OK;
+}
+
 ReduceArgs reduce_args(modap_ctx *c) {
     ReduceArgs r{};
     r.part = c->part;
     r.ldPart = c->ldPart;
     r.G = c->tile.grid;
+    r.Gs = c->skern ? c->finish_blocks : c->tile.grid;
     r.acc_f64 = c->dt == 0;
     r.n = c->n;
     r.h_part = c->h_part;
@@ -347,6 +458,16 @@ hipEvent_t event_at(modap_ctx *c, size_t i) {
         c->events.push_back(e);
     }
     return c->events[i];
+}
+
+// Create the events of `iters` queued iterations of which every `every`-th is
+// profiled, before any is queued: creating one while the device runs ahead
+// of the host would leave the device idle.
+modap_status reserve_events(modap_ctx *c, int64_t iters, int64_t every) {
+    if (every <= 0 || iters <= 0) return MODAP_OK;
+    const int64_t need = 4 * ((iters + every - 1) / every);
+    if (!event_at(c, (size_t)need - 1)) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
+    return MODAP_OK;
 }
 
 // Profiling: events 4i..4i+3 of iteration i mark the sweep's start and end
@@ -409,9 +530,8 @@ modap_status enqueue_iteration(modap_ctx *c, const modap_params *p, int track, i
     a.b_out = c->b;
     a.j = j;
     a.check_status = 1;
-    const SweepKernel *k = hv ? c->kern_v : c->kern_nov;
     modap_status st;
-    HIP_TRY(c, k->launch(a, c->tile.grid, c->stream, ev[0], ev[1]));
+    if ((st = launch_sweep(c, a, hv, ev[0], ev[1]))) return st;
     ReduceArgs r = reduce_args(c);
     r.y = c->y;
     r.ctl = c->ctl;
@@ -484,6 +604,7 @@ modap_status status_of(modap_ctx *c, const State &k, bool solve) {
 
 void release_system(modap_ctx *c) {
     free_dev(c->A);
+    free_dev(c->wrow);
     free_dev(c->b);
     free_dev(c->nu);
     free_dev(c->x);
@@ -630,6 +751,8 @@ void modap_destroy(modap_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     release_system(c);
     free_dev(c->part);
+    free_dev(c->pdot);
+    free_dev(c->wrow);
     free_dev(c->h_part);
     free_dev(c->dmax_part);
     free_dev(c->binf_part);
@@ -893,6 +1016,7 @@ modap_status modap_iterate(modap_ctx *c, const modap_params *p, int64_t k, modap
     size_t ev = 0;
     double bytes = 0.0;
     const int track = p->track != 0;
+    if ((st = reserve_events(c, k, p->profile))) return st;
     for (int64_t i = 0; i < k; ++i)
         if ((st = enqueue_iteration(c, p, track, i, &ev, &bytes))) return st;
     if (!out) return MODAP_OK;
@@ -917,6 +1041,7 @@ modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) 
     LAUNCH_TRY(c, "ctl_begin launch");
     if ((st = enqueue_prime(c, c->work, c->x))) return st;
     const int64_t total = p->max_iters + 1;  // the last sweep checks the last step
+    if ((st = reserve_events(c, std::min<int64_t>(total, 4096), p->profile))) return st;
     int64_t queued = 0, chunk = 1;
     int slot = 0, pending = -1;
     size_t ev = 0;
@@ -975,7 +1100,7 @@ modap_status modap_eval_sweep(modap_ctx *c, const double *x, double *r, double *
     a.check_status = 0;
     a.j = c->jn;
     a.r_out = r ? c->r_eval : nullptr;
-    HIP_TRY(c, (hv ? c->kern_v : c->kern_nov)->launch(a, c->tile.grid, c->stream, nullptr, nullptr));
+    if ((st = launch_sweep(c, a, hv, nullptr, nullptr))) return st;
     ReduceArgs ra = reduce_args(c);
     ra.y = c->y_eval;
     ra.ctl = nullptr;

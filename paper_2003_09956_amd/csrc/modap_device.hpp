@@ -106,8 +106,10 @@ struct SweepArgs {
 struct ReduceArgs {
     const void *part;       // [G x ldPart] Acc (float or double per acc_f64)
     int64_t ldPart;
-    int32_t G;
+    int32_t G;              // partial-y rows
     int32_t acc_f64;
+    int32_t Gs;             // per-workgroup scalar partials (h, dmax, binf)
+    int32_t pad0;
     int64_t n;
     double *y;              // [n] out
     const Ctrl *ctl;        // iteration mode: state slot (j-1)&1 (skip when stopped)

@@ -6,4 +6,6 @@
     MODAP_SHAPE(256, 64, 1, 2), MODAP_SHAPE(256, 64, 2, 2),                                      \
     MODAP_SHAPE(256, 256, 2, 1), MODAP_SHAPE(256, 256, 4, 1), MODAP_SHAPE(256, 256, 2, 2),       \
     MODAP_SHAPE(512, 512, 2, 1), MODAP_SHAPE(512, 512, 4, 1), MODAP_SHAPE(512, 512, 2, 2)
+// split-row form: 256 lanes x 4 chunks per column tile
+#define MODAP_SPLIT_C 4
 #include "sweep_inst.inc"

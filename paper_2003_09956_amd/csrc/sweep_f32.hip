@@ -9,4 +9,6 @@
     MODAP_SHAPE(512, 512, 2, 1), MODAP_SHAPE(512, 512, 4, 1), MODAP_SHAPE(512, 512, 8, 1),       \
     MODAP_SHAPE(512, 512, 2, 2), MODAP_SHAPE(512, 512, 4, 2), MODAP_SHAPE(512, 512, 2, 4),       \
     MODAP_SHAPE(1024, 1024, 2, 1)
+// split-row form: 256 lanes x 8 chunks per column tile
+#define MODAP_SPLIT_C 8
 #include "sweep_inst.inc"

@@ -8,4 +8,6 @@
     MODAP_SHAPE(256, 256, 2, 2), MODAP_SHAPE(256, 256, 4, 2),                                    \
     MODAP_SHAPE(512, 512, 2, 1), MODAP_SHAPE(512, 512, 4, 1), MODAP_SHAPE(512, 512, 8, 1),       \
     MODAP_SHAPE(512, 512, 2, 2), MODAP_SHAPE(512, 512, 4, 2)
+// split-row form: 256 lanes x 8 chunks per column tile
+#define MODAP_SPLIT_C 8
 #include "sweep_inst.inc"

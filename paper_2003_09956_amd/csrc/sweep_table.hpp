@@ -25,4 +25,19 @@ const SweepKernel *sweep_kernels_0(int *count);
 const SweepKernel *sweep_kernels_1(int *count);
 const SweepKernel *sweep_kernels_2(int *count);
 
+struct SplitArgs;
+// Split-row two-phase kernels of one storage type (workgroup of 256, C chunks
+// per column tile).
+struct SplitKernels {
+    int dt;
+    int block;
+    int chunks;
+    hipError_t (*dot)(const SplitArgs &, int bands, int tiles, bool has_v, hipStream_t);
+    hipError_t (*finish)(const SplitArgs &, int blocks, bool has_v, hipStream_t);
+    hipError_t (*axpy)(const SplitArgs &, int bands, int tiles, hipStream_t);
+};
+const SplitKernels *split_kernels_0();
+const SplitKernels *split_kernels_1();
+const SplitKernels *split_kernels_2();
+
 }  // namespace modap

@@ -35,14 +35,12 @@ def probe_point(sys_, scale, seed):
 
 
 SHAPES = [(1, 1), (2, 3), (5, 17), (63, 127), (64, 64), (65, 200), (256, 513), (1000, 700),
-          (2049, 300), (4096, 1100), (8192, 600), (12000, 257), (16384, 260)]
+          (2049, 300), (4096, 1100), (8192, 600), (12000, 257), (16384, 260), (16390, 70), (40001, 90)]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("n,m", SHAPES)
 def test_eval_sweep_matches_oracle(P, dtype, n, m):
-    if dtype == "f64" and n > 8192:
-        pytest.skip("FP64 rows beyond 8192 use the split-row form")
     say(f"eval_sweep dtype={dtype} n={n} m={m}")
     sys_ = W.gaussian(n, m, seed=n * 7 + m, dtype=dtype)
     x = probe_point(sys_, 2.0 / np.sqrt(n) + 0.05, seed=m)
@@ -473,3 +471,65 @@ def test_autotune_keeps_parity_and_caches(P, tmp_path, monkeypatch):
         t2 = s2.get_tile()
         assert (t2["block"], t2["lanes_per_row"], t2["chunks"], t2["rows_per_step"], t2["grid"]) == \
                (best["block"], best["lanes_per_row"], best["chunks"], best["rows_per_step"], best["grid"])
+
+
+SPLIT = {"f64": (256, 256, 8), "f32": (256, 256, 8), "bf16": (256, 256, 4)}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n,m,bands", [(300, 700, 0), (5000, 3000, 0), (9000, 5000, 3), (20000, 9000, 0)])
+def test_split_row_form_matches_oracle(P, dtype, n, m, bands):
+    """The two-phase split-row sweep (column tiles, then an AXPY over the
+    violated rows only), forced on any size, with a translation pending."""
+    sys_ = W.gaussian(n, m, seed=n + m, dtype=dtype)
+    v = np.random.default_rng(n).normal(scale=0.05, size=n)
+    x = probe_point(sys_, 1.0 / np.sqrt(n) + 0.02, seed=m)
+    o = oracle.sweep(sys_.A, dtype, oracle.translate(sys_.A, dtype, sys_.b, v), x)
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype=dtype)
+        blk, lpr, ch = SPLIT[dtype]
+        say(f"split dtype={dtype} n={n} m={m} bands={bands}")
+        s.set_tile(blk, lpr, ch, bands, 1, kind=1)
+        t = s.get_tile()
+        assert t["kind"] == 1 and t["grid"] >= 1
+        s.update_coeffs(translate=v)
+        g = s.eval_sweep(x)
+    check_sweep(sys_.A, dtype, o, g.y, g.h, g.max_viol, g.r, label=f"split {dtype} {n}x{m}")
+
+
+def test_split_row_form_is_chosen_for_long_rows(P):
+    """Rows longer than the one-pass shapes cover fall back to the split form."""
+    sys_ = W.gaussian(20000, 200, seed=3, dtype="f64")
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype="f64")
+        assert s.get_tile()["kind"] == 1
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_split_row_iteration_matches_oracle_steps(P, dtype):
+    """Steps and the drift schedule through the split-row form."""
+    n, m = 9000, 2000
+    sys_ = W.gaussian(n, m, seed=77, dtype=dtype)
+    V = W.drift(n, 10, sigma=1e-3, seed=77)
+    lam, tol = 0.3, TOL[dtype]
+    prm = P.params(lam=lam, eps=1e-9)
+    b = sys_.b.copy()
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, x0=sys_.z + 0.05, dtype=dtype)
+        blk, lpr, ch = SPLIT[dtype]
+        s.set_tile(blk, lpr, ch, 0, 1, kind=1)
+        s.set_drift(V)
+        x = sys_.z + 0.05
+        for k in range(5):
+            say(f"split step k={k} dtype={dtype}")
+            s.iterate(1, prm)
+            x1, _, st = s.query()
+            o = oracle.sweep(sys_.A, dtype, b, x)
+            assert o.h > 0
+            xo, status = oracle.step(o.y, o.h, 0, lam, x)
+            near = o.r > -tol * o.t
+            s_y = np.linalg.norm(weighted_abs_rows(sys_.A, dtype, np.where(near, o.t / o.nu, 0)))
+            bound = tol * (np.linalg.norm(x) + lam * s_y / np.linalg.norm(o.y))
+            assert np.linalg.norm(x1 - xo) <= bound, (k, np.linalg.norm(x1 - xo), bound)
+            b = oracle.translate(sys_.A, dtype, b, V[k])
+            x = x1
