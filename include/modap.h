@@ -97,8 +97,9 @@ typedef struct {
     double hbm_bytes;       /* algorithmic bytes of the sweeps launched in this call:
                                m*n*sizeof(A) + 16m (+ 8m when a translation is applied) each */
     double sweep_ms;        /* profile: summed duration of the sweep kernels of this call */
-    double reduce_ms;       /* profile: summed time from the start of each reduction of y to the
-                               end of the kernel that takes the stop decision and the step */
+    double reduce_ms;       /* profile: summed duration of the reductions of y (each also makes
+                               the previous step permanent in x); the stop decision and the
+                               step length are taken at the start of the next sweep */
     int64_t profiled;       /* profile: number of sweeps timed in this call */
 } modap_stats;
 

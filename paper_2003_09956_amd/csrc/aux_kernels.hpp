@@ -52,7 +52,9 @@ __global__ void check_finite(const double *p, int64_t count, int *flag) {
 // Column sums of the workgroup partials of y, in a fixed order, in FP64.
 // Workgroup b writes its share of ||y||^2 to ynp[b]; workgroup 0 also forms
 // the totals of h, dmax and binf.  The stop test and the step are taken from
-// these by the stage kernel.
+// these by the next sweep (or by the stage kernel at the end of a call).  In
+// iteration mode it first makes the previous step permanent in x and then
+// writes the working vectors of the next sweep.
 template <typename Acc>
 __global__ __launch_bounds__(1024) void reduce_y(const ReduceArgs a) {
     constexpr int COLS = 64;                    // columns per workgroup
@@ -61,13 +63,45 @@ __global__ __launch_bounds__(1024) void reduce_y(const ReduceArgs a) {
     constexpr int RPW = 64 / LPRR;              // partial rows per wavefront load
     constexpr int RG = 16 * RPW;                // row groups per workgroup
     constexpr int U = 8;                        // loads in flight per lane
-    if (a.iterate && a.ctl->st[slot_of(a.j - 1)].status != ST_RUNNING) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    const int wv = tid >> 6;
     const int rg = (tid >> 6) * RPW + lane / LPRR;
     const int cl = lane % LPRR;
+    const int64_t col = (int64_t)blockIdx.x * COLS + tid;   // column of threads 0..63
     // ldPart is a multiple of 64 and covers every workgroup's columns
     const Acc *pc = reinterpret_cast<const Acc *>(a.part) + (int64_t)blockIdx.x * COLS + cl * VW;
+
+    // Every load that does not depend on the state is issued before the state
+    // is examined: the first batch of partial rows, the column's x and
+    // previous y, and (workgroup 0) the first scalar partials.
+    uint4 v[U];
+    auto issue = [&](int g0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int g = min(g0 + u * RG, a.G - 1);
+            v[u] = *reinterpret_cast<const uint4 *>(pc + (int64_t)g * a.ldPart);
+        }
+    };
+    issue(rg);
+    const bool colw = a.work && tid < COLS && col < a.n;
+    double xo = 0.0, yo = 0.0;
+    if (colw) {
+        xo = a.x[col];
+        yo = a.y[col];
+    }
+    int64_t h = 0;
+    double dm = 0.0, bm = 0.0;
+    if (blockIdx.x == 0 && tid < a.Gs) {
+        h = a.h_part[tid];
+        dm = a.dmax_part[tid];
+        bm = a.binf_part[tid];
+    }
+    State S{};
+    if (a.iterate) {
+        S = a.ctl->st[slot_of(a.j - 1)];
+        if (S.status != ST_RUNNING) return;
+    }
 
     // Batches of U independent 16-byte loads (partial rows rg, rg+RG, ...),
     // each batch summed in order, batches in order: a fixed order for a given G.
@@ -75,12 +109,7 @@ __global__ __launch_bounds__(1024) void reduce_y(const ReduceArgs a) {
 #pragma unroll
     for (int k = 0; k < VW; ++k) acc[k] = 0.0;
     for (int g0 = rg; g0 < a.G; g0 += U * RG) {
-        uint4 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int g = min(g0 + u * RG, a.G - 1);
-            v[u] = *reinterpret_cast<const uint4 *>(pc + (int64_t)g * a.ldPart);
-        }
+        if (g0 != rg) issue(g0);
 #pragma unroll
         for (int k = 0; k < VW; ++k) {
             double bsum = 0.0;
@@ -98,12 +127,26 @@ __global__ __launch_bounds__(1024) void reduce_y(const ReduceArgs a) {
     for (int k = 0; k < VW; ++k) sh[rg][cl * VW + k] = acc[k];
     __syncthreads();
     if (tid < 64) {
-        const int64_t col = (int64_t)blockIdx.x * COLS + tid;
         double yv = 0.0;
 #pragma unroll 8
         for (int r = 0; r < RG; ++r) yv += sh[r][tid];
         double sq = 0.0;
         if (col < a.n) {
+            if (colw) {
+                // the step decided on the previous check becomes permanent in
+                // FP64, then the working vectors of the next sweep: x, the
+                // drift row due next (applied if the next decision moves on),
+                // and this sweep's y
+                if (a.apply_step && S.s != 0.0) {
+                    xo = step_point(xo, S.s, yo);
+                    a.x[col] = xo;
+                }
+                const bool due = a.V && S.sched_pos < a.ctl->sched_len;
+                Acc *w = reinterpret_cast<Acc *>(a.work);
+                w[col] = (Acc)xo;
+                w[a.ldA + col] = due ? (Acc)a.V[S.sched_pos * a.ldV + col] : (Acc)0;
+                w[2 * a.ldA + col] = (Acc)yv;
+            }
             a.y[col] = yv;
             sq = yv * yv;
         }
@@ -112,10 +155,7 @@ __global__ __launch_bounds__(1024) void reduce_y(const ReduceArgs a) {
     }
     if (blockIdx.x != 0) return;
 
-    const int wv = tid >> 6;
-    int64_t h = 0;
-    double dm = 0.0, bm = 0.0;
-    for (int g = tid; g < a.Gs; g += 1024) {
+    for (int g = tid + 1024; g < a.Gs; g += 1024) {
         h += a.h_part[g];
         dm = max_nan(dm, a.dmax_part[g]);
         bm = max_nan(bm, a.binf_part[g]);
@@ -144,12 +184,12 @@ __global__ __launch_bounds__(1024) void reduce_y(const ReduceArgs a) {
     *a.tot = t;
 }
 
-// Settle iteration j after its check: every workgroup takes the decision
-// from the check's totals (the same arithmetic in every workgroup),
-// workgroup 0 records it in slot j & 1, and each workgroup, for its columns,
-// makes the step permanent in FP64 (x <- x - s*y, eq. 12 or Algorithm 1) and
-// writes the working vectors of the next sweep in the accumulation type:
-// x, and the translation due before the next check (drift row v_idx).
+// End of a call: settle the last check j (no sweep follows to do it).  Every
+// workgroup takes the decision from the check's totals (the same arithmetic in
+// every workgroup), workgroup 0 records it in slot j & 1, and each workgroup,
+// for its columns, makes the step permanent in FP64 (x <- x - s*y, eq. 12 or
+// Algorithm 1) and writes x and the translation due next into the working
+// vectors.
 template <typename Acc>
 __global__ __launch_bounds__(256) void stage_iter(const StageArgs a) {
     const State p = a.ctl->st[slot_of(a.j - 1)];

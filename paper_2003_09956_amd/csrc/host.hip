@@ -70,7 +70,7 @@ struct modap_ctx {
     int part_grid = 0;
     double *ynp = nullptr;
     Totals *tot = nullptr;
-    void *work = nullptr;        // [2 x ldA] accumulation type: x and v of the next sweep
+    void *work = nullptr;        // [3 x ldA] accumulation type: x, v and y of the next sweep
     void *work_eval = nullptr;
 
     Ctrl *ctl = nullptr;
@@ -372,7 +372,12 @@ SweepArgs sweep_args(modap_ctx *c) {
     a.b_in = c->b;
     a.nu = c->nu;
     a.work = c->work;
-    a.ctl = c->ctl;
+    a.pd.ctl = c->ctl;
+    a.pd.j = c->jn;
+    a.pd.tot = c->tot;
+    a.pd.ynp = c->ynp;
+    a.pd.R = reduce_grid(c);
+    a.pd.decide = 0;
     a.part = c->part;
     a.ldPart = c->ldPart;
     a.h_part = c->h_part;
@@ -397,8 +402,7 @@ modap_status launch_sweep(modap_ctx *c, const SweepArgs &a, bool hv, hipEvent_t 
     s.b_out = a.b_out;
     s.nu = a.nu;
     s.work = a.work;
-    s.ctl = a.ctl;
-    s.j = a.j;
+    s.pd = a.pd;
     s.check_status = a.check_status;
     s.ntiles = c->ntiles;
     s.rows_per_band = c->rows_per_band;
@@ -426,6 +430,10 @@ ReduceArgs reduce_args(modap_ctx *c) {
     r.Gs = c->skern ? c->finish_blocks : c->tile.grid;
     r.acc_f64 = c->dt == 0;
     r.n = c->n;
+    r.ldA = c->ldA;
+    r.x = c->x;
+    r.V = c->V;
+    r.ldV = c->ldA;
     r.h_part = c->h_part;
     r.dmax_part = c->dmax_part;
     r.binf_part = c->binf_part;
@@ -434,13 +442,13 @@ ReduceArgs reduce_args(modap_ctx *c) {
     return r;
 }
 
-modap_status launch_reduce(modap_ctx *c, const ReduceArgs &r, hipEvent_t e0 = nullptr) {
-    if (e0) {
+modap_status launch_reduce(modap_ctx *c, const ReduceArgs &r, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+    if (e0 || e1) {
         ReduceArgs copy = r;
         void *args[] = {&copy};
         const void *f = r.acc_f64 ? reinterpret_cast<const void *>(&reduce_y<double>)
                                   : reinterpret_cast<const void *>(&reduce_y<float>);
-        HIP_TRY(c, hipExtLaunchKernel(f, dim3(reduce_grid(c)), dim3(1024), args, 0, c->stream, e0, nullptr, 0));
+        HIP_TRY(c, hipExtLaunchKernel(f, dim3(reduce_grid(c)), dim3(1024), args, 0, c->stream, e0, e1, 0));
         return MODAP_OK;
     }
     if (r.acc_f64)
@@ -471,8 +479,8 @@ modap_status reserve_events(modap_ctx *c, int64_t iters, int64_t every) {
 }
 
 // Profiling: events 4i..4i+3 of iteration i mark the sweep's start and end
-// and the reduction's start and the stage kernel's end, recorded by the
-// kernel dispatches themselves.
+// and the reduction's start and end, recorded by the kernel dispatches
+// themselves.
 bool profile_events(modap_ctx *c, size_t first, hipEvent_t (&e)[4]) {
     for (int k = 0; k < 4; ++k) {
         e[k] = event_at(c, first + k);
@@ -515,8 +523,10 @@ modap_status enqueue_prime(modap_ctx *c, void *work, const double *x) {
     return MODAP_OK;
 }
 
-// Queue one iteration: the sweep at the current x on the current data, the
-// reduction of y, and the stage kernel (decision, step, next working vectors).
+// Queue iteration i of a call: the sweep (which first settles the previous
+// check, except in the first iteration of a call) at the current x on the
+// current data, then the reduction of y (which makes the previous step
+// permanent in x and writes the next sweep's working vectors).
 modap_status enqueue_iteration(modap_ctx *c, const modap_params *p, int track, int64_t i, size_t *ev_used,
                                double *bytes) {
     const bool hv = translation_possible(c);
@@ -528,7 +538,9 @@ modap_status enqueue_iteration(modap_ctx *c, const modap_params *p, int track, i
     }
     SweepArgs a = sweep_args(c);
     a.b_out = c->b;
-    a.j = j;
+    a.pd.j = j;
+    a.pd.decide = i > 0;   // the first sweep of a call runs under the committed state
+    a.pd.dp = decide_params(p, track);
     a.check_status = 1;
     modap_status st;
     if ((st = launch_sweep(c, a, hv, ev[0], ev[1]))) return st;
@@ -537,21 +549,23 @@ modap_status enqueue_iteration(modap_ctx *c, const modap_params *p, int track, i
     r.ctl = c->ctl;
     r.j = j;
     r.iterate = 1;
-    if ((st = launch_reduce(c, r, ev[2]))) return st;
-    StageArgs g = stage_args(c, p, track, j);
-    const void *sf = c->dt == 0 ? reinterpret_cast<const void *>(&stage_iter<double>)
-                                : reinterpret_cast<const void *>(&stage_iter<float>);
-    if (ev[3]) {
-        void *args[] = {&g};
-        HIP_TRY(c, hipExtLaunchKernel(sf, dim3(stage_grid(c)), dim3(256), args, 0, c->stream, nullptr, ev[3], 0));
-    } else if (c->dt == 0) {
-        hipLaunchKernelGGL(stage_iter<double>, dim3(stage_grid(c)), dim3(256), 0, c->stream, (const StageArgs)g);
-    } else {
-        hipLaunchKernelGGL(stage_iter<float>, dim3(stage_grid(c)), dim3(256), 0, c->stream, (const StageArgs)g);
-    }
-    LAUNCH_TRY(c, "stage_iter launch");
+    r.apply_step = i > 0;
+    r.work = c->work;
+    if ((st = launch_reduce(c, r, ev[2], ev[3]))) return st;
     c->jn = j + 1;
     *bytes += sweep_bytes(c, hv);
+    return MODAP_OK;
+}
+
+// End of a call that queued iterations: settle the last check (decision,
+// step) with the stage kernel, so the committed state is in slot (jn-1)&1.
+modap_status enqueue_settle(modap_ctx *c, const modap_params *p, int track) {
+    StageArgs g = stage_args(c, p, track, c->jn - 1);
+    if (c->dt == 0)
+        hipLaunchKernelGGL(stage_iter<double>, dim3(stage_grid(c)), dim3(256), 0, c->stream, (const StageArgs)g);
+    else
+        hipLaunchKernelGGL(stage_iter<float>, dim3(stage_grid(c)), dim3(256), 0, c->stream, (const StageArgs)g);
+    LAUNCH_TRY(c, "stage_iter launch");
     return MODAP_OK;
 }
 
@@ -804,7 +818,7 @@ modap_status modap_set_system(modap_ctx *c, int64_t m, int64_t n, modap_dtype st
     HIP_TRY(c, hipMalloc(&c->vpend, vbytes));
     HIP_TRY(c, hipMalloc(&c->x_eval, vbytes));
     HIP_TRY(c, hipMalloc(&c->y_eval, vbytes));
-    const size_t wbytes = 2 * acc_size(c->dt) * (size_t)c->ldA;
+    const size_t wbytes = 3 * acc_size(c->dt) * (size_t)c->ldA;
     HIP_TRY(c, hipMalloc(&c->work, wbytes));
     HIP_TRY(c, hipMalloc(&c->work_eval, wbytes));
     HIP_TRY(c, hipMemsetAsync(c->work, 0, wbytes, c->stream));
@@ -1019,6 +1033,7 @@ modap_status modap_iterate(modap_ctx *c, const modap_params *p, int64_t k, modap
     if ((st = reserve_events(c, k, p->profile))) return st;
     for (int64_t i = 0; i < k; ++i)
         if ((st = enqueue_iteration(c, p, track, i, &ev, &bytes))) return st;
+    if (k > 0 && (st = enqueue_settle(c, p, track))) return st;
     if (!out) return MODAP_OK;
     State kc;
     if ((st = read_state(c, &kc))) return st;
@@ -1053,8 +1068,9 @@ modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) 
         for (int64_t i = 0; i < cnt; ++i)
             if ((st = enqueue_iteration(c, p, 0, queued + i, &ev, &bytes))) return st;
         queued += cnt;
-        HIP_TRY(c, hipMemcpyAsync(&c->hst[slot], &c->ctl->st[last_slot(c)], sizeof(State), hipMemcpyDeviceToHost,
-                                  c->stream));
+        // the newest settled state: the check before the last queued sweep
+        HIP_TRY(c, hipMemcpyAsync(&c->hst[slot], &c->ctl->st[slot_of(c->jn - 2)], sizeof(State),
+                                  hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipEventRecord(c->sync_ev[slot], c->stream));
         if (pending >= 0) {
             HIP_TRY(c, hipEventSynchronize(c->sync_ev[pending]));
@@ -1067,8 +1083,9 @@ modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) 
         slot ^= 1;
         chunk = std::min<int64_t>(chunk * 2, 64);
     }
+    if ((st = enqueue_settle(c, p, 0))) return st;
     if (!done) {
-        HIP_TRY(c, hipEventSynchronize(c->sync_ev[pending]));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
         observed = std::chrono::steady_clock::now();
     }
     State kc;
@@ -1098,7 +1115,6 @@ modap_status modap_eval_sweep(modap_ctx *c, const double *x, double *r, double *
     a.b_out = nullptr;
     a.work = c->work_eval;
     a.check_status = 0;
-    a.j = c->jn;
     a.r_out = r ? c->r_eval : nullptr;
     if ((st = launch_sweep(c, a, hv, nullptr, nullptr))) return st;
     ReduceArgs ra = reduce_args(c);
@@ -1198,7 +1214,6 @@ modap_status modap_autotune(modap_ctx *c, int reps, modap_tile *best) {
             a.b_out = nullptr;
             a.work = c->work_eval;
             a.check_status = 0;
-            a.j = c->jn;
             const SweepKernel *k = hv ? c->kern_v : c->kern_nov;
             HIP_TRY(c, k->launch(a, c->tile.grid, c->stream, nullptr, nullptr));  // warm-up
             times.clear();

@@ -34,10 +34,11 @@ struct alignas(16) State {
     int32_t pad;
 };
 
-// Device-resident control block of one context.  The state after iteration
-// j lives in slot j & 1: the stage kernel of iteration j reads slot (j-1)&1
-// and writes slot j&1, and kernel boundaries order every write before its
-// readers, so no device-wide fence is needed anywhere.
+// Device-resident control block of one context.  The state after the check
+// of sweep j (and the decision taken on it) lives in slot j & 1.  It is
+// written once, from slot (j-1)&1, by the first kernel of sweep j+1, or by the
+// stage kernel that ends a call; kernel boundaries order every write before
+// its readers, so no device-wide fence is needed anywhere.
 struct alignas(128) Ctrl {
     State st[2];
     int64_t step_limit;   // no step is taken once steps reaches this (set per call)
@@ -82,6 +83,21 @@ template <> struct Store<2> {  // bfloat16 bit patterns
     static constexpr int VEC = 8;
 };
 
+// What a sweep needs to settle the previous check before it runs: sweep j of
+// a call (all but the first) takes the decision of check j-1 itself, from the
+// state in slot (j-2)&1 and the totals and norm parts of reduction j-1, and
+// commits it to slot (j-1)&1.  Every workgroup takes the same decision from the
+// same data in the same order; one of them writes it.
+struct Pending {
+    Ctrl *ctl;
+    int64_t j;
+    const Totals *tot;
+    const double *ynp;
+    int32_t R;              // norm parts
+    int32_t decide;         // 0: slot (j-1)&1 already holds the state this sweep runs under
+    Decide dp;
+};
+
 struct SweepArgs {
     const void *A;          // [m x ldA] storage type, rows padded with zeros to ldA
     int64_t ldA;            // multiple of the 16-byte vector width
@@ -89,9 +105,8 @@ struct SweepArgs {
     const double *b_in;     // [m]
     double *b_out;          // [m] or null; written (may alias b_in) only when a translation applies
     const double *nu;       // [m] ||a_i||^2
-    const void *work;       // [2 x ldA] Acc: the working point x and the translation v
-    const Ctrl *ctl;        // state slot (j-1)&1: whether to run, whether v applies
-    int64_t j;
+    const void *work;       // [3 x ldA] Acc: the point x, the translation v, the direction y
+    Pending pd;             // the state this sweep runs under (whether to run, step, translation)
     int32_t check_status;   // 1: do nothing unless the state is ST_RUNNING
     int32_t pad;
     double *r_out;          // [m] or null
@@ -109,9 +124,9 @@ struct ReduceArgs {
     int32_t G;              // partial-y rows
     int32_t acc_f64;
     int32_t Gs;             // per-workgroup scalar partials (h, dmax, binf)
-    int32_t pad0;
-    int64_t n;
-    double *y;              // [n] out
+    int32_t apply_step;     // iteration mode: make the step of state (j-1)&1 permanent in x first
+    int64_t n, ldA;
+    double *y;              // [n] in: previous direction (apply_step), out: this sweep's
     const Ctrl *ctl;        // iteration mode: state slot (j-1)&1 (skip when stopped)
     int64_t j;
     int32_t iterate;
@@ -121,6 +136,10 @@ struct ReduceArgs {
     const double *binf_part;
     Totals *tot;            // out (workgroup 0)
     double *ynp;            // out [gridDim.x]
+    double *x;              // iteration mode: [n] FP64 approximation
+    void *work;             // iteration mode: out [3 x ldA] Acc x, drift row due next, y
+    const double *V;        // drift schedule [T x ldV] or null
+    int64_t ldV;
 };
 
 struct StageArgs {
@@ -140,7 +159,7 @@ struct StageArgs {
     void *work;             // out [2 x ldA] Acc
 };
 
-__device__ __forceinline__ int slot_of(int64_t j) { return (int)(j & 1); }
+__host__ __device__ __forceinline__ int slot_of(int64_t j) { return (int)(j & 1); }
 
 // x - s*y with one rounding.
 __device__ __forceinline__ double step_point(double x, double s, double y) {
@@ -206,6 +225,18 @@ __device__ __forceinline__ State decide(const State &p, const Totals &t, double 
             s.sched_pos = p.sched_pos + 1;
         }
     }
+    return s;
+}
+
+// The state that sweep pd.j runs under (see Pending).  Called by whole
+// wavefronts (the norm of y is summed across the wavefront); `writer` commits
+// a fresh decision.
+__device__ __forceinline__ State sweep_state(const Pending &pd, int lane, bool writer) {
+    if (!pd.decide) return pd.ctl->st[slot_of(pd.j - 1)];
+    const State p = pd.ctl->st[slot_of(pd.j - 2)];
+    const double yn = ynorm_of(pd.ynp, pd.R, lane);
+    const State s = decide(p, *pd.tot, yn, pd.dp, pd.ctl->step_limit, pd.ctl->sched_len);
+    if (writer) pd.ctl->st[slot_of(pd.j - 1)] = s;
     return s;
 }
 

@@ -30,9 +30,8 @@ struct SplitArgs {
     const double *b_in;
     double *b_out;
     const double *nu;
-    const void *work;        // [2 x ldA] Acc working vectors
-    const Ctrl *ctl;
-    int64_t j;
+    const void *work;        // [3 x ldA] Acc working vectors x, v, y
+    Pending pd;              // settled by split_dot; the later kernels read slot (j-1)&1
     int32_t check_status;
     int32_t ntiles;          // column tiles
     int64_t rows_per_band;
@@ -56,10 +55,11 @@ __global__ __launch_bounds__(BLOCK) void split_dot(const SplitArgs a) {
     constexpr int CW = BLOCK * VEC;
     constexpr int TW = CW * C;
     constexpr int AV = 16 / (int)sizeof(Acc);
-    const State &st = a.ctl->st[slot_of(a.j - 1)];
-    if (a.check_status && st.status != ST_RUNNING) return;
-
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const State st = sweep_state(a.pd, lane, blockIdx.x == 0 && blockIdx.y == 0 && tid == 0);
+    if (a.check_status && st.status != ST_RUNNING) return;
+    const double s = a.pd.decide ? st.s : 0.0;   // step decided on the previous check
+
     const int64_t tile0 = (int64_t)blockIdx.y * TW;
     const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_band;
     const int64_t r1 = min(a.m, r0 + a.rows_per_band);
@@ -69,6 +69,7 @@ __global__ __launch_bounds__(BLOCK) void split_dot(const SplitArgs a) {
     Acc xr[C][VEC], vr[C][VEC];
     const Acc *wx = reinterpret_cast<const Acc *>(a.work);
     const Acc *wv = wx + a.ldA;
+    const Acc *wy = wx + 2 * a.ldA;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int64_t col = min(col_of(c), a.ldA - VEC);
@@ -80,6 +81,13 @@ __global__ __launch_bounds__(BLOCK) void split_dot(const SplitArgs a) {
             if (HAS_V) {
                 const uint4 uv = *reinterpret_cast<const uint4 *>(wv + col + e);
                 __builtin_memcpy(&vr[c][e], &uv, 16);
+            }
+            if (s != 0.0) {
+                Acc yv[AV];
+                const uint4 uy = *reinterpret_cast<const uint4 *>(wy + col + e);
+                __builtin_memcpy(yv, &uy, 16);
+#pragma unroll
+                for (int k = 0; k < AV; ++k) xr[c][e + k] = (Acc)step_point((double)xr[c][e + k], s, (double)yv[k]);
             }
         }
 #pragma unroll
@@ -149,7 +157,7 @@ __global__ __launch_bounds__(BLOCK) void split_dot(const SplitArgs a) {
 // the step weight; per workgroup: h, dmax, binf.
 template <typename Acc>
 __global__ __launch_bounds__(256) void split_finish(const SplitArgs a, int has_v) {
-    const State &st = a.ctl->st[slot_of(a.j - 1)];
+    const State &st = a.pd.ctl->st[slot_of(a.pd.j - 1)];
     if (a.check_status && st.status != ST_RUNNING) return;
     const bool apply_v = has_v && (st.vpend_valid || st.v_idx >= 0);
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -220,7 +228,7 @@ __global__ __launch_bounds__(BLOCK) void split_axpy(const SplitArgs a) {
     constexpr int TW = CW * C;
     constexpr int AV = 16 / (int)sizeof(Acc);
     constexpr int LIST = 4096;   // rows per band at most (checked by the host)
-    const State &st = a.ctl->st[slot_of(a.j - 1)];
+    const State &st = a.pd.ctl->st[slot_of(a.pd.j - 1)];
     if (a.check_status && st.status != ST_RUNNING) return;
     const int tid = threadIdx.x;
     const int64_t tile0 = (int64_t)blockIdx.y * TW;

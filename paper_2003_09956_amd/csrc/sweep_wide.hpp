@@ -9,8 +9,9 @@
 //   y   += (r_i/||a_i||^2) a_i   if r_i > 0   (while the row is still in registers)
 //   h   += [r_i > 0],  dmax = max r_i/||a_i||,  binf = max |b'_i|
 //
-// x and v come from the working vectors written once per iteration by the
-// stage kernel, in the accumulation type.
+// x, v and y come from the working vectors written once per iteration by the
+// reduction kernel, in the accumulation type; the step decided on the previous
+// check (x_j = x_{j-1} - s*y_{j-1}) is applied while they are staged.
 //
 // Thread shape: LPR lanes (a multiple of the 64-wide wavefront) share a row;
 // a workgroup of BLOCK lanes holds BLOCK/LPR row groups, and each row group
@@ -84,11 +85,6 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
     static_assert(LPR % 64 == 0 && BLOCK % LPR == 0, "row groups are whole wavefronts");
     static_assert(VEC % AV == 0, "a lane's columns are whole 16-byte vectors of the working vectors");
 
-    const State &st = a.ctl->st[slot_of(a.j - 1)];
-    const int32_t status = st.status;
-    if (a.check_status && status != ST_RUNNING) return;
-    const bool apply_v = HAS_V && (st.vpend_valid || st.v_idx >= 0);
-
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -135,13 +131,17 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
         }
     };
 
-    // This lane's slices of the working point x and of v (padded with zeros
-    // to ldA), then the first rows.
+    // This lane's slices of the working vectors x, v and (when the previous
+    // step is still to be applied) y, padded with zeros to ldA, and the first
+    // rows: none of these loads depends on the state, so they are all in
+    // flight while the state is settled.  yacc holds the slice of y until the
+    // step is applied.
     Acc xr[C][VEC];
     Acc vr[C][VEC];
     Acc yacc[C][VEC];
     const Acc *wx = reinterpret_cast<const Acc *>(a.work);
     const Acc *wv = wx + a.ldA;
+    const Acc *wy = wx + 2 * a.ldA;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int64_t col = min(col_of(c), a.ldA - VEC);
@@ -156,16 +156,27 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
 #pragma unroll
                 for (int k = 0; k < AV; ++k) vr[c][e + k] = (Acc)0;
             }
+            if (a.pd.decide) {
+                const uint4 uy = *reinterpret_cast<const uint4 *>(wy + col + e);
+                __builtin_memcpy(&yacc[c][e], &uy, 16);
+            }
         }
     }
     uint4 bufA[RS][C], bufB[RS][C];
     double bA[RS], nA[RS], bB[RS], nB[RS];
     if (nsteps > 0) load_rows(bufA, bA, nA, 0);
+
+    const State st = sweep_state(a.pd, lane, blockIdx.x == 0 && tid == 0);
+    if (a.check_status && st.status != ST_RUNNING) return;
+    const bool apply_v = HAS_V && (st.vpend_valid || st.v_idx >= 0);
+    // the step decided on the previous check: x_j = x_{j-1} - s*y_{j-1}, one rounding
+    const double s = a.pd.decide ? st.s : 0.0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const bool in = col_of(c) < a.ldA;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
+            if (s != 0.0) xr[c][e] = (Acc)step_point((double)xr[c][e], s, (double)yacc[c][e]);
             if (!in) {
                 xr[c][e] = (Acc)0;
                 vr[c][e] = (Acc)0;

@@ -533,3 +533,62 @@ def test_split_row_iteration_matches_oracle_steps(P, dtype):
             assert np.linalg.norm(x1 - xo) <= bound, (k, np.linalg.norm(x1 - xo), bound)
             b = oracle.translate(sys_.A, dtype, b, V[k])
             x = x1
+
+
+def _run_calls(P, sys_, dtype, V, prm, chunks, tile=None, x0=None):
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, x0=x0, dtype=dtype)
+        if tile is not None:
+            s.set_tile(*tile[:4], 1, kind=tile[4])
+        s.set_drift(V)
+        for k in chunks:
+            st = s.iterate(k, prm)
+        x, b, st = s.query(want_x=True, want_b=True)
+    return x, b, st
+
+
+@pytest.mark.parametrize("form", ["one-pass", "split"])
+@pytest.mark.parametrize("track", [False, True])
+def test_queued_iterations_equal_single_calls_f64(P, form, track):
+    """Iterations queued in one call settle each check at the start of the
+    next sweep; one iteration per call settles it at the end of the call.
+    With FP64 storage the working vectors are exact, so both give the same
+    bits: x, the translated b, and the counters, with the drift applied every
+    iteration (and, in tracking mode, past the eps-feasible checks)."""
+    n, m = 700, 1500
+    sys_ = W.gaussian(n, m, seed=21, dtype="f64")
+    V = W.drift(n, 40, sigma=2e-3, seed=21)
+    prm = P.params(lam=0.2, eps=1e-6, track=track)
+    tile = (256, 256, 8, 0, 1) if form == "split" else None
+    x0 = sys_.z + 0.5   # about 13 from the feasible set: 30 steps of 0.2 do not reach it
+    say(f"queued vs single form={form} track={track}")
+    xa, ba, sa = _run_calls(P, sys_, "f64", V, prm, [30], tile, x0)
+    xb, bb, sb = _run_calls(P, sys_, "f64", V, prm, [1] * 30, tile, x0)
+    xc, bc, sc = _run_calls(P, sys_, "f64", V, prm, [7, 1, 15, 7], tile, x0)
+    assert sa.sweeps == sb.sweeps == sc.sweeps == 30
+    assert sa.iters == sb.iters == sc.iters > 0
+    assert np.array_equal(xa, xb) and np.array_equal(xa, xc)
+    assert np.array_equal(ba, bb) and np.array_equal(ba, bc)
+
+
+def test_queued_iterations_follow_the_oracle_f32(P):
+    """Three iterations queued in one call with the drift applied, against the
+    oracle's three steps from the same start on the same moving data (rows far
+    from the boundary, so the three masks are not in doubt)."""
+    n, m = 512, 1200
+    sys_ = W.gaussian(n, m, seed=8, dtype="f32")
+    V = W.drift(n, 10, sigma=1e-3, seed=8)
+    lam = 0.05
+    x0 = sys_.z + 0.5
+    say("queued f32 vs oracle")
+    xg, bg, st = _run_calls(P, sys_, "f32", V, P.params(lam=lam, eps=1e-9), [3], None, x0)
+    assert st.iters == 3
+    x, b = x0.copy(), sys_.b.copy()
+    for k in range(3):
+        o = oracle.sweep(sys_.A, "f32", b, x)
+        x, status = oracle.step(o.y, o.h, 0, lam, x)
+        assert status == 0
+        b = oracle.translate(sys_.A, "f32", b, V[k])
+    assert np.linalg.norm(xg - x) <= 3 * TOL["f32"] * (np.linalg.norm(x) + lam), np.linalg.norm(xg - x)
+    scale = np.abs(W.stored_to_f64(sys_.A, "f32")) @ np.abs(V[:3]).sum(axis=0) + np.abs(sys_.b)
+    assert np.max(np.abs(bg - b) / scale) <= TOL["f32"]
