@@ -4,25 +4,27 @@
 Workload (one "step" = one full iteration of the method on one GPU: the fused
 sweep over A -- residuals, violated-row mask, positive-slice sum y, eps test,
 and the translation of the system by that iteration's drift vector, b <- b + A v
--- then the fixed-order reduction of y with the ModAP step x <- x - lambda
+-- then the fixed-order reduction of y and the ModAP step x <- x - lambda
 y/||y||):
 
-  FP32 non-stationary Gaussian system, n = 8192, m = 16384, rows a_i ~ N(0,1)
-  normalised and stored FP32; hidden point z ~ U(-1,1)^n, b = A z + U(0,1);
-  drift v ~ N(0, 1e-2^2)^n per iteration; x0 = 0; lambda = 1;
+  default: FP32 non-stationary Gaussian system, n = 8192, m = 16384, rows
+  a_i ~ N(0,1) normalised and stored FP32; hidden point z ~ U(-1,1)^n,
+  b = A z + U(0,1); drift v ~ N(0, 1e-2^2)^n per iteration; x0 = 0; lambda = 1;
   eps = 1e-6 * ||b||_inf.
+  --workload bf16-16384x65536: the same construction at n = 16384, m = 65536
+  with A stored BF16 (2 GiB), drift |v| = 1e-4 per iteration.
 
 The timed loop runs in tracking mode (an eps-feasible check takes no step but
 the system keeps moving), so every timed step reads all of A.
 
 Printed JSON line: `value` is the whole-job algorithmic HBM throughput of the
-timed steps, m*n*4 + 24*m bytes per step (A, b read and written, ||a_i||^2),
-divided by wall time; `roofline` is the same byte count over the sweep
-kernel's average duration (HIP events recorded by the dispatches of every tenth
-timed iteration, on the library's stream); time-to-feasible
-p50/p99 comes from solves of the FP64 box-plus-sum system (n=256, m=513,
-20 seeds) and of the FP32 system above; `cpu_baseline` times the CPU oracle on
-a bounded number of iterations of the same system.
+timed steps, m*n*sizeof(A) + 24*m bytes per step (A, b read and written,
+||a_i||^2), divided by wall time; `roofline` is the same byte count over the
+sweep kernel's average duration (HIP events recorded by the dispatches of every
+tenth timed iteration, on the library's stream); time-to-feasible p50/p99 comes
+from solves of the FP64 box-plus-sum system (n=256, m=513, 20 seeds) and of the
+default FP32 system under its drift; `cpu_baseline` times the CPU oracle on a
+bounded number of iterations of the same system.
 """
 from __future__ import annotations
 
@@ -40,12 +42,23 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_EVERY = 10      # one iteration in ten carries HIP events on its kernel dispatches
 METRIC = "pseudo-projection sweep HBM GB/s (% of peak); p50/p99 time-to-feasible"
 KERNEL_SOURCES = ["paper_2003_09956_amd/csrc/sweep_wide.hpp", "paper_2003_09956_amd/csrc/modap_device.hpp",
-                  "paper_2003_09956_amd/csrc/sweep_f32.hip", "paper_2003_09956_amd/csrc/sweep_inst.inc"]
+                  "paper_2003_09956_amd/csrc/sweep_inst.inc"]
+# The systems a step can run on: storage, n, m, drift sigma, description.
+WORKLOADS = {
+    "f32-8192x16384": ("f32", 8192, 16384, 1e-2,
+                       "FP32 non-stationary Gaussian system n=8192 m=16384, drift N(0,1e-2^2) per coordinate "
+                       "per iteration, lambda=1, eps=1e-6*||b||inf, ModAP fixed-length step"),
+    "bf16-16384x65536": ("bf16", 16384, 65536, 1e-4 / 128,
+                         "BF16-stored Gaussian system n=16384 m=65536 (FP32 accumulation, FP64 scalars), "
+                         "drift |v|=1e-4 per iteration, lambda=1, eps=1e-6*||b||inf, ModAP fixed-length step"),
+}
+ELEM_BYTES = {"f64": 8, "f32": 4, "bf16": 2}
+DT_CODE = {"f64": 0, "f32": 1, "bf16": 2}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(dt: str = "f32") -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in KERNEL_SOURCES + [f"paper_2003_09956_amd/csrc/sweep_{dt}.hip"]:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -60,23 +73,28 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if xs else None
 
 
-def counters_path(tile: str) -> str:
+def tile_str(tile) -> str:
+    return (f"{tile['block']},{tile['lanes_per_row']},{tile['chunks']},{tile['rows_per_step']},"
+            f"{tile['depth']},{tile['interleave']},{tile['grid']}")
+
+
+def counters_path(dt: str, n: int, m: int, tile: str) -> str:
     """Committed rocprofv3 counter summary of the sweep at one tile
-    (block,lanes_per_row,chunks,rows_per_step,grid)."""
-    return os.path.join(ROOT, "profiles", f"sweep_wide_f32_n8192_m16384_tile{tile.replace(',', '-')}_counters.txt")
+    (block,lanes_per_row,chunks,rows_per_step,depth,interleave,grid)."""
+    return os.path.join(ROOT, "profiles", f"sweep_wide_{dt}_n{n}_m{m}_tile{tile.replace(',', '-')}_counters.txt")
 
 
-def measured_traffic(tile):
+def measured_traffic(dt, n, m, tile):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of known size), if
     one was taken on the current kernel source at this shape; else None."""
-    want = f"{tile['block']},{tile['lanes_per_row']},{tile['chunks']},{tile['rows_per_step']},{tile['grid']}"
+    want = tile_str(tile)
     try:
-        with open(counters_path(want)) as f:
+        with open(counters_path(dt, n, m, want)) as f:
             kv = dict(l.split(" = ", 1) for l in f.read().splitlines() if " = " in l and not l.startswith("#"))
     except OSError:
         return None
-    if kv.get("source_hash") != kernel_source_hash() or kv.get("tile") != want:
+    if kv.get("source_hash") != kernel_source_hash(dt) or kv.get("tile") != want:
         return None
     return int(float(kv["bytes_per_launch"]))
 
@@ -103,12 +121,12 @@ def cpu_baseline(sys_, V, seconds_budget):
     import oracle
     oracle.build(force=False)
     t0 = time.perf_counter()
-    oracle.solve(sys_.A, "f32", sys_.b, sys_.x0, lam=1.0, eps=1e-300, eps_relative=False,
+    oracle.solve(sys_.A, sys_.dtype, sys_.b, sys_.x0, lam=1.0, eps=1e-300, eps_relative=False,
                  rule=0, max_steps=1, V=V[:1])
     one = time.perf_counter() - t0
     steps = max(1, int(seconds_budget / max(one, 1e-3)))
     t0 = time.perf_counter()
-    res = oracle.solve(sys_.A, "f32", sys_.b, sys_.x0, lam=1.0, eps=1e-300, eps_relative=False,
+    res = oracle.solve(sys_.A, sys_.dtype, sys_.b, sys_.x0, lam=1.0, eps=1e-300, eps_relative=False,
                        rule=0, max_steps=steps, V=V[:steps])
     dt = time.perf_counter() - t0
     assert res.iters == steps
@@ -124,8 +142,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttf", action="store_true", help="skip the time-to-feasible solves")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="f32-8192x16384",
+                    help="system the timed steps run on (default: the FP32 n=8192 m=16384 system)")
     ap.add_argument("--tile", type=str, default=None,
-                    help="force the sweep shape block,lanes_per_row,chunks,rows_per_step,grid (skips the autotuner)")
+                    help="force the sweep shape block,lanes_per_row,chunks,rows_per_step,depth,interleave,grid "
+                         "(skips the autotuner)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes five times (counter calibration)")
     args = ap.parse_args()
@@ -156,24 +177,25 @@ def main():
     P.lib()
 
     K, WU = args.steps, args.warmup
-    sigma, lam, eps = 1e-2, 1.0, 1e-6
-    log("generating n=8192 m=16384 FP32 system ...")
-    sys_ = W.c2(args.seed)
-    V = W.drift(sys_.n, K + WU, sigma=sigma, seed=args.seed)
-    m, n = sys_.m, sys_.n
-    bytes_per_step = m * n * 4 + 24 * m
+    dt, n, m, sigma, desc = WORKLOADS[args.workload]
+    default_workload = args.workload == "f32-8192x16384"
+    lam, eps = 1.0, 1e-6
+    log(f"generating the {args.workload} system ...")
+    sys_ = W.gaussian(n, m, args.seed, dt)
+    V = W.drift(n, K + WU, sigma=sigma, seed=args.seed)
+    bytes_per_step = m * n * ELEM_BYTES[dt] + 24 * m
 
     with P.Solver(0) as s:
-        s.set_system(sys_.A, sys_.b, dtype="f32")      # first call: allocation and warm-up
+        s.set_system(sys_.A, sys_.b, dtype=dt)      # first call: allocation and warm-up
         torch.cuda.synchronize()
         u0 = time.perf_counter()
-        s.set_system(sys_.A, sys_.b, dtype="f32")      # host arrays: A, b over PCIe, then the row norms
+        s.set_system(sys_.A, sys_.b, dtype=dt)      # host arrays: A, b over PCIe, then the row norms
         torch.cuda.synchronize()
         upload_s = time.perf_counter() - u0
         s.set_drift(V)
         if args.tile:
-            blk, lpr, ch, rs, grid = (int(v) for v in args.tile.split(","))
-            s.set_tile(blk, lpr, ch, grid, rs)
+            blk, lpr, ch, rs, depth, il, grid = (int(v) for v in args.tile.split(","))
+            s.set_tile(blk, lpr, ch, grid, rs, depth=depth, interleave=il)
             tile = s.get_tile()
             log("tile (forced)", tile)
         else:
@@ -188,7 +210,7 @@ def main():
         st = s.iterate(K, P.params(lam=lam, eps=eps, track=True, profile=PROFILE_EVERY))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        if st.sweeps != K + WU or st.profiled != (K + PROFILE_EVERY - 1) // PROFILE_EVERY:
+        if st.sweeps != K + WU or st.profiled != n_prof:
             raise RuntimeError(f"timed region ran {st.sweeps - WU} sweeps, expected {K}")
         wall = t1 - t0
         sweep_us = st.sweep_ms * 1e3 / st.profiled
@@ -197,18 +219,19 @@ def main():
         log(f"timed {K} steps in {wall * 1e3:.2f} ms; sweep {sweep_us:.1f} us, reduce {reduce_us:.1f} us")
 
         # time-to-feasible on the same moving system, from x0 = 0
-        ttf_c2 = None
-        if not args.no_ttf:
-            s.set_system(sys_.A, sys_.b, dtype="f32")
+        ttf_drift = None
+        if not args.no_ttf and default_workload:
+            s.set_system(sys_.A, sys_.b, dtype=dt)
             V2 = W.drift(n, 3000, sigma=sigma, seed=args.seed + 1)
             s.set_drift(V2)
             st2, code = s.solve(P.params(lam=lam, eps=eps, max_iters=3000), raise_on_stop=False)
-            ttf_c2 = {"caught": code == 0, "ms": st2.seconds * 1e3, "steps": int(st2.iters),
-                      "max_violation": st2.max_viol, "eps_abs": st2.eps_abs}
-            log("ttf n=8192", ttf_c2)
+            ttf_drift = {"caught": code == 0, "ms": st2.seconds * 1e3, "steps": int(st2.iters),
+                         "max_violation": st2.max_viol, "eps_abs": st2.eps_abs}
+            log("ttf under drift", ttf_drift)
 
     value = bytes_per_step * K / wall / 1e9
     achieved = bytes_per_step / (sweep_us * 1e-6) / 1e9
+    kind = "sweep_split" if tile["kind"] == 1 else "sweep_wide"
     line = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -220,12 +243,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dt,
         "data": "synthetic",
-        "config": {"workload": "FP32 non-stationary Gaussian system n=8192 m=16384, "
-                               "drift N(0,1e-2^2) per coordinate per iteration, lambda=1, "
-                               "eps=1e-6*||b||inf, ModAP fixed-length step",
-                   "n": n, "m": m, "storage": "f32", "accumulate": "f32 dot, f64 scalars",
+        "config": {"workload": desc, "n": n, "m": m, "storage": dt,
+                   "accumulate": "f64" if dt == "f64" else "f32 dot, f64 scalars",
                    "bytes_per_step": bytes_per_step, "tile": tile},
         "pct_of_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "iterations_per_s": round(K / wall, 1),
@@ -234,8 +255,9 @@ def main():
                         "pcie_inclusive_GBs": round(bytes_per_step * K / (wall + upload_s) / 1e9, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(tile),
-                     "kernel": f"sweep_wide<1,{tile['block']},{tile['lanes_per_row']},{tile['chunks']},true>",
+                     "traffic": measured_traffic(dt, n, m, tile) if tile["kind"] == 0 else None,
+                     "kernel": f"{kind}<{DT_CODE[dt]},{tile['block']},{tile['lanes_per_row']},{tile['chunks']},"
+                               f"{tile['rows_per_step']},{tile['depth']},true>",
                      "avg_us": round(sweep_us, 3), "reduce_avg_us": round(reduce_us, 3)},
     }
     if not args.no_ttf:
@@ -243,14 +265,15 @@ def main():
         line["time_to_feasible"] = {
             "box_sum_f64_n256_m513": {"p50_ms": round(percentile(ms, 50), 3), "p99_ms": round(percentile(ms, 99), 3),
                                       "seeds": 20, "steps_p50": percentile(its, 50)},
-            "gaussian_f32_n8192_m16384_drift": ttf_c2,
         }
+        if ttf_drift is not None:
+            line["time_to_feasible"]["gaussian_f32_n8192_m16384_drift"] = ttf_drift
     if not args.no_cpu_baseline:
-        steps, dt = cpu_baseline(sys_, V, args.cpu_seconds)
-        line["cpu_baseline"] = {"value": round(bytes_per_step * steps / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
+        steps, secs = cpu_baseline(sys_, V, args.cpu_seconds)
+        line["cpu_baseline"] = {"value": round(bytes_per_step * steps / secs / 1e9, 4), "unit": "GB/s", "cores": 1,
                                 "kind": "oracle",
-                                "sample": f"{steps} iterations (translate, sweep, step) of the full n=8192 m=16384 "
-                                          f"FP32 system, {dt:.1f} s, single-threaded extended-precision oracle"}
+                                "sample": f"{steps} iterations (translate, sweep, step) of the full n={n} m={m} "
+                                          f"{dt} system, {secs:.1f} s, single-threaded extended-precision oracle"}
     print(json.dumps(line), flush=True)
 
 

@@ -111,8 +111,11 @@ typedef struct {
     int32_t lanes_per_row;  /* threads that share one row (64 .. block) */
     int32_t chunks;         /* 16-byte vectors per thread per row (kind 0) or per column tile (kind 1) */
     int32_t grid;           /* workgroups of the sweep (0 on input: the library's choice) */
-    int32_t rows_per_step;  /* rows each row group loads per step; the next step's rows are
-                               in flight while the current ones are reduced */
+    int32_t rows_per_step;  /* rows each row group loads per step */
+    int32_t depth;          /* kind 0: steps held per row group; the next depth-1 steps' rows are
+                               in flight while one is reduced (0 on input: the library's choice) */
+    int32_t interleave;     /* kind 0: 0 = each workgroup takes a contiguous band of rows;
+                               1 = the workgroups take consecutive row blocks in turn */
 } modap_tile;
 
 /* Create a context on HIP device `device`.  hip_stream: the hipStream_t to

@@ -55,7 +55,8 @@ class Stats(C.Structure):
 
 class Tile(C.Structure):
     _fields_ = [("kind", C.c_int32), ("block", C.c_int32), ("lanes_per_row", C.c_int32),
-                ("chunks", C.c_int32), ("grid", C.c_int32), ("rows_per_step", C.c_int32)]
+                ("chunks", C.c_int32), ("grid", C.c_int32), ("rows_per_step", C.c_int32),
+                ("depth", C.c_int32), ("interleave", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -296,11 +297,13 @@ class Solver:
         self._check(lib().modap_query(self._ctx, px, pb, C.byref(out), 0))
         return x, b, out
 
-    def set_tile(self, block=None, lanes_per_row=None, chunks=None, grid=0, rows_per_step=1, kind=0):
+    def set_tile(self, block=None, lanes_per_row=None, chunks=None, grid=0, rows_per_step=1, kind=0, depth=0,
+                 interleave=0):
         if block is None:
             self._check(lib().modap_set_tile(self._ctx, None))
             return
-        t = Tile(int(kind), int(block), int(lanes_per_row), int(chunks), int(grid), int(rows_per_step))
+        t = Tile(int(kind), int(block), int(lanes_per_row), int(chunks), int(grid), int(rows_per_step), int(depth),
+                 int(interleave))
         self._check(lib().modap_set_tile(self._ctx, C.byref(t)))
 
     def autotune(self, reps=5):

@@ -61,7 +61,9 @@ struct modap_ctx {
     void *pdot = nullptr;
     size_t pdot_bytes = 0;
     double *wrow = nullptr;
-    int64_t rows_per_block = 0;
+    int64_t rows_per_block = 0;  // one-pass sweep: row mapping (see SweepArgs)
+    int64_t block_stride = 0;
+    int64_t step_stride = 0;
     int64_t ldPart = 0;
     void *part = nullptr;
     size_t part_bytes = 0;
@@ -144,14 +146,16 @@ const SweepKernel *kernels_for(int dt, int *count) {
     }
 }
 
-const SweepKernel *find_kernel(int dt, int block, int lpr, int chunks, int rs, bool has_v) {
+// The compiled kernel of a shape; depth 0 takes the shallowest one compiled.
+const SweepKernel *find_kernel(int dt, int block, int lpr, int chunks, int rs, int depth, bool has_v) {
     int cnt = 0;
     const SweepKernel *t = kernels_for(dt, &cnt);
+    const SweepKernel *hit = nullptr;
     for (int i = 0; i < cnt; ++i)
         if (t[i].block == block && t[i].lpr == lpr && t[i].chunks == chunks && t[i].rs == rs &&
-            t[i].has_v == has_v)
-            return &t[i];
-    return nullptr;
+            t[i].has_v == has_v && (depth == 0 ? (!hit || t[i].pd < hit->pd) : t[i].pd == depth))
+            hit = &t[i];
+    return hit;
 }
 
 int64_t coverage(int dt, int lpr, int chunks) { return (int64_t)lpr * vec_elems(dt) * chunks; }
@@ -166,9 +170,10 @@ const SplitKernels *split_for(int dt) {
 
 constexpr int64_t kMaxBandRows = 4096;  // rows per band of the split-row form (its row list)
 
-// Built-in choice of the fused sweep's shape: the smallest row coverage that
-// holds a padded row; among equal coverage, about 16 elements per lane, then
-// the larger workgroup, then two rows per step.
+// Built-in choice of the fused sweep's shape (what measured fastest on the
+// headline systems): the smallest row coverage that holds a padded row; among
+// equal coverage, about 32 elements (128 bytes of FP32) per lane per row, then
+// the smaller workgroup, one row per step and the shallowest prefetch.
 bool choose_shape(int dt, int64_t ldA, modap_tile *out) {
     int cnt = 0;
     const SweepKernel *t = kernels_for(dt, &cnt);
@@ -180,8 +185,8 @@ bool choose_shape(int dt, int64_t ldA, modap_tile *out) {
         const int64_t cov = coverage(dt, t[i].lpr, t[i].chunks);
         if (cov < ldA) continue;
         const int epl = t[i].chunks * vec_elems(dt);
-        const int score = std::abs(epl - 16) * 16 + (t[i].block == 1024 ? 0 : t[i].block == 512 ? 4 : 8) +
-                          (t[i].rs == 2 ? 0 : t[i].rs == 1 ? 1 : 2);
+        const int score = std::abs(epl - 32) * 16 + (t[i].block == 256 ? 0 : t[i].block == 512 ? 4 : 8) +
+                          (t[i].rs == 1 ? 0 : 2) + 4 * (t[i].pd - 2) + (t[i].lpr == t[i].block ? 0 : 1);
         if (!best || cov < best_cov || (cov == best_cov && score < best_score)) {
             best = &t[i];
             best_cov = cov;
@@ -196,6 +201,8 @@ bool choose_shape(int dt, int64_t ldA, modap_tile *out) {
         out->chunks = sk->chunks;
         out->grid = 0;
         out->rows_per_step = 1;
+        out->depth = 0;
+        out->interleave = 0;
         return true;
     }
     out->kind = 0;
@@ -204,6 +211,8 @@ bool choose_shape(int dt, int64_t ldA, modap_tile *out) {
     out->chunks = best->chunks;
     out->grid = 0;
     out->rows_per_step = best->rs;
+    out->depth = best->pd;
+    out->interleave = 0;
     return true;
 }
 
@@ -258,6 +267,8 @@ modap_status configure_split(modap_ctx *c, modap_tile t) {
     c->ldPart = (int64_t)ntiles * tw;
     t.grid = (int)bands;
     t.rows_per_step = 1;
+    t.depth = 0;
+    t.interleave = 0;
     c->tile = t;
     c->kern_v = c->kern_nov = nullptr;
     return MODAP_OK;
@@ -269,9 +280,12 @@ modap_status configure(modap_ctx *c, const modap_tile &want) {
     if (t.kind == 1) return configure_split(c, t);
     if (t.kind != 0) return fail(c, MODAP_E_INVAL, "tile kind must be 0 (one pass) or 1 (split rows)");
     if (t.rows_per_step <= 0) t.rows_per_step = 1;
-    const SweepKernel *kv = find_kernel(c->dt, t.block, t.lanes_per_row, t.chunks, t.rows_per_step, true);
-    const SweepKernel *kn = find_kernel(c->dt, t.block, t.lanes_per_row, t.chunks, t.rows_per_step, false);
-    if (!kv || !kn) return fail(c, MODAP_E_INVAL, "no compiled sweep kernel of that shape for this storage type");
+    if (t.depth < 0) return fail(c, MODAP_E_INVAL, "tile depth must be >= 0");
+    const SweepKernel *kv = find_kernel(c->dt, t.block, t.lanes_per_row, t.chunks, t.rows_per_step, t.depth, true);
+    if (!kv) return fail(c, MODAP_E_INVAL, "no compiled sweep kernel of that shape for this storage type");
+    t.depth = kv->pd;
+    const SweepKernel *kn = find_kernel(c->dt, t.block, t.lanes_per_row, t.chunks, t.rows_per_step, t.depth, false);
+    if (!kn) return fail(c, MODAP_E_INVAL, "no compiled sweep kernel of that shape for this storage type");
     const int64_t cov = coverage(c->dt, t.lanes_per_row, t.chunks);
     if (cov < c->ldA) return fail(c, MODAP_E_INVAL, "sweep shape does not cover a row");
     const int per_step = (t.block / t.lanes_per_row) * t.rows_per_step;
@@ -282,9 +296,21 @@ modap_status configure(modap_ctx *c, const modap_tile &want) {
             per_cu = 1;
         grid = c->cu_count * per_cu;
     }
-    int64_t rpb = (c->m + grid - 1) / grid;
-    rpb = ((rpb + per_step - 1) / per_step) * per_step;
-    grid = (int)((c->m + rpb - 1) / rpb);
+    if (t.interleave != 0 && t.interleave != 1) return fail(c, MODAP_E_INVAL, "tile interleave must be 0 or 1");
+    int64_t rpb, block_stride, step_stride;
+    if (t.interleave) {
+        // workgroup b takes row blocks b, b + grid, b + 2*grid, ... of per_step rows
+        grid = (int)std::min<int64_t>(grid, (c->m + per_step - 1) / per_step);
+        rpb = c->m;
+        block_stride = per_step;
+        step_stride = (int64_t)grid * per_step;
+    } else {
+        rpb = (c->m + grid - 1) / grid;
+        rpb = ((rpb + per_step - 1) / per_step) * per_step;
+        grid = (int)((c->m + rpb - 1) / rpb);
+        block_stride = rpb;
+        step_stride = per_step;
+    }
     const size_t acc = acc_size(c->dt);
     modap_status st;
     if ((st = ensure_part(c, (size_t)grid * (size_t)cov * acc))) return st;
@@ -293,6 +319,8 @@ modap_status configure(modap_ctx *c, const modap_tile &want) {
     c->kern_v = kv;
     c->kern_nov = kn;
     c->rows_per_block = rpb;
+    c->block_stride = block_stride;
+    c->step_stride = step_stride;
     c->ldPart = cov;
     t.grid = grid;
     c->tile = t;
@@ -384,6 +412,8 @@ SweepArgs sweep_args(modap_ctx *c) {
     a.dmax_part = c->dmax_part;
     a.binf_part = c->binf_part;
     a.rows_per_block = c->rows_per_block;
+    a.block_stride = c->block_stride;
+    a.step_stride = c->step_stride;
     return a;
 }
 
@@ -662,7 +692,7 @@ modap_status launch_flush(modap_ctx *c) {
 }
 
 
-// Tuning cache: lines "dt ldA m block lanes_per_row chunks rows_per_step grid".
+// Tuning cache: lines "dt ldA m block lanes_per_row chunks rows_per_step depth interleave grid".
 const char *tune_cache_path() {
     const char *p = std::getenv("MODAP_TUNE_CACHE");
     return (p && *p) ? p : nullptr;
@@ -674,15 +704,21 @@ bool cache_lookup(const modap_ctx *c, modap_tile *t) {
     FILE *f = std::fopen(path, "r");
     if (!f) return false;
     long long dt, lda, m;
-    int blk, lpr, ch, rs, grid;
+    int blk, lpr, ch, rs, depth, il, grid;
     bool found = false;
-    while (std::fscanf(f, "%lld %lld %lld %d %d %d %d %d", &dt, &lda, &m, &blk, &lpr, &ch, &rs, &grid) == 8) {
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::sscanf(line, "%lld %lld %lld %d %d %d %d %d %d %d", &dt, &lda, &m, &blk, &lpr, &ch, &rs, &depth,
+                        &il, &grid) != 10)
+            continue;  // not a line of this format
         if (dt == c->dt && lda == c->ldA && m == c->m) {  // the last matching line wins
             t->kind = 0;
             t->block = blk;
             t->lanes_per_row = lpr;
             t->chunks = ch;
             t->rows_per_step = rs;
+            t->depth = depth;
+            t->interleave = il;
             t->grid = grid;
             found = true;
         }
@@ -696,8 +732,8 @@ void cache_store(const modap_ctx *c, const modap_tile &t) {
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%d %lld %lld %d %d %d %d %d\n", c->dt, (long long)c->ldA, (long long)c->m, t.block,
-                 t.lanes_per_row, t.chunks, t.rows_per_step, t.grid);
+    std::fprintf(f, "%d %lld %lld %d %d %d %d %d %d %d\n", c->dt, (long long)c->ldA, (long long)c->m, t.block,
+                 t.lanes_per_row, t.chunks, t.rows_per_step, t.depth, t.interleave, t.grid);
     std::fclose(f);
 }
 
@@ -1206,8 +1242,9 @@ modap_status modap_autotune(modap_ctx *c, int reps, modap_tile *best) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tab[i].func, tab[i].block, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
-        for (int mult = 1; mult <= std::max(2, per_cu); ++mult) {
-            modap_tile t{0, tab[i].block, tab[i].lpr, tab[i].chunks, c->cu_count * mult, tab[i].rs};
+        for (int trial = 0; trial < 2 * std::max(2, per_cu); ++trial) {
+            const int mult = trial / 2 + 1, il = trial % 2;
+            modap_tile t{0, tab[i].block, tab[i].lpr, tab[i].chunks, c->cu_count * mult, tab[i].rs, tab[i].pd, il};
             if (mult > 1 && mult != per_cu && mult != 2) continue;
             if (configure(c, t) != MODAP_OK) continue;
             SweepArgs a = sweep_args(c);

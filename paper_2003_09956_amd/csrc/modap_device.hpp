@@ -115,7 +115,11 @@ struct SweepArgs {
     int64_t *h_part;        // [grid]
     double *dmax_part;      // [grid]
     double *binf_part;      // [grid]
+    // rows of workgroup b: from b*block_stride, one step of rows every
+    // step_stride rows, below min(m, b*block_stride + rows_per_block)
     int64_t rows_per_block;
+    int64_t block_stride;
+    int64_t step_stride;
 };
 
 struct ReduceArgs {

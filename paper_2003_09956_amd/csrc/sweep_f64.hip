@@ -1,13 +1,14 @@
-// Fused sweep shapes for IEEE binary64 storage (16-byte vector = 2 elements).
+// Fused sweep shapes for IEEE binary64 storage (16-byte vector = 2 elements):
+// (workgroup, lanes per row, chunks, rows per step, steps in flight + 1).
 // Every shape listed compiles without register spills.
 #define MODAP_DT 0
 #define MODAP_SHAPES                                                                             \
-    MODAP_SHAPE(256, 64, 1, 1), MODAP_SHAPE(256, 64, 2, 1), MODAP_SHAPE(256, 64, 4, 1),          \
-    MODAP_SHAPE(256, 64, 1, 2), MODAP_SHAPE(256, 64, 2, 2), MODAP_SHAPE(256, 64, 4, 2),          \
-    MODAP_SHAPE(256, 256, 2, 1), MODAP_SHAPE(256, 256, 4, 1), MODAP_SHAPE(256, 256, 8, 1),       \
-    MODAP_SHAPE(256, 256, 2, 2), MODAP_SHAPE(256, 256, 4, 2),                                    \
-    MODAP_SHAPE(512, 512, 2, 1), MODAP_SHAPE(512, 512, 4, 1), MODAP_SHAPE(512, 512, 8, 1),       \
-    MODAP_SHAPE(512, 512, 2, 2), MODAP_SHAPE(512, 512, 4, 2)
+    MODAP_SHAPE(256, 64, 1, 1, 2), MODAP_SHAPE(256, 64, 2, 1, 2), MODAP_SHAPE(256, 64, 4, 1, 2),          \
+    MODAP_SHAPE(256, 64, 1, 2, 2), MODAP_SHAPE(256, 64, 2, 2, 2), MODAP_SHAPE(256, 64, 4, 2, 2),          \
+    MODAP_SHAPE(256, 256, 2, 1, 2), MODAP_SHAPE(256, 256, 4, 1, 2), MODAP_SHAPE(256, 256, 8, 1, 2),       \
+    MODAP_SHAPE(256, 256, 2, 2, 2), MODAP_SHAPE(256, 256, 4, 2, 2),                                    \
+    MODAP_SHAPE(512, 512, 2, 1, 2), MODAP_SHAPE(512, 512, 4, 1, 2), MODAP_SHAPE(512, 512, 8, 1, 2),       \
+    MODAP_SHAPE(512, 512, 2, 2, 2), MODAP_SHAPE(512, 512, 4, 2, 2)
 // split-row form: 256 lanes x 8 chunks per column tile
 #define MODAP_SPLIT_C 8
 #include "sweep_inst.inc"

@@ -15,6 +15,7 @@ struct SweepKernel {
     int lpr;
     int chunks;
     int rs;
+    int pd;          // steps of rows in flight + 1
     bool has_v;
     SweepLaunch launch;
     const void *func;

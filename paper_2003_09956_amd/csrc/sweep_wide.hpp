@@ -15,18 +15,19 @@
 //
 // Thread shape: LPR lanes (a multiple of the 64-wide wavefront) share a row;
 // a workgroup of BLOCK lanes holds BLOCK/LPR row groups, and each row group
-// takes RS consecutive rows per step.  The row is cut into C chunks of LPR*VEC
+// takes RS consecutive rows per step, with the rows of the next PD-1 steps in
+// flight (PD at the start).  The row is cut into C chunks of LPR*VEC
 // columns; lane l owns VEC consecutive columns of every chunk, so each
 // wavefront load of a chunk is 64 contiguous 16-byte vectors (1 KiB).  The
 // chunks are visited in an order rotated by the workgroup index, so that the
 // workgroups do not all read the same part of the working vectors at once.
 // The lane's slices of x, v and of the partial y stay in registers for the
-// whole sweep; the next step's rows are loaded (non-temporally: A is read once
-// per sweep) while the current ones are reduced, so 2*RS rows per row group
-// are in flight.  Dot products are reduced across the wavefront with a
+// whole sweep; the next PD-1 steps' rows are loaded (non-temporally: A is read
+// once per sweep) while the current ones are reduced.  Dot products are reduced across the wavefront with a
 // butterfly (the same value in every lane) and across the wavefronts of a row
 // group through LDS, in a fixed order, so results do not depend on timing.
-// Each workgroup owns a contiguous band of rows and writes one partial y; the
+// Each workgroup owns a fixed set of rows (a contiguous band, or row blocks
+// taken in turn with the other workgroups) and writes one partial y; the
 // reduction kernel sums the partials in a fixed order.
 #pragma once
 
@@ -71,7 +72,7 @@ __device__ __forceinline__ void unpack<2>(const uint4 &u, float (&o)[8]) {
     o[7] = __uint_as_float(u.w & 0xffff0000u);
 }
 
-template <int DT, int BLOCK, int LPR, int C, int RS, bool HAS_V>
+template <int DT, int BLOCK, int LPR, int C, int RS, int PD, bool HAS_V>
 __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
     using S = Store<DT>;
     using Acc = typename S::Acc;
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
     constexpr int AV = 16 / (int)sizeof(Acc);  // working-vector elements per 16-byte load
     static_assert(LPR % 64 == 0 && BLOCK % LPR == 0, "row groups are whole wavefronts");
     static_assert(VEC % AV == 0, "a lane's columns are whole 16-byte vectors of the working vectors");
+    static_assert(PD >= 2, "at least one step is in flight while another is reduced");
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -98,14 +100,17 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
         return (int64_t)cc * CW + gl * VEC;
     };
 
-    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
+    // A step takes NG*RS consecutive rows; the workgroup's steps are either
+    // consecutive (a band of rows) or step_stride rows apart (the workgroups
+    // take consecutive row blocks in turn, so that at any time they all read
+    // one contiguous region of A).
+    const int64_t r0 = (int64_t)blockIdx.x * a.block_stride;
     const int64_t r1 = min(a.m, r0 + a.rows_per_block);
-    constexpr int ROWS_PER_STEP = NG * RS;
-    const int64_t nsteps = r1 > r0 ? (r1 - r0 + ROWS_PER_STEP - 1) / ROWS_PER_STEP : 0;
+    const int64_t nsteps = r1 > r0 ? (r1 - r0 + a.step_stride - 1) / a.step_stride : 0;
     const char *Ab = reinterpret_cast<const char *>(a.A);
     const int64_t row_bytes = a.ldA * (int64_t)sizeof(T);
 
-    auto row_of = [&](int64_t t, int q) -> int64_t { return r0 + (t * NG + grp) * RS + q; };
+    auto row_of = [&](int64_t t, int q) -> int64_t { return r0 + t * a.step_stride + grp * RS + q; };
     // Loads are issued unconditionally (addresses clamped into the row band and
     // the padded row) so that no branch separates them; rows past the band
     // and columns past the padded row are discarded afterwards.
@@ -131,11 +136,17 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
         }
     };
 
-    // This lane's slices of the working vectors x, v and (when the previous
-    // step is still to be applied) y, padded with zeros to ldA, and the first
-    // rows: none of these loads depends on the state, so they are all in
-    // flight while the state is settled.  yacc holds the slice of y until the
-    // step is applied.
+    // The rows of the first PD steps (from HBM), then this lane's slices of
+    // the working vectors x, v and (when the previous step is still to be
+    // applied) y, padded with zeros to ldA (from L2): none of these loads
+    // depends on the state, so they are all in flight while the state is
+    // settled.  yacc holds the slice of y until the step is applied.
+    uint4 buf[PD][RS][C];
+    double bq[PD][RS], nq[PD][RS];
+#pragma unroll
+    for (int k = 0; k < PD; ++k)
+        if (k < nsteps) load_rows(buf[k], bq[k], nq[k], k);
+
     Acc xr[C][VEC];
     Acc vr[C][VEC];
     Acc yacc[C][VEC];
@@ -162,10 +173,6 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
             }
         }
     }
-    uint4 bufA[RS][C], bufB[RS][C];
-    double bA[RS], nA[RS], bB[RS], nB[RS];
-    if (nsteps > 0) load_rows(bufA, bA, nA, 0);
-
     const State st = sweep_state(a.pd, lane, blockIdx.x == 0 && tid == 0);
     if (a.check_status && st.status != ST_RUNNING) return;
     const bool apply_v = HAS_V && (st.vpend_valid || st.v_idx >= 0);
@@ -262,14 +269,20 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
         }
     };
 
-    for (int64_t t = 0; t < nsteps; t += 2) {
-        if (t + 1 < nsteps) load_rows(bufB, bB, nB, t + 1);
-        mask_cols(bufA);
-        process(bufA, bA, nA, t);
-        if (t + 1 < nsteps) {
-            if (t + 2 < nsteps) load_rows(bufA, bA, nA, t + 2);
-            mask_cols(bufB);
-            process(bufB, bB, nB, t + 1);
+    // A ring of PD steps' rows: while one is reduced the next PD-1 are in
+    // flight, and a buffer is refilled (PD steps ahead) as soon as it has been
+    // reduced.  nsteps is the same for the whole workgroup, so every branch
+    // below is uniform and the barriers inside process() are reached by all
+    // lanes.
+    for (int64_t t = 0; t < nsteps; t += PD) {
+#pragma unroll
+        for (int k = 0; k < PD; ++k) {
+            const int64_t tk = t + k;
+            if (tk < nsteps) {
+                mask_cols(buf[k]);
+                process(buf[k], bq[k], nq[k], tk);
+                if (tk + PD < nsteps) load_rows(buf[k], bq[k], nq[k], tk + PD);
+            }
         }
     }
 
@@ -287,18 +300,40 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
             }
         }
     } else {
-        __shared__ Acc ysh[NG][C * CW];
+        // The row groups' partials meet in LDS and are summed in group order;
+        // chunk c of the result is written by row group c % NG, each lane its
+        // own columns, in whole 16-byte vectors.
+        __shared__ __attribute__((aligned(16))) Acc ysh[NG][C * CW];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) ysh[grp][col_of(c) + e] = yacc[c][e];
+            for (int e = 0; e < VEC; e += AV) {
+                uint4 w;
+                __builtin_memcpy(&w, &yacc[c][e], 16);
+                *reinterpret_cast<uint4 *>(&ysh[grp][col_of(c) + e]) = w;
+            }
         }
         __syncthreads();
-        for (int col = tid; col < C * CW; col += BLOCK) {
-            Acc acc = (Acc)0;
 #pragma unroll
-            for (int g = 0; g < NG; ++g) acc += ysh[g][col];
-            part[col] = acc;
+        for (int c = 0; c < C; ++c) {
+            if (c % NG != grp) continue;
+#pragma unroll
+            for (int e = 0; e < VEC; e += AV) {
+                Acc sum[AV];
+#pragma unroll
+                for (int k = 0; k < AV; ++k) sum[k] = (Acc)0;
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    Acc t[AV];
+                    const uint4 u = *reinterpret_cast<const uint4 *>(&ysh[g][col_of(c) + e]);
+                    __builtin_memcpy(t, &u, 16);
+#pragma unroll
+                    for (int k = 0; k < AV; ++k) sum[k] += t[k];
+                }
+                uint4 w;
+                __builtin_memcpy(&w, sum, 16);
+                *reinterpret_cast<uint4 *>(part + col_of(c) + e) = w;
+            }
         }
     }
 

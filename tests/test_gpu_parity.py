@@ -52,18 +52,26 @@ def test_eval_sweep_matches_oracle(P, dtype, n, m):
     check_sweep(sys_.A, dtype, o, g.y, g.h, g.max_viol, g.r, label=f"{dtype} {n}x{m}")
 
 
-ALL_SHAPES = {
-    "f64": [(256, 64, 1, 1), (256, 64, 2, 1), (256, 64, 4, 1), (256, 64, 1, 2), (256, 64, 2, 2),
-            (256, 64, 4, 2), (256, 256, 2, 1), (256, 256, 4, 1), (256, 256, 8, 1), (256, 256, 2, 2),
-            (256, 256, 4, 2), (512, 512, 2, 1), (512, 512, 4, 1), (512, 512, 8, 1), (512, 512, 2, 2),
-            (512, 512, 4, 2)],
-    "f32": [(256, 64, 1, 1), (256, 64, 2, 1), (256, 64, 4, 1), (256, 64, 1, 2), (256, 64, 2, 2),
-            (256, 64, 4, 2), (256, 256, 2, 1), (256, 256, 4, 1), (256, 256, 8, 1), (256, 256, 2, 2),
-            (256, 256, 4, 2), (256, 256, 2, 4), (512, 512, 2, 1), (512, 512, 4, 1), (512, 512, 8, 1),
-            (512, 512, 2, 2), (512, 512, 4, 2), (512, 512, 2, 4), (1024, 1024, 2, 1)],
-    "bf16": [(256, 64, 1, 1), (256, 64, 2, 1), (256, 64, 4, 1), (256, 64, 1, 2), (256, 64, 2, 2),
-             (256, 256, 2, 1), (256, 256, 4, 1), (256, 256, 2, 2), (512, 512, 2, 1), (512, 512, 4, 1),
-             (512, 512, 2, 2)],
+ALL_SHAPES = {  # (block, lanes per row, chunks, rows per step, depth), as compiled
+    "f64": [
+            (256, 64, 1, 1, 2), (256, 64, 2, 1, 2), (256, 64, 4, 1, 2), (256, 64, 1, 2, 2), (256, 64, 2, 2, 2),
+            (256, 64, 4, 2, 2), (256, 256, 2, 1, 2), (256, 256, 4, 1, 2), (256, 256, 8, 1, 2), (256, 256, 2, 2, 2),
+            (256, 256, 4, 2, 2), (512, 512, 2, 1, 2), (512, 512, 4, 1, 2), (512, 512, 8, 1, 2),
+            (512, 512, 2, 2, 2), (512, 512, 4, 2, 2)],
+    "f32": [
+            (256, 64, 1, 1, 2), (256, 64, 2, 1, 2), (256, 64, 4, 1, 2), (256, 64, 1, 2, 2), (256, 64, 2, 2, 2),
+            (256, 64, 4, 2, 2), (256, 256, 2, 1, 2), (256, 256, 4, 1, 2), (256, 256, 8, 1, 2), (256, 256, 2, 2, 2),
+            (256, 256, 4, 2, 2), (256, 256, 2, 4, 2), (512, 512, 2, 1, 2), (512, 512, 4, 1, 2),
+            (512, 512, 8, 1, 2), (512, 512, 2, 2, 2), (512, 512, 4, 2, 2), (512, 512, 2, 4, 2),
+            (1024, 1024, 2, 1, 2), (512, 256, 8, 1, 2), (512, 256, 4, 1, 2),
+            (512, 512, 4, 1, 3), (512, 512, 4, 1, 4), (512, 512, 4, 2, 3), (1024, 1024, 2, 1, 3),
+            (1024, 1024, 2, 1, 4)],
+    "bf16": [
+            (256, 64, 1, 1, 2), (256, 64, 2, 1, 2), (256, 64, 4, 1, 2), (256, 64, 1, 2, 2), (256, 64, 2, 2, 2),
+            (256, 256, 2, 1, 2), (256, 256, 4, 1, 2), (256, 256, 2, 2, 2), (512, 512, 2, 1, 2),
+            (512, 512, 4, 1, 2), (512, 512, 2, 2, 2), (1024, 1024, 1, 1, 2), (1024, 1024, 1, 1, 4),
+            (256, 256, 4, 1, 3), (256, 256, 4, 1, 4), (512, 512, 2, 2, 3), (512, 512, 4, 1, 3),
+            (512, 512, 4, 1, 4)],
 }
 VEC = {"f64": 2, "f32": 4, "bf16": 8}
 
@@ -79,15 +87,18 @@ def test_every_kernel_shape_and_grid(P, dtype):
     ys = []
     with P.Solver() as s:
         s.set_system(sys_.A, sys_.b, dtype=dtype)
-        for (blk, lpr, ch, rs) in ALL_SHAPES[dtype]:
+        for (blk, lpr, ch, rs, pd) in ALL_SHAPES[dtype]:
             if lpr * VEC[dtype] * ch < n:
                 continue
-            for grid in (0, 7):
-                say(f"shape dtype={dtype} block={blk} lpr={lpr} chunks={ch} rows/step={rs} grid={grid}")
-                s.set_tile(blk, lpr, ch, grid, rs)
+            for grid, il in ((0, 0), (7, 0), (0, 1), (5, 1)):
+                say(f"shape dtype={dtype} block={blk} lpr={lpr} chunks={ch} rows/step={rs} depth={pd} "
+                    f"interleave={il} grid={grid}")
+                s.set_tile(blk, lpr, ch, grid, rs, depth=pd, interleave=il)
+                t = s.get_tile()
+                assert t["depth"] == pd and t["interleave"] == il
                 g = s.eval_sweep(x)
                 check_sweep(sys_.A, dtype, o, g.y, g.h, g.max_viol, g.r,
-                            label=f"{dtype} {blk}/{lpr}/{ch}/{rs}/{grid}")
+                            label=f"{dtype} {blk}/{lpr}/{ch}/{rs}/{pd}/{il}/{grid}")
                 ys.append(g.y)
     assert len(ys) >= 4
 
@@ -469,8 +480,8 @@ def test_autotune_keeps_parity_and_caches(P, tmp_path, monkeypatch):
     with P.Solver() as s2:
         s2.set_system(sys_.A, sys_.b, dtype="f32")
         t2 = s2.get_tile()
-        assert (t2["block"], t2["lanes_per_row"], t2["chunks"], t2["rows_per_step"], t2["grid"]) == \
-               (best["block"], best["lanes_per_row"], best["chunks"], best["rows_per_step"], best["grid"])
+        keys = ("block", "lanes_per_row", "chunks", "rows_per_step", "depth", "interleave", "grid")
+    assert tuple(t2[k] for k in keys) == tuple(best[k] for k in keys)
 
 
 SPLIT = {"f64": (256, 256, 8), "f32": (256, 256, 8), "bf16": (256, 256, 4)}
