@@ -215,6 +215,109 @@ modap_status modap_get_tile(modap_ctx *ctx, modap_tile *tile);
  * Errors: E_STATE, E_INVAL (reps < 1), E_DEVICE. */
 modap_status modap_autotune(modap_ctx *ctx, int reps, modap_tile *best);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent systems of uneven size advanced together.
+ *
+ * Every system of a batch is the problem above (its own data, x, drift,
+ * updates, stop test and step, with the same parameters for all), and one
+ * iteration of the batch is one iteration of every system that is still
+ * running.  All systems of a batch share one storage type.  The sweeps of all
+ * systems run in one persistent kernel launch: work items (bands of rows of
+ * one system) are taken from a device queue, one wavefront per row; then one
+ * launch reduces every system's y and applies its step.  Each item writes its
+ * own partial sums, so a system's results are the same, bit for bit, whatever
+ * other systems share the batch.  Rows are limited to 2048 (FP32), 4096
+ * (BF16) or 1024 (FP64) elements; longer systems use a single-system context.
+ * Conventions (ownership, ptrs_on_device, ordering, layout, precision) are
+ * those of the single-system calls.
+ * ------------------------------------------------------------------------ */
+typedef struct modap_batch modap_batch;
+
+typedef struct {
+    int64_t iters;          /* batch iterations queued by this call */
+    int64_t running;        /* systems still iterating after the call */
+    int64_t systems;        /* systems in the batch */
+    double seconds;         /* host wall time of this call */
+    double hbm_bytes;       /* algorithmic bytes of the sweeps of this call (as in modap_stats,
+                               counting every system queued) */
+    double sweep_ms;        /* profile: summed duration of the batch sweep kernels */
+    double reduce_ms;       /* profile: summed duration of the batch reductions */
+    int64_t profiled;       /* profile: iterations timed */
+} modap_batch_stats;
+
+/* Batch tuning: target bytes of A per work item for each row-length bucket
+ * (rows of at most 64*VEC*C elements, C = 1, 2, 4, 8, VEC = 16 bytes / element
+ * size), and the persistent grid (0 = one full occupancy of the device). */
+typedef struct {
+    int32_t item_kib[4];    /* KiB of A per work item, buckets C = 1, 2, 4, 8 (>= 1) */
+    int32_t grid;           /* workgroups of the batch sweep (0: the library's choice) */
+} modap_batch_tile;
+
+/* Create an empty batch for systems stored in `storage` on HIP device
+ * `device`, queuing on hip_stream (NULL: the device's default stream).
+ * Errors: E_INVAL, E_DEVICE, E_NOMEM. */
+modap_status modap_batch_create(int device, void *hip_stream, modap_dtype storage, modap_batch **out);
+
+/* Release the batch and every system in it.  NULL is a no-op. */
+void modap_batch_destroy(modap_batch *batch);
+
+/* Add the system A x <= b with starting point x0 (NULL = 0), laid out as for
+ * modap_set_system; *id receives its handle.  The system joins the batch at
+ * the next iteration, with fresh counters.  Synchronises.  Errors: E_INVAL
+ * (sizes, NULL, lda < n, rows longer than the batched sweep covers,
+ * non-finite b or x0), E_ZERO_ROW, E_NOMEM, E_DEVICE. */
+modap_status modap_batch_add(modap_batch *batch, int64_t m, int64_t n, const void *A, int64_t lda,
+                             const double *b, const double *x0, int ptrs_on_device, int64_t *id);
+
+/* Remove a system from the batch and free its memory.  Errors: E_INVAL (unknown id). */
+modap_status modap_batch_remove(modap_batch *batch, int64_t id);
+
+/* Drift schedule of one system (see modap_set_drift).  Errors: E_INVAL, E_NOMEM. */
+modap_status modap_batch_set_drift(modap_batch *batch, int64_t id, int64_t T, const double *V, int64_t ldv,
+                                   int ptrs_on_device);
+
+/* Data update of one system between iterations (see modap_update_coeffs).
+ * Errors: E_INVAL, E_ZERO_ROW. */
+modap_status modap_batch_update(modap_batch *batch, int64_t id, int64_t k, const int64_t *rows,
+                                const void *new_rows, const double *new_b, const double *translate_v,
+                                int ptrs_on_device);
+
+/* Queue k iterations of every running system (see modap_iterate); out may be
+ * NULL (then the call does not wait).  Errors: E_STATE (empty batch), E_INVAL,
+ * E_DEVICE. */
+modap_status modap_batch_iterate(modap_batch *batch, const modap_params *params, int64_t k,
+                                 modap_batch_stats *out);
+
+/* Iterate until no system is running: each stops on its own when
+ * eps-feasible, after max_iters steps, without a step direction or on a
+ * NaN/Inf; the per-system outcome is read with modap_batch_query.  The host
+ * reads the number of running systems once per batch of queued iterations.
+ * out may be NULL.  Errors: E_STATE, E_INVAL, E_DEVICE. */
+modap_status modap_batch_solve(modap_batch *batch, const modap_params *params, modap_batch_stats *out);
+
+/* Read one system's x ([n]), b ([m], pending translations applied) and
+ * statistics (out->state, iters, max_viol, ...; seconds and the profile
+ * fields are 0).  Any of x, b, out may be NULL.  Synchronises.
+ * Errors: E_INVAL (unknown id), E_DEVICE. */
+modap_status modap_batch_query(modap_batch *batch, int64_t id, double *x, double *b, modap_stats *out,
+                               int ptrs_on_device);
+
+/* Set (tile != NULL) or reset (NULL) the batch tuning, or read it (the
+ * grid as requested; a launch never uses more workgroups than there are work
+ * items).  Errors: E_INVAL. */
+modap_status modap_batch_set_tile(modap_batch *batch, const modap_batch_tile *tile);
+modap_status modap_batch_get_tile(modap_batch *batch, modap_batch_tile *tile);
+
+/* Autotuner of the batch: for each row-length bucket present, the item size
+ * (KiB of A per work item, from 32 to 1024) and then the grid are chosen by
+ * timing `reps` stateless batch sweeps of the current systems (their state
+ * is not changed); the result is kept and returned in *best (may be NULL).
+ * Synchronises.  Errors: E_STATE (empty batch), E_INVAL, E_DEVICE. */
+modap_status modap_batch_autotune(modap_batch *batch, int reps, modap_batch_tile *best);
+
+/* Message describing the last failing call on the batch. */
+const char *modap_batch_last_error(modap_batch *batch);
+
 /* Message for a status code (static storage). */
 const char *modap_strerror(modap_status status);
 

@@ -31,7 +31,11 @@ STATE_NAMES = {0: "running", 1: "converged", 2: "no_direction", 3: "numeric", 4:
 # every symbol declared in include/modap.h
 EXPORTS = ["modap_create", "modap_destroy", "modap_set_system", "modap_set_x", "modap_update_coeffs",
            "modap_set_drift", "modap_iterate", "modap_solve", "modap_eval_sweep", "modap_query",
-           "modap_set_tile", "modap_get_tile", "modap_autotune", "modap_strerror", "modap_last_error"]
+           "modap_set_tile", "modap_get_tile", "modap_autotune", "modap_strerror", "modap_last_error",
+           "modap_batch_create", "modap_batch_destroy", "modap_batch_add", "modap_batch_remove",
+           "modap_batch_set_drift", "modap_batch_update", "modap_batch_iterate", "modap_batch_solve",
+           "modap_batch_query", "modap_batch_set_tile", "modap_batch_get_tile", "modap_batch_autotune",
+           "modap_batch_last_error"]
 
 
 class Params(C.Structure):
@@ -60,6 +64,22 @@ class Tile(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("running", C.c_int64), ("systems", C.c_int64),
+                ("seconds", C.c_double), ("hbm_bytes", C.c_double), ("sweep_ms", C.c_double),
+                ("reduce_ms", C.c_double), ("profiled", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchTile(C.Structure):
+    _fields_ = [("item_kib", C.c_int32 * 4), ("grid", C.c_int32)]
+
+    def as_dict(self):
+        return {"item_kib": list(self.item_kib), "grid": self.grid}
 
 
 class ModapError(RuntimeError):
@@ -98,8 +118,24 @@ def lib():
         L.modap_strerror.restype = C.c_char_p
         L.modap_last_error.argtypes = [vp]
         L.modap_last_error.restype = C.c_char_p
+        L.modap_batch_create.argtypes = [i32, vp, i32, C.POINTER(vp)]
+        L.modap_batch_destroy.argtypes = [vp]
+        L.modap_batch_destroy.restype = None
+        L.modap_batch_add.argtypes = [vp, i64, i64, vp, i64, dp, dp, i32, C.POINTER(C.c_int64)]
+        L.modap_batch_remove.argtypes = [vp, i64]
+        L.modap_batch_set_drift.argtypes = [vp, i64, i64, dp, i64, i32]
+        L.modap_batch_update.argtypes = [vp, i64, i64, vp, vp, dp, dp, i32]
+        L.modap_batch_iterate.argtypes = [vp, C.POINTER(Params), i64, C.POINTER(BatchStats)]
+        L.modap_batch_solve.argtypes = [vp, C.POINTER(Params), C.POINTER(BatchStats)]
+        L.modap_batch_query.argtypes = [vp, i64, dp, dp, C.POINTER(Stats), i32]
+        L.modap_batch_set_tile.argtypes = [vp, C.POINTER(BatchTile)]
+        L.modap_batch_get_tile.argtypes = [vp, C.POINTER(BatchTile)]
+        L.modap_batch_autotune.argtypes = [vp, i32, C.POINTER(BatchTile)]
+        L.modap_batch_last_error.argtypes = [vp]
+        L.modap_batch_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("modap_destroy", "modap_strerror", "modap_last_error"):
+            if name not in ("modap_destroy", "modap_strerror", "modap_last_error", "modap_batch_destroy",
+                            "modap_batch_last_error"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -315,4 +351,122 @@ class Solver:
     def get_tile(self):
         t = Tile()
         self._check(lib().modap_get_tile(self._ctx, C.byref(t)))
+        return t.as_dict()
+
+
+class Batch:
+    """Many independent systems of one storage type advanced together: one
+    persistent sweep launch and one reduction launch per iteration for all of
+    them (modap_batch_* of the C ABI)."""
+
+    def __init__(self, dtype="f32", device: int = 0, stream=None):
+        L = lib()
+        self.device = int(device)
+        self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        if stream is None:
+            try:
+                import torch
+                stream = torch.cuda.current_stream(self.device).cuda_stream
+            except Exception:
+                stream = None
+        h = C.c_void_p()
+        st = L.modap_batch_create(self.device, C.c_void_p(int(stream)) if stream else None, self.dtype, C.byref(h))
+        if st != OK:
+            raise ModapError(st, L.modap_strerror(st).decode())
+        self._h = h
+        self.shapes = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().modap_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st):
+        if st != OK:
+            raise ModapError(st, lib().modap_batch_last_error(self._h).decode())
+
+    def add(self, A, b, x0=None):
+        """Add a system; returns its id."""
+        m, n = int(A.shape[0]), int(A.shape[1])
+        g = _Args(self.device)
+        pa = g.ptr(A, _NP_STORE[self.dtype], m * n)
+        pb = g.ptr(b, np.float64, m)
+        px = g.ptr(x0, np.float64, n)
+        i = C.c_int64()
+        self._check(lib().modap_batch_add(self._h, m, n, pa, n, pb, px, g.on_dev, C.byref(i)))
+        self.shapes[i.value] = (m, n)
+        return i.value
+
+    def remove(self, sid):
+        self._check(lib().modap_batch_remove(self._h, int(sid)))
+        self.shapes.pop(int(sid), None)
+
+    def set_drift(self, sid, V=None):
+        n = self.shapes.get(int(sid), (0, 0))[1]
+        g = _Args(self.device)
+        T = 0 if V is None else int(V.shape[0])
+        pv = g.ptr(V, np.float64, T * n) if T else None
+        self._check(lib().modap_batch_set_drift(self._h, int(sid), T, pv, n, g.on_dev))
+
+    def update(self, sid, rows=None, new_rows=None, new_b=None, translate=None):
+        n = self.shapes.get(int(sid), (0, 0))[1]
+        g = _Args(self.device)
+        k = 0 if rows is None else int(len(rows))
+        pr = g.ptr(rows, np.int64, k) if k else None
+        pn = g.ptr(new_rows, _NP_STORE[self.dtype], k * n) if k else None
+        pb = g.ptr(new_b, np.float64, k) if k else None
+        pv = g.ptr(translate, np.float64, n)
+        self._check(lib().modap_batch_update(self._h, int(sid), k, pr, pn, pb, pv, g.on_dev))
+
+    def iterate(self, k, prm=None, stats=True):
+        prm = prm or params()
+        out = BatchStats() if stats else None
+        self._check(lib().modap_batch_iterate(self._h, C.byref(prm), int(k), C.byref(out) if stats else None))
+        return out
+
+    def solve(self, prm=None):
+        prm = prm or params()
+        out = BatchStats()
+        self._check(lib().modap_batch_solve(self._h, C.byref(prm), C.byref(out)))
+        return out
+
+    def query(self, sid, want_x=True, want_b=False):
+        m, n = self.shapes.get(int(sid), (0, 0))   # an unknown id is reported by the library
+        x = np.empty(n) if want_x else None
+        b = np.empty(m) if want_b else None
+        out = Stats()
+        g = _Args(self.device)
+        px = g.ptr(x, np.float64) if want_x else None
+        pb = g.ptr(b, np.float64) if want_b else None
+        self._check(lib().modap_batch_query(self._h, int(sid), px, pb, C.byref(out), 0))
+        return x, b, out
+
+    def set_tile(self, item_kib=None, grid=0):
+        if item_kib is None and grid == 0:
+            self._check(lib().modap_batch_set_tile(self._h, None))
+            return
+        kib = list(item_kib) if item_kib is not None else [256] * 4
+        t = BatchTile((C.c_int32 * 4)(*[int(v) for v in kib]), int(grid))
+        self._check(lib().modap_batch_set_tile(self._h, C.byref(t)))
+
+    def get_tile(self):
+        t = BatchTile()
+        self._check(lib().modap_batch_get_tile(self._h, C.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, reps=3):
+        t = BatchTile()
+        self._check(lib().modap_batch_autotune(self._h, int(reps), C.byref(t)))
         return t.as_dict()

@@ -1,0 +1,850 @@
+// Host half of the batched C ABI (modap_batch_* in include/modap.h) and the
+// instantiation of the batch kernels.
+//
+// A batch owns, per system, the same device data as a single-system context
+// (rows padded to a 16-byte multiple, b, ||a_i||^2, x, y, the one-shot
+// translation, the drift schedule, the working vectors, a control block, the
+// totals and the norm parts of y), and for the whole batch the tables the
+// kernels read: one descriptor per system, the system of every work item,
+// the 64-column blocks of the reduction, the per-item partials and the item
+// queue.  The tables are rebuilt at the start of a call after systems were
+// added or removed or the tuning changed.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "aux_launch.hpp"
+#include "batch_kernels.hpp"
+#include "host_common.hpp"
+#include "modap.h"
+
+using namespace modap;
+using namespace modap_host;
+
+namespace {
+
+struct BSys {
+    bool alive = false;
+    int64_t m = 0, n = 0, ldA = 0;
+    void *A = nullptr;
+    double *b = nullptr, *nu = nullptr, *x = nullptr, *y = nullptr, *vpend = nullptr, *V = nullptr;
+    int64_t T = 0;
+    void *work = nullptr;
+    Ctrl *ctl = nullptr;
+    Totals *tot = nullptr;
+    double *ynp = nullptr;
+    int C = 0;
+    bool vpend_maybe = false;
+};
+
+constexpr int kBuckets[4] = {1, 2, 4, 8};
+
+int bucket_of(int C) { return C == 1 ? 0 : C == 2 ? 1 : C == 4 ? 2 : 3; }
+
+}  // namespace
+
+struct modap_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int cu_count = 0;
+    std::string err;
+    int dt = 1;
+    size_t es = 4;
+    std::vector<BSys> sys;
+    int64_t jn = 0;
+    modap_batch_tile tile{{64, 256, 256, 1024}, 0};   // what the autotuner finds for FP32 rows up to 2048
+
+    // tables of the current membership (rebuilt when dirty)
+    bool dirty = true;
+    std::vector<int32_t> order;            // alive system ids in table order
+    std::vector<BatchSys> h_sys;
+    std::vector<int32_t> h_item_sys;
+    std::vector<BatchCol> h_cols;
+    BatchSys *d_sys = nullptr;
+    size_t sys_cap = 0;
+    int32_t *d_item_sys = nullptr;
+    size_t item_cap = 0;
+    BatchCol *d_cols = nullptr;
+    size_t cols_cap = 0;
+    void *part = nullptr;
+    size_t part_bytes = 0;
+    int64_t *h_part = nullptr;
+    double *dmax_part = nullptr, *binf_part = nullptr;
+    int nitems = 0;
+    double bytes_per_iter = 0.0;
+    int grid = 0;
+
+    int32_t *queue = nullptr;
+    int *d_count = nullptr;
+    int *h_count = nullptr;               // pinned [2]
+    unsigned long long *bad = nullptr;
+    int *flag = nullptr;
+    void *stage = nullptr;
+    size_t stage_bytes = 0;
+    std::vector<hipEvent_t> events;
+    hipEvent_t sync_ev[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+modap_status b_to_device(modap_batch *c, void *dst, const void *src, size_t bytes, int on_dev) {
+    if (bytes == 0) return MODAP_OK;
+    HIP_TRY(c, hipMemcpyAsync(dst, src, bytes, on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+    return MODAP_OK;
+}
+
+modap_status b_from_device(modap_batch *c, void *dst, const void *src, size_t bytes, int on_dev) {
+    if (bytes == 0) return MODAP_OK;
+    HIP_TRY(c, hipMemcpyAsync(dst, src, bytes, on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    return MODAP_OK;
+}
+
+void release_sys(BSys &s) {
+    free_dev(s.A);
+    free_dev(s.b);
+    free_dev(s.nu);
+    free_dev(s.x);
+    free_dev(s.y);
+    free_dev(s.vpend);
+    free_dev(s.V);
+    free_dev(s.work);
+    free_dev(s.ctl);
+    free_dev(s.tot);
+    free_dev(s.ynp);
+    s.alive = false;
+    s.T = 0;
+}
+
+modap_status check_batch(modap_batch *c) {
+    if (!c) return MODAP_E_INVAL;
+    return MODAP_OK;
+}
+
+BSys *find_sys(modap_batch *c, int64_t id) {
+    if (id < 0 || id >= (int64_t)c->sys.size() || !c->sys[(size_t)id].alive) return nullptr;
+    return &c->sys[(size_t)id];
+}
+
+// Largest row (padded length) the batched sweep covers.
+int64_t max_row(int dt) { return 64 * (int64_t)vec_elems(dt) * kBatchCmax; }
+
+int chunks_for(int dt, int64_t ldA) {
+    for (int C : kBuckets)
+        if (64 * (int64_t)vec_elems(dt) * C >= ldA) return C;
+    return 0;
+}
+
+modap_status ensure_stage(modap_batch *c, size_t bytes) {
+    if (bytes <= c->stage_bytes) return MODAP_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    free_dev(c->stage);
+    HIP_TRY(c, hipMalloc(&c->stage, bytes));
+    c->stage_bytes = bytes;
+    return MODAP_OK;
+}
+
+template <typename P>
+modap_status ensure_buf(modap_batch *c, P *&p, size_t &cap, size_t count) {
+    if (count <= cap) return MODAP_OK;
+    free_dev(p);
+    const size_t want = std::max(count, cap * 2);
+    HIP_TRY(c, hipMalloc(&p, sizeof(P) * want));
+    cap = want;
+    return MODAP_OK;
+}
+
+// Rows of one work item of a system: about item_kib KiB of A, a multiple of
+// the wavefronts of a workgroup.
+int64_t rows_per_item(const modap_batch *c, const BSys &s) {
+    const int64_t kib = std::max<int32_t>(1, c->tile.item_kib[bucket_of(s.C)]);
+    int64_t r = kib * 1024 / (s.ldA * (int64_t)c->es);
+    r = std::max<int64_t>(kBatchWaves, (r + kBatchWaves - 1) / kBatchWaves * kBatchWaves);
+    return std::min<int64_t>(r, (s.m + kBatchWaves - 1) / kBatchWaves * kBatchWaves);
+}
+
+modap_status rebuild(modap_batch *c) {
+    if (!c->dirty) return MODAP_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));  // the previous tables may still be read
+    c->order.clear();
+    c->h_sys.clear();
+    c->h_item_sys.clear();
+    c->h_cols.clear();
+    int64_t items = 0, part = 0;
+    double bytes = 0.0;
+    for (size_t id = 0; id < c->sys.size(); ++id) {
+        const BSys &s = c->sys[id];
+        if (!s.alive) continue;
+        BatchSys d{};
+        d.A = s.A;
+        d.ldA = s.ldA;
+        d.m = s.m;
+        d.n = s.n;
+        d.b = s.b;
+        d.nu = s.nu;
+        d.x = s.x;
+        d.y = s.y;
+        d.vpend = s.vpend;
+        d.V = s.T > 0 ? s.V : nullptr;
+        d.work = s.work;
+        d.ctl = s.ctl;
+        d.tot = s.tot;
+        d.ynp = s.ynp;
+        d.R = (int32_t)((s.n + 63) / 64);
+        d.C = s.C;
+        d.rows_per_item = rows_per_item(c, s);
+        d.item0 = items;
+        d.nitems = (s.m + d.rows_per_item - 1) / d.rows_per_item;
+        d.part0 = part;
+        const int32_t idx = (int32_t)c->h_sys.size();
+        for (int64_t q = 0; q < d.nitems; ++q) c->h_item_sys.push_back(idx);
+        for (int32_t blk = 0; blk < d.R; ++blk) c->h_cols.push_back(BatchCol{idx, blk});
+        items += d.nitems;
+        part += d.nitems * s.ldA;
+        bytes += (double)s.m * (double)s.n * (double)c->es + 24.0 * (double)s.m;
+        c->h_sys.push_back(d);
+        c->order.push_back((int32_t)id);
+    }
+    c->nitems = (int)items;
+    c->bytes_per_iter = bytes;
+    modap_status st;
+    if ((st = ensure_buf(c, c->d_sys, c->sys_cap, std::max<size_t>(1, c->h_sys.size())))) return st;
+    size_t cap = c->item_cap;
+    if ((st = ensure_buf(c, c->d_item_sys, cap, std::max<size_t>(1, (size_t)items)))) return st;
+    if (cap != c->item_cap) {
+        size_t c2 = 0, c3 = 0, c4 = 0;
+        free_dev(c->h_part);
+        free_dev(c->dmax_part);
+        free_dev(c->binf_part);
+        if ((st = ensure_buf(c, c->h_part, c2, cap)) || (st = ensure_buf(c, c->dmax_part, c3, cap)) ||
+            (st = ensure_buf(c, c->binf_part, c4, cap)))
+            return st;
+        c->item_cap = cap;
+    }
+    if ((st = ensure_buf(c, c->d_cols, c->cols_cap, std::max<size_t>(1, c->h_cols.size())))) return st;
+    const size_t pbytes = std::max<size_t>(16, (size_t)part * acc_size(c->dt));
+    if (pbytes > c->part_bytes) {
+        free_dev(c->part);
+        HIP_TRY(c, hipMalloc(&c->part, pbytes));
+        c->part_bytes = pbytes;
+    }
+    if (!c->h_sys.empty()) {
+        HIP_TRY(c, hipMemcpyAsync(c->d_sys, c->h_sys.data(), sizeof(BatchSys) * c->h_sys.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->d_item_sys, c->h_item_sys.data(), sizeof(int32_t) * c->h_item_sys.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->d_cols, c->h_cols.data(), sizeof(BatchCol) * c->h_cols.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+    }
+    // persistent grid: one full occupancy of the device unless tuned
+    int per_cu = 0;
+    const void *f = c->dt == 0 ? reinterpret_cast<const void *>(&sweep_batch<0>)
+                  : c->dt == 1 ? reinterpret_cast<const void *>(&sweep_batch<1>)
+                               : reinterpret_cast<const void *>(&sweep_batch<2>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    c->grid = c->tile.grid > 0 ? c->tile.grid : c->cu_count * per_cu;
+    c->grid = std::max(1, std::min(c->grid, std::max(1, c->nitems)));
+    c->dirty = false;
+    return MODAP_OK;
+}
+
+BatchArgs batch_args(modap_batch *c) {
+    BatchArgs a{};
+    a.sys = c->d_sys;
+    a.nsys = (int32_t)c->h_sys.size();
+    a.nitems = c->nitems;
+    a.item_sys = c->d_item_sys;
+    a.part = c->part;
+    a.h_part = c->h_part;
+    a.dmax_part = c->dmax_part;
+    a.binf_part = c->binf_part;
+    a.queue = c->queue;
+    a.j = c->jn;
+    a.check_status = 1;
+    a.write_b = 1;
+    return a;
+}
+
+Decide decide_of(const modap_params *p, int track) {
+    Decide d{};
+    d.lambda = p->lambda;
+    d.eps = p->eps;
+    d.eps_relative = p->eps_relative;
+    d.rule = p->step == MODAP_STEP_AVG ? 1 : 0;
+    d.track = track;
+    return d;
+}
+
+modap_status check_params(modap_batch *c, const modap_params *p) {
+    if (!p) return fail(c, MODAP_E_INVAL, "params is NULL");
+    if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return fail(c, MODAP_E_INVAL, "lambda must be finite and > 0");
+    if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(c, MODAP_E_INVAL, "eps must be finite and > 0");
+    if (p->step != MODAP_STEP_FIXED && p->step != MODAP_STEP_AVG) return fail(c, MODAP_E_INVAL, "unknown step rule");
+    if (p->max_iters < 0) return fail(c, MODAP_E_INVAL, "max_iters must be >= 0");
+    if (p->profile < 0) return fail(c, MODAP_E_INVAL, "profile must be >= 0");
+    return MODAP_OK;
+}
+
+hipEvent_t event_at(modap_batch *c, size_t i) {
+    while (c->events.size() <= i) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->events.push_back(e);
+    }
+    return c->events[i];
+}
+
+modap_status launch(modap_batch *c, const void *f, int grid, int block, BatchArgs a, hipEvent_t e0, hipEvent_t e1,
+                    const BatchCol *cols = nullptr, int64_t extra = 0, bool with_cols = false,
+                    bool with_i64 = false) {
+    void *args3[] = {&a, &cols};
+    void *args2[] = {&a, &extra};
+    void *args1[] = {&a};
+    void **args = with_cols ? args3 : with_i64 ? args2 : args1;
+    HIP_TRY(c, hipExtLaunchKernel(f, dim3(grid), dim3(block), args, 0, c->stream, e0, e1, 0));
+    return MODAP_OK;
+}
+
+const void *sweep_fn(int dt) {
+    return dt == 0 ? reinterpret_cast<const void *>(&sweep_batch<0>)
+         : dt == 1 ? reinterpret_cast<const void *>(&sweep_batch<1>)
+                   : reinterpret_cast<const void *>(&sweep_batch<2>);
+}
+const void *reduce_fn(int dt) {
+    return dt == 0 ? reinterpret_cast<const void *>(&reduce_batch<double>)
+                   : reinterpret_cast<const void *>(&reduce_batch<float>);
+}
+const void *prime_fn(int dt) {
+    return dt == 0 ? reinterpret_cast<const void *>(&prime_batch<double>)
+                   : reinterpret_cast<const void *>(&prime_batch<float>);
+}
+
+// Call start: clear stops of earlier calls, set the step limit, prime the
+// working vectors and empty the queue.
+modap_status enqueue_begin(modap_batch *c, int64_t max_steps) {
+    BatchArgs a = batch_args(c);
+    const int nsys = a.nsys;
+    modap_status st;
+    if ((st = launch(c, reinterpret_cast<const void *>(&begin_batch), (nsys + 255) / 256, 256, a, nullptr, nullptr,
+                     nullptr, max_steps, false, true)))
+        return st;
+    return launch(c, prime_fn(c->dt), nsys, 256, a, nullptr, nullptr);
+}
+
+modap_status enqueue_iteration(modap_batch *c, const modap_params *p, int track, int64_t i, size_t *ev_used,
+                               double *bytes) {
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (p->profile > 0 && i % p->profile == 0) {
+        for (int k = 0; k < 4; ++k) {
+            ev[k] = event_at(c, *ev_used + k);
+            if (!ev[k]) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
+        }
+        *ev_used += 4;
+    }
+    BatchArgs a = batch_args(c);
+    a.decide = i > 0;
+    a.apply_step = i > 0;
+    a.dp = decide_of(p, track);
+    modap_status st;
+    if ((st = launch(c, sweep_fn(c->dt), c->grid, 256, a, ev[0], ev[1]))) return st;
+    if ((st = launch(c, reduce_fn(c->dt), (int)c->h_cols.size(), 256, a, ev[2], ev[3], c->d_cols, 0, true)))
+        return st;
+    c->jn += 1;
+    *bytes += c->bytes_per_iter;
+    return MODAP_OK;
+}
+
+modap_status enqueue_settle(modap_batch *c, const modap_params *p, int track) {
+    BatchArgs a = batch_args(c);
+    a.j = c->jn - 1;
+    a.dp = decide_of(p, track);
+    return launch(c, reinterpret_cast<const void *>(&settle_batch), a.nsys, 256, a, nullptr, nullptr);
+}
+
+modap_status profile_totals(modap_batch *c, size_t ev_used, modap_batch_stats *o) {
+    double sw = 0.0, rd = 0.0;
+    int64_t cnt = 0;
+    for (size_t i = 0; i + 3 < ev_used; i += 4) {
+        float x = 0.f, y = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&x, c->events[i], c->events[i + 1]));
+        HIP_TRY(c, hipEventElapsedTime(&y, c->events[i + 2], c->events[i + 3]));
+        sw += x;
+        rd += y;
+        ++cnt;
+    }
+    o->sweep_ms = sw;
+    o->reduce_ms = rd;
+    o->profiled = cnt;
+    return MODAP_OK;
+}
+
+modap_status count_running_now(modap_batch *c, int slot_index, int *out) {
+    BatchArgs a = batch_args(c);
+    hipLaunchKernelGGL(count_running, dim3(1), dim3(256), 0, c->stream, a, slot_index, c->d_count);
+    LAUNCH_TRY(c, "count_running launch");
+    HIP_TRY(c, hipMemcpyAsync(out, c->d_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    return MODAP_OK;
+}
+
+int last_slot(const modap_batch *c) { return (int)((c->jn - 1) & 1); }
+
+}  // namespace
+
+extern "C" {
+
+modap_status modap_batch_create(int device, void *hip_stream, modap_dtype storage, modap_batch **out) {
+    if (!out) return MODAP_E_INVAL;
+    *out = nullptr;
+    if (storage != MODAP_F64 && storage != MODAP_F32 && storage != MODAP_BF16) return MODAP_E_INVAL;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return MODAP_E_INVAL;
+    modap_batch *c = new (std::nothrow) modap_batch();
+    if (!c) return MODAP_E_NOMEM;
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->dt = (int)storage;
+    c->es = elem_size(c->dt);
+    DeviceGuard g(device);
+    hipDeviceProp_t prop;
+    bool ok = hipGetDeviceProperties(&prop, device) == hipSuccess;
+    if (ok) c->cu_count = prop.multiProcessorCount;
+    ok = ok && hipMalloc(&c->queue, sizeof(int32_t)) == hipSuccess && hipMalloc(&c->d_count, sizeof(int)) == hipSuccess &&
+         hipMalloc(&c->bad, sizeof(unsigned long long)) == hipSuccess && hipMalloc(&c->flag, sizeof(int)) == hipSuccess &&
+         hipHostMalloc(&c->h_count, 2 * sizeof(int)) == hipSuccess &&
+         hipEventCreateWithFlags(&c->sync_ev[0], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&c->sync_ev[1], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        modap_batch_destroy(c);
+        return MODAP_E_DEVICE;
+    }
+    *out = c;
+    return MODAP_OK;
+}
+
+void modap_batch_destroy(modap_batch *c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (BSys &s : c->sys) release_sys(s);
+    free_dev(c->d_sys);
+    free_dev(c->d_item_sys);
+    free_dev(c->d_cols);
+    free_dev(c->part);
+    free_dev(c->h_part);
+    free_dev(c->dmax_part);
+    free_dev(c->binf_part);
+    free_dev(c->queue);
+    free_dev(c->d_count);
+    free_dev(c->bad);
+    free_dev(c->flag);
+    free_dev(c->stage);
+    if (c->h_count) (void)hipHostFree(c->h_count);
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->sync_ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+}
+
+modap_status modap_batch_add(modap_batch *c, int64_t m, int64_t n, const void *A, int64_t lda, const double *b,
+                             const double *x0, int on_dev, int64_t *id) {
+    if (!c) return MODAP_E_INVAL;
+    if (!id) return fail(c, MODAP_E_INVAL, "id is NULL");
+    if (m < 1 || n < 1 || lda < n || !A || !b) return fail(c, MODAP_E_INVAL, "bad sizes or NULL data");
+    const int64_t v = vec_elems(c->dt);
+    const int64_t ldA = (n + v - 1) / v * v;
+    if (ldA > max_row(c->dt))
+        return fail(c, MODAP_E_INVAL, "rows longer than the batched sweep covers (" + std::to_string(max_row(c->dt)) +
+                                          " elements): use a single-system context");
+    if (!on_dev) {
+        if (!all_finite(b, m)) return fail(c, MODAP_E_INVAL, "b has a non-finite entry");
+        if (x0 && !all_finite(x0, n)) return fail(c, MODAP_E_INVAL, "x0 has a non-finite entry");
+    }
+    DeviceGuard g(c->device);
+    BSys s;
+    s.m = m;
+    s.n = n;
+    s.ldA = ldA;
+    s.C = chunks_for(c->dt, ldA);
+    const size_t abytes = (size_t)m * (size_t)ldA * c->es;
+    const size_t vbytes = sizeof(double) * (size_t)ldA;
+    const size_t wbytes = 3 * acc_size(c->dt) * (size_t)ldA;
+    auto cleanup = [&](modap_status st) {
+        release_sys(s);
+        return st;
+    };
+    hipError_t e = hipSuccess;
+    if ((e = hipMalloc(&s.A, abytes)) != hipSuccess || (e = hipMalloc(&s.b, sizeof(double) * m)) != hipSuccess ||
+        (e = hipMalloc(&s.nu, sizeof(double) * m)) != hipSuccess || (e = hipMalloc(&s.x, vbytes)) != hipSuccess ||
+        (e = hipMalloc(&s.y, vbytes)) != hipSuccess || (e = hipMalloc(&s.vpend, vbytes)) != hipSuccess ||
+        (e = hipMalloc(&s.work, wbytes)) != hipSuccess || (e = hipMalloc(&s.ctl, sizeof(Ctrl))) != hipSuccess ||
+        (e = hipMalloc(&s.tot, sizeof(Totals))) != hipSuccess ||
+        (e = hipMalloc(&s.ynp, sizeof(double) * (size_t)((n + 63) / 64))) != hipSuccess)
+        return cleanup(hip_fail(c, e, "hipMalloc"));
+    modap_status st = MODAP_OK;
+    auto q = [&](hipError_t r, const char *what) {
+        if (r != hipSuccess && st == MODAP_OK) st = hip_fail(c, r, what);
+    };
+    if (ldA != n) q(hipMemsetAsync(s.A, 0, abytes, c->stream), "hipMemsetAsync");
+    q(hipMemcpy2DAsync(s.A, (size_t)ldA * c->es, A, (size_t)lda * c->es, (size_t)n * c->es, (size_t)m,
+                       on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream),
+      "hipMemcpy2DAsync");
+    q(hipMemcpyAsync(s.b, b, sizeof(double) * m, on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream),
+      "copy b");
+    q(hipMemsetAsync(s.x, 0, vbytes, c->stream), "hipMemsetAsync");
+    if (x0)
+        q(hipMemcpyAsync(s.x, x0, sizeof(double) * n, on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                         c->stream),
+          "copy x0");
+    q(hipMemsetAsync(s.y, 0, vbytes, c->stream), "hipMemsetAsync");
+    q(hipMemsetAsync(s.vpend, 0, vbytes, c->stream), "hipMemsetAsync");
+    q(hipMemsetAsync(s.work, 0, wbytes, c->stream), "hipMemsetAsync");
+    const unsigned long long none = ULLONG_MAX;
+    q(hipMemcpyAsync(c->bad, &none, sizeof none, hipMemcpyHostToDevice, c->stream), "copy");
+    q(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream), "hipMemsetAsync");
+    q(aux_row_norms(c->dt, s.A, ldA, m, n, s.nu, c->bad, c->stream), "row_norms launch");
+    if (on_dev) {
+        q(aux_check_finite(s.b, m, c->flag, c->stream), "check_finite launch");
+        q(aux_check_finite(s.x, n, c->flag, c->stream), "check_finite launch");
+    }
+    q(aux_ctl_init(s.ctl, c->stream), "ctl_init launch");
+    unsigned long long bad = 0;
+    int flag = 0;
+    q(hipMemcpyAsync(&bad, c->bad, sizeof bad, hipMemcpyDeviceToHost, c->stream), "copy");
+    q(hipMemcpyAsync(&flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream), "copy");
+    q(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (st) return cleanup(st);
+    if (flag) return cleanup(fail(c, MODAP_E_INVAL, "b or x0 has a non-finite entry"));
+    if (bad != ULLONG_MAX) return cleanup(fail(c, MODAP_E_ZERO_ROW, "row " + std::to_string(bad) + " is zero or not finite"));
+    s.alive = true;
+    // a fresh system's committed state must sit in the batch's slot
+    // (jn-1)&1: ctl_init filled both slots
+    size_t slot = c->sys.size();
+    for (size_t i = 0; i < c->sys.size(); ++i)
+        if (!c->sys[i].alive && !c->sys[i].A) {
+            slot = i;
+            break;
+        }
+    if (slot == c->sys.size()) c->sys.push_back(s);
+    else c->sys[slot] = s;
+    *id = (int64_t)slot;
+    c->dirty = true;
+    c->err.clear();
+    return MODAP_OK;
+}
+
+modap_status modap_batch_remove(modap_batch *c, int64_t id) {
+    if (!c) return MODAP_E_INVAL;
+    BSys *s = find_sys(c, id);
+    if (!s) return fail(c, MODAP_E_INVAL, "unknown system id");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    release_sys(*s);
+    c->dirty = true;
+    return MODAP_OK;
+}
+
+modap_status modap_batch_set_drift(modap_batch *c, int64_t id, int64_t T, const double *V, int64_t ldv, int on_dev) {
+    if (!c) return MODAP_E_INVAL;
+    BSys *s = find_sys(c, id);
+    if (!s) return fail(c, MODAP_E_INVAL, "unknown system id");
+    if (T < 0) return fail(c, MODAP_E_INVAL, "T < 0");
+    if (T > 0 && V && ldv < s->n) return fail(c, MODAP_E_INVAL, "ldv < n");
+    if (T > 0 && V && !on_dev)
+        for (int64_t r = 0; r < T; ++r)
+            if (!all_finite(V + r * ldv, s->n)) return fail(c, MODAP_E_INVAL, "drift has a non-finite entry");
+    DeviceGuard g(c->device);
+    const int sl = last_slot(c);
+    if (s->V) {
+        HIP_TRY(c, aux_sched_to_vpend(s->ctl, sl, s->vpend, s->V, s->ldA, s->n, c->stream));
+        s->vpend_maybe = true;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        free_dev(s->V);
+        s->T = 0;
+    }
+    if (T > 0 && V) {
+        HIP_TRY(c, hipMalloc(&s->V, sizeof(double) * (size_t)T * (size_t)s->ldA));
+        HIP_TRY(c, hipMemsetAsync(s->V, 0, sizeof(double) * (size_t)T * (size_t)s->ldA, c->stream));
+        HIP_TRY(c, hipMemcpy2DAsync(s->V, sizeof(double) * (size_t)s->ldA, V, sizeof(double) * (size_t)ldv,
+                                    sizeof(double) * (size_t)s->n, (size_t)T,
+                                    on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+        s->T = T;
+    }
+    HIP_TRY(c, aux_ctl_set_drift(s->ctl, sl, s->T, c->stream));
+    c->dirty = true;
+    return MODAP_OK;
+}
+
+modap_status modap_batch_update(modap_batch *c, int64_t id, int64_t k, const int64_t *rows, const void *new_rows,
+                                const double *new_b, const double *v, int on_dev) {
+    if (!c) return MODAP_E_INVAL;
+    BSys *s = find_sys(c, id);
+    if (!s) return fail(c, MODAP_E_INVAL, "unknown system id");
+    if (k < 0 || k > s->m) return fail(c, MODAP_E_INVAL, "k out of range");
+    if (k > 0 && (!rows || !new_rows || !new_b)) return fail(c, MODAP_E_INVAL, "rows, new_rows and new_b are required");
+    const size_t rbytes = (size_t)k * (size_t)s->n * c->es;
+    if (k > 0 && !on_dev) {
+        std::unordered_set<int64_t> seen;
+        for (int64_t q = 0; q < k; ++q) {
+            if (rows[q] < 0 || rows[q] >= s->m) return fail(c, MODAP_E_INVAL, "row index out of range");
+            if (!seen.insert(rows[q]).second) return fail(c, MODAP_E_INVAL, "row indices must be distinct");
+            if (!std::isfinite(new_b[q])) return fail(c, MODAP_E_INVAL, "new_b has a non-finite entry");
+        }
+    }
+    if (v && !on_dev && !all_finite(v, s->n)) return fail(c, MODAP_E_INVAL, "translation has a non-finite entry");
+    DeviceGuard g(c->device);
+    const int64_t *d_rows = rows;
+    const void *d_new = new_rows;
+    const double *d_b = new_b;
+    const double *d_v = v;
+    modap_status st;
+    if (!on_dev) {
+        const size_t o1 = 0, o2 = o1 + (size_t)k * 8, o3 = (o2 + rbytes + 15) / 16 * 16, o4 = o3 + (size_t)k * 8;
+        const size_t total = o4 + (v ? (size_t)s->n * 8 : 0);
+        if ((st = ensure_stage(c, total + 16))) return st;
+        char *p = reinterpret_cast<char *>(c->stage);
+        if (k > 0) {
+            if ((st = b_to_device(c, p + o1, rows, (size_t)k * 8, 0))) return st;
+            if ((st = b_to_device(c, p + o2, new_rows, rbytes, 0))) return st;
+            if ((st = b_to_device(c, p + o3, new_b, (size_t)k * 8, 0))) return st;
+        }
+        if (v && (st = b_to_device(c, p + o4, v, (size_t)s->n * 8, 0))) return st;
+        d_rows = reinterpret_cast<const int64_t *>(p + o1);
+        d_new = p + o2;
+        d_b = reinterpret_cast<const double *>(p + o3);
+        d_v = v ? reinterpret_cast<const double *>(p + o4) : nullptr;
+    }
+    const int sl = last_slot(c);
+    if (k > 0)
+        HIP_TRY(c, aux_scatter_rows(c->dt, s->A, s->ldA, s->m, s->n, k, d_rows, d_new, d_b, s->b, s->nu, s->ctl, sl,
+                                    s->vpend, c->stream));
+    if (d_v) {
+        HIP_TRY(c, aux_vpend_add(s->ctl, sl, s->vpend, d_v, s->n, c->stream));
+        s->vpend_maybe = true;
+    }
+    // the staging buffer is reused by the next call: wait for the copies out of it
+    if (!on_dev) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MODAP_OK;
+}
+
+modap_status modap_batch_iterate(modap_batch *c, const modap_params *p, int64_t k, modap_batch_stats *out) {
+    if (!c) return MODAP_E_INVAL;
+    modap_status st;
+    if ((st = check_params(c, p))) return st;
+    if (k < 0) return fail(c, MODAP_E_INVAL, "k < 0");
+    DeviceGuard g(c->device);
+    if ((st = rebuild(c))) return st;
+    if (c->h_sys.empty()) return fail(c, MODAP_E_STATE, "the batch has no systems");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int track = p->track != 0;
+    if (p->profile > 0 && k > 0 && !event_at(c, (size_t)(4 * ((k + p->profile - 1) / p->profile)) - 1))
+        return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
+    if ((st = enqueue_begin(c, -1))) return st;
+    size_t ev = 0;
+    double bytes = 0.0;
+    for (int64_t i = 0; i < k; ++i)
+        if ((st = enqueue_iteration(c, p, track, i, &ev, &bytes))) return st;
+    if (k > 0 && (st = enqueue_settle(c, p, track))) return st;
+    if (!out) return MODAP_OK;
+    if ((st = count_running_now(c, last_slot(c), &c->h_count[0]))) return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *out = modap_batch_stats{};
+    out->iters = k;
+    out->running = c->h_count[0];
+    out->systems = (int64_t)c->h_sys.size();
+    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    out->hbm_bytes = bytes;
+    if (p->profile && (st = profile_totals(c, ev, out))) return st;
+    return MODAP_OK;
+}
+
+modap_status modap_batch_solve(modap_batch *c, const modap_params *p, modap_batch_stats *out) {
+    if (!c) return MODAP_E_INVAL;
+    modap_status st;
+    if ((st = check_params(c, p))) return st;
+    DeviceGuard g(c->device);
+    if ((st = rebuild(c))) return st;
+    if (c->h_sys.empty()) return fail(c, MODAP_E_STATE, "the batch has no systems");
+    const auto t0 = std::chrono::steady_clock::now();
+    if ((st = enqueue_begin(c, p->max_iters))) return st;
+    const int64_t total = p->max_iters + 1;
+    if (p->profile > 0 && !event_at(c, (size_t)(4 * ((std::min<int64_t>(total, 4096) + p->profile - 1) / p->profile)) - 1))
+        return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
+    int64_t queued = 0, chunk = 1;
+    int slot = 0, pending = -1;
+    size_t ev = 0;
+    double bytes = 0.0;
+    bool done = false;
+    while (queued < total && !done) {
+        const int64_t cnt = std::min(chunk, total - queued);
+        for (int64_t i = 0; i < cnt; ++i)
+            if ((st = enqueue_iteration(c, p, 0, queued + i, &ev, &bytes))) return st;
+        queued += cnt;
+        // the newest settled states: the checks before the last queued sweep
+        if ((st = count_running_now(c, (int)((c->jn - 2) & 1), &c->h_count[slot]))) return st;
+        HIP_TRY(c, hipEventRecord(c->sync_ev[slot], c->stream));
+        if (pending >= 0) {
+            HIP_TRY(c, hipEventSynchronize(c->sync_ev[pending]));
+            if (c->h_count[pending] == 0) done = true;
+        }
+        pending = slot;
+        slot ^= 1;
+        chunk = std::min<int64_t>(chunk * 2, 64);
+    }
+    if ((st = enqueue_settle(c, p, 0))) return st;
+    if ((st = count_running_now(c, last_slot(c), &c->h_count[0]))) return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (out) {
+        *out = modap_batch_stats{};
+        out->iters = queued;
+        out->running = c->h_count[0];
+        out->systems = (int64_t)c->h_sys.size();
+        out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        out->hbm_bytes = bytes;
+        if (p->profile && (st = profile_totals(c, ev, out))) return st;
+    }
+    return MODAP_OK;
+}
+
+modap_status modap_batch_query(modap_batch *c, int64_t id, double *x, double *b, modap_stats *out, int on_dev) {
+    if (!c) return MODAP_E_INVAL;
+    BSys *s = find_sys(c, id);
+    if (!s) return fail(c, MODAP_E_INVAL, "unknown system id");
+    DeviceGuard g(c->device);
+    modap_status st;
+    const int sl = last_slot(c);
+    if (x && (st = b_from_device(c, x, s->x, sizeof(double) * s->n, on_dev))) return st;
+    if (b) {
+        HIP_TRY(c, aux_flush(c->dt, s->A, s->ldA, s->m, s->n, s->ctl, sl, s->vpend, s->T > 0 ? s->V : nullptr, s->b,
+                             c->stream));
+        if ((st = b_from_device(c, b, s->b, sizeof(double) * s->m, on_dev))) return st;
+    }
+    State k;
+    HIP_TRY(c, hipMemcpyAsync(&k, &s->ctl->st[sl], sizeof(State), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (out) {
+        *out = modap_stats{};
+        out->iters = k.steps;
+        out->sweeps = k.sweeps;
+        out->converged = k.feasible;
+        out->state = k.status;
+        out->max_viol = k.dmax;
+        out->h = k.h;
+        out->y_norm = k.ynorm;
+        out->b_inf = k.binf;
+        out->eps_abs = k.eps_abs;
+    }
+    return MODAP_OK;
+}
+
+modap_status modap_batch_set_tile(modap_batch *c, const modap_batch_tile *t) {
+    if (!c) return MODAP_E_INVAL;
+    if (!t) {
+        c->tile = modap_batch_tile{{64, 256, 256, 1024}, 0};
+    } else {
+        for (int q = 0; q < 4; ++q)
+            if (t->item_kib[q] < 1) return fail(c, MODAP_E_INVAL, "item_kib must be >= 1");
+        if (t->grid < 0) return fail(c, MODAP_E_INVAL, "grid must be >= 0");
+        c->tile = *t;
+    }
+    c->dirty = true;
+    return MODAP_OK;
+}
+
+modap_status modap_batch_get_tile(modap_batch *c, modap_batch_tile *t) {
+    if (!c) return MODAP_E_INVAL;
+    if (!t) return fail(c, MODAP_E_INVAL, "tile is NULL");
+    *t = c->tile;
+    return MODAP_OK;
+}
+
+modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *best) {
+    if (!c) return MODAP_E_INVAL;
+    if (reps < 1) return fail(c, MODAP_E_INVAL, "reps < 1");
+    DeviceGuard g(c->device);
+    modap_status st;
+    if ((st = rebuild(c))) return st;
+    if (c->h_sys.empty()) return fail(c, MODAP_E_STATE, "the batch has no systems");
+    bool present[4] = {false, false, false, false};
+    for (const BatchSys &d : c->h_sys) present[bucket_of(d.C)] = true;
+    hipEvent_t e0 = event_at(c, 0), e1 = event_at(c, 1);
+    if (!e0 || !e1) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
+    // one timing: `reps` stateless sweeps (no decision, no b written)
+    auto time_sweeps = [&](float *ms) -> modap_status {
+        modap_status s2;
+        if ((s2 = rebuild(c))) return s2;
+        BatchArgs a = batch_args(c);
+        if ((s2 = launch(c, prime_fn(c->dt), a.nsys, 256, a, nullptr, nullptr))) return s2;
+        a.check_status = 0;
+        a.write_b = 0;
+        std::vector<float> t;
+        for (int r = 0; r <= reps; ++r) {
+            HIP_TRY(c, hipMemsetAsync(c->queue, 0, sizeof(int32_t), c->stream));
+            if ((s2 = launch(c, sweep_fn(c->dt), c->grid, 256, a, r ? e0 : nullptr, r ? e1 : nullptr))) return s2;
+            if (r) {
+                HIP_TRY(c, hipEventSynchronize(e1));
+                float x = 0.f;
+                HIP_TRY(c, hipEventElapsedTime(&x, e0, e1));
+                t.push_back(x);
+            }
+        }
+        std::sort(t.begin(), t.end());
+        *ms = t[t.size() / 2];
+        return MODAP_OK;
+    };
+    modap_batch_tile cur = c->tile;
+    cur.grid = 0;
+    const int sizes[] = {32, 64, 128, 256, 512, 1024};
+    for (int q = 0; q < 4; ++q) {
+        if (!present[q]) continue;
+        float win = 1e30f;
+        int pick = cur.item_kib[q];
+        for (int kib : sizes) {
+            modap_batch_tile t = cur;
+            t.item_kib[q] = kib;
+            c->tile = t;
+            c->dirty = true;
+            float ms = 0.f;
+            if ((st = time_sweeps(&ms))) return st;
+            if (ms < win) {
+                win = ms;
+                pick = kib;
+            }
+        }
+        cur.item_kib[q] = pick;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep_fn(c->dt), 256, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    float win = 1e30f;
+    int pick = 0;
+    for (int mult = 1; mult <= per_cu; ++mult) {
+        modap_batch_tile t = cur;
+        t.grid = c->cu_count * mult;
+        c->tile = t;
+        c->dirty = true;
+        float ms = 0.f;
+        if ((st = time_sweeps(&ms))) return st;
+        if (ms < win) {
+            win = ms;
+            pick = t.grid;
+        }
+    }
+    cur.grid = pick;
+    c->tile = cur;
+    c->dirty = true;
+    if ((st = rebuild(c))) return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (best) *best = c->tile;
+    return MODAP_OK;
+}
+
+const char *modap_batch_last_error(modap_batch *c) { return c ? c->err.c_str() : "batch is NULL"; }
+
+}  // extern "C"

@@ -1,0 +1,461 @@
+// Batched sweep: many independent systems advanced together.
+//
+// Every system of a batch is the problem of the single-system library (the
+// sweep of section 3, the eps test of eq. 10, the step of eq. 12 or
+// Algorithm 1, the translation of the data), and every system keeps its own
+// state.  Two kernels advance all of them by one iteration:
+//
+//   sweep_batch   a persistent grid takes work items -- bands of rows of one
+//                 system -- from a device queue until it is empty.  One
+//                 wavefront streams one row at a time (its dot products need
+//                 no barrier); the four wavefronts of a workgroup take every
+//                 fourth row of the band; the item's x and v are staged in
+//                 LDS and each lane keeps C 16-byte chunks of its partial y in
+//                 registers, C = 1, 2, 4 or 8 chosen per system from its row
+//                 length.  Each item writes
+//                 its own partial y and scalars, so a system's result does not
+//                 depend on which workgroup took which item, nor on the other
+//                 systems in the batch.
+//   reduce_batch  one workgroup per 64 columns of a system: the system's item
+//                 partials summed in item order, the previous step made
+//                 permanent in x, and the next sweep's working vectors.
+//
+// The decision on a check is taken, as in the single-system library, by the
+// first kernel of the next sweep: every item of system s settles check j-1 of
+// s from the state in slot (j-2)&1 and the totals of the last reduction; the
+// system's first item commits it to slot (j-1)&1.
+#pragma once
+
+#include "modap_device.hpp"
+#include "sweep_wide.hpp"
+
+namespace modap {
+
+// One system of a batch, as the batch kernels see it.
+struct BatchSys {
+    const void *A;          // [m x ldA] storage type, rows padded with zeros
+    int64_t ldA, m, n;
+    double *b;              // [m]
+    const double *nu;       // [m] ||a_i||^2
+    double *x, *y;          // [ldA] FP64, zero-padded
+    const double *vpend;    // [ldA] one-shot translation
+    const double *V;        // drift schedule [T x ldA] or null
+    void *work;             // [3 x ldA] Acc: x, v and y of the next sweep
+    Ctrl *ctl;
+    Totals *tot;
+    double *ynp;            // [R] norm parts of y
+    int32_t R;              // 64-column blocks: ceil(n/64)
+    int32_t C;              // 16-byte chunks per lane: 64*VEC*C >= ldA
+    int64_t item0, nitems;  // the system's work items
+    int64_t part0;          // Acc offset of the first item's partial y (stride ldA)
+    int64_t rows_per_item;
+};
+
+// A 64-column block of one system (one workgroup of the reduction).
+struct BatchCol {
+    int32_t sys;
+    int32_t blk;
+};
+
+struct BatchArgs {
+    const BatchSys *sys;
+    int32_t nsys;
+    int32_t nitems;
+    const int32_t *item_sys;  // [nitems] the system of each item; a system's items are consecutive
+    void *part;               // per-item partial y
+    int64_t *h_part;          // [nitems]
+    double *dmax_part;        // [nitems]
+    double *binf_part;        // [nitems]
+    int32_t *queue;           // next item to take; zero before every sweep
+    int64_t j;                // index of this iteration (all systems advance together)
+    int32_t decide;           // the sweep settles the previous check (all but a call's first)
+    int32_t apply_step;       // the reduction makes the previous step permanent first
+    Decide dp;
+    int32_t check_status;     // skip systems whose state is not ST_RUNNING
+    int32_t write_b;          // store the translated b (0: a stateless sweep, e.g. for timing)
+};
+
+constexpr int kBatchWaves = 4;  // wavefronts per workgroup of sweep_batch
+constexpr int kBatchCmax = 8;   // largest C compiled
+
+// One work item: rows [r0, r1) of system S, wavefront w taking rows r0+w,
+// r0+w+4, ...  The item's x (with the previous step applied) and v are staged
+// once in LDS, and every lane reads its columns from there for each row; the
+// lane's partial y and two rows in flight stay in registers.  Every branch
+// that guards a barrier is uniform over the workgroup.
+template <int DT, int C>
+__device__ void batch_item(const BatchArgs &a, const BatchSys &S, int64_t k,
+                           typename Store<DT>::Acc (*lds)[kBatchCmax * 64 * Store<DT>::VEC],
+                           int64_t *hsh, double *dsh, double *bsh) {
+    using St = Store<DT>;
+    using Acc = typename St::Acc;
+    using T = typename St::T;
+    constexpr int VEC = St::VEC;
+    constexpr int CW = 64 * VEC;                   // columns per chunk
+    constexpr int AV = 16 / (int)sizeof(Acc);      // Acc per 16-byte vector
+    constexpr int COLS = C * CW;                   // staged columns (>= ldA)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t band = k - S.item0;
+    const int64_t r0 = band * S.rows_per_item;
+    const int64_t r1 = min(S.m, r0 + S.rows_per_item);
+    const int64_t ldA = S.ldA;
+    auto col_of = [&](int c) -> int { return c * CW + lane * VEC; };
+    const char *Ab = reinterpret_cast<const char *>(S.A);
+    const int64_t row_bytes = ldA * (int64_t)sizeof(T);
+
+    // this wavefront's rows; the first two are requested before the state is settled
+    const int64_t nrows = r1 - r0;
+    const int64_t nmine = nrows > wave ? (nrows - wave + kBatchWaves - 1) / kBatchWaves : 0;
+    auto row_of = [&](int64_t t) -> int64_t { return r0 + wave + t * kBatchWaves; };
+    auto load_row = [&](uint4 (&buf)[C], double &bi, double &ni, int64_t t) {
+        const int64_t row = min(row_of(t), r1 - 1);
+        const char *rp = Ab + row * row_bytes;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            buf[c] = load_stream(rp + min((int64_t)col_of(c), ldA - VEC) * (int64_t)sizeof(T));
+        bi = S.b[row];
+        ni = S.nu[row];
+    };
+    uint4 bufA[C], bufB[C];
+    double bA = 0.0, nA = 1.0, bB = 0.0, nB = 1.0;
+    if (nmine > 0) load_row(bufA, bA, nA, 0);
+    if (nmine > 1) load_row(bufB, bB, nB, 1);
+
+    Pending pd{S.ctl, a.j, S.tot, S.ynp, S.R, a.decide, a.dp};
+    const State st = sweep_state(pd, lane, band == 0 && tid == 0);
+    if (a.check_status && st.status != ST_RUNNING) return;
+    const bool apply_v = st.vpend_valid || st.v_idx >= 0;
+    const double s = a.decide ? st.s : 0.0;
+
+    // stage x_j = x_{j-1} - s*y_{j-1} (one rounding) and v, zero past ldA
+    Acc *xs = lds[0];
+    Acc *vs = lds[1];
+    const Acc *wx = reinterpret_cast<const Acc *>(S.work);
+    const Acc *wv = wx + ldA;
+    const Acc *wy = wx + 2 * ldA;
+    for (int col = tid * AV; col < COLS; col += 256 * AV) {
+        Acc xv[AV], vv[AV];
+        if (col < ldA) {
+            const uint4 ux = *reinterpret_cast<const uint4 *>(wx + col);
+            __builtin_memcpy(xv, &ux, 16);
+            if (s != 0.0) {
+                Acc yv[AV];
+                const uint4 uy = *reinterpret_cast<const uint4 *>(wy + col);
+                __builtin_memcpy(yv, &uy, 16);
+#pragma unroll
+                for (int q = 0; q < AV; ++q) xv[q] = (Acc)step_point((double)xv[q], s, (double)yv[q]);
+            }
+            if (apply_v) {
+                const uint4 uv = *reinterpret_cast<const uint4 *>(wv + col);
+                __builtin_memcpy(vv, &uv, 16);
+            } else {
+#pragma unroll
+                for (int q = 0; q < AV; ++q) vv[q] = (Acc)0;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < AV; ++q) xv[q] = vv[q] = (Acc)0;
+        }
+        uint4 ux, uv;
+        __builtin_memcpy(&ux, xv, 16);
+        __builtin_memcpy(&uv, vv, 16);
+        *reinterpret_cast<uint4 *>(xs + col) = ux;
+        *reinterpret_cast<uint4 *>(vs + col) = uv;
+    }
+    __syncthreads();
+
+    Acc yacc[C][VEC];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) yacc[c][e] = (Acc)0;
+    int64_t h = 0;
+    double dmax = 0.0, binf = 0.0;
+    auto process = [&](uint4 (&buf)[C], double bi, double ni, int64_t t) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (col_of(c) >= ldA) buf[c] = make_uint4(0u, 0u, 0u, 0u);
+        Acc dot = (Acc)0, tdot = (Acc)0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            Acc av[VEC], xv[VEC], vv[VEC];
+            unpack<DT>(buf[c], av);
+#pragma unroll
+            for (int e = 0; e < VEC; e += AV) {
+                const uint4 ux = *reinterpret_cast<const uint4 *>(xs + col_of(c) + e);
+                __builtin_memcpy(&xv[e], &ux, 16);
+            }
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) dot = fma(xv[e], av[e], dot);
+            if (apply_v) {
+#pragma unroll
+                for (int e = 0; e < VEC; e += AV) {
+                    const uint4 uv = *reinterpret_cast<const uint4 *>(vs + col_of(c) + e);
+                    __builtin_memcpy(&vv[e], &uv, 16);
+                }
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) tdot = fma(vv[e], av[e], tdot);
+            }
+        }
+        dot = wave_sum(dot);
+        const int64_t row = row_of(t);
+        double bb = bi;
+        if (apply_v) {
+            bb += (double)wave_sum(tdot);
+            if (a.write_b && lane == 0) S.b[row] = bb;
+        }
+        const double r = (double)dot - bb;
+        binf = max_nan(binf, fabs(bb));
+        if (r > 0.0) {
+            ++h;
+            dmax = max_nan(dmax, r / sqrt(ni));
+            const Acc w = (Acc)(r / ni);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                Acc av[VEC];
+                unpack<DT>(buf[c], av);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) yacc[c][e] = fma(w, av[e], yacc[c][e]);
+            }
+        } else if (r != r) {
+            dmax = r;
+        }
+    };
+    for (int64_t t = 0; t < nmine; t += 2) {
+        process(bufA, bA, nA, t);
+        if (t + 2 < nmine) load_row(bufA, bA, nA, t + 2);
+        if (t + 1 < nmine) {
+            process(bufB, bB, nB, t + 1);
+            if (t + 3 < nmine) load_row(bufB, bB, nB, t + 3);
+        }
+    }
+
+    // The wavefronts' partials are summed pairwise in LDS (the staging space
+    // is free once every wavefront has left the row loop):
+    // (w0 + w2) + (w1 + w3); wavefront 0 writes the item's partial.
+    auto put = [&](Acc *dst) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int e = 0; e < VEC; e += AV) {
+                uint4 w;
+                __builtin_memcpy(&w, &yacc[c][e], 16);
+                *reinterpret_cast<uint4 *>(dst + col_of(c) + e) = w;
+            }
+    };
+    auto add = [&](const Acc *src) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int e = 0; e < VEC; e += AV) {
+                Acc t4[AV];
+                const uint4 u = *reinterpret_cast<const uint4 *>(src + col_of(c) + e);
+                __builtin_memcpy(t4, &u, 16);
+#pragma unroll
+                for (int q = 0; q < AV; ++q) yacc[c][e + q] += t4[q];
+            }
+    };
+    if (lane == 0) {
+        hsh[wave] = h;
+        dsh[wave] = dmax;
+        bsh[wave] = binf;
+    }
+    __syncthreads();
+    if (wave >= 2) put(lds[wave - 2]);
+    __syncthreads();
+    if (wave < 2) add(lds[wave]);
+    __syncthreads();
+    if (wave == 1) put(lds[0]);
+    __syncthreads();
+    if (wave == 0) {
+        add(lds[0]);
+        Acc *part = reinterpret_cast<Acc *>(a.part) + S.part0 + band * ldA;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (col_of(c) >= ldA) continue;
+#pragma unroll
+            for (int e = 0; e < VEC; e += AV) {
+                uint4 w;
+                __builtin_memcpy(&w, &yacc[c][e], 16);
+                *reinterpret_cast<uint4 *>(part + col_of(c) + e) = w;
+            }
+        }
+    }
+    if (tid == 0) {
+        int64_t hh = 0;
+        double dd = 0.0, bm = 0.0;
+        for (int g = 0; g < kBatchWaves; ++g) {
+            hh += hsh[g];
+            dd = max_nan(dd, dsh[g]);
+            bm = max_nan(bm, bsh[g]);
+        }
+        a.h_part[k] = hh;
+        a.dmax_part[k] = dd;
+        a.binf_part[k] = bm;
+    }
+}
+
+// Persistent sweep over every item of the batch.  Each workgroup takes items
+// from the queue until it is exhausted (every workgroup reaches the end).
+template <int DT>
+__global__ __launch_bounds__(256) void sweep_batch(const BatchArgs a) {
+    using Acc = typename Store<DT>::Acc;
+    constexpr int VEC = Store<DT>::VEC;
+    __shared__ __attribute__((aligned(16))) Acc lds[2][kBatchCmax * 64 * VEC];
+    __shared__ int64_t hsh[kBatchWaves];
+    __shared__ double dsh[kBatchWaves], bsh[kBatchWaves];
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();  // the previous item's use of LDS is over
+        if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int k = s_item;
+        if (k >= a.nitems) return;
+        const BatchSys &S = a.sys[a.item_sys[k]];
+        switch (S.C) {
+            case 1: batch_item<DT, 1>(a, S, k, lds, hsh, dsh, bsh); break;
+            case 2: batch_item<DT, 2>(a, S, k, lds, hsh, dsh, bsh); break;
+            case 4: batch_item<DT, 4>(a, S, k, lds, hsh, dsh, bsh); break;
+            default: batch_item<DT, 8>(a, S, k, lds, hsh, dsh, bsh); break;
+        }
+    }
+}
+
+// Column sums of a system's item partials (item order, FP64), the previous
+// step made permanent in x, and the next sweep's working vectors.  One
+// workgroup per 64-column block; block 0 of a system also forms its totals.
+// Workgroup 0 empties the item queue for the next sweep.
+template <typename Acc>
+__global__ __launch_bounds__(256) void reduce_batch(const BatchArgs a, const BatchCol *cols) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.queue = 0;
+    const BatchCol cb = cols[blockIdx.x];
+    const BatchSys &S = a.sys[cb.sys];
+    const State P = S.ctl->st[slot_of(a.j - 1)];
+    if (P.status != ST_RUNNING) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t col = (int64_t)cb.blk * 64 + lane;
+    const Acc *part = reinterpret_cast<const Acc *>(a.part) + S.part0;
+    double acc = 0.0;
+    if (col < S.n)
+        for (int64_t q = wave; q < S.nitems; q += kBatchWaves) acc += (double)part[q * S.ldA + col];
+    __shared__ double sh[kBatchWaves][64];
+    sh[wave][lane] = acc;
+    __shared__ int64_t hw[kBatchWaves];
+    __shared__ double dw[kBatchWaves], bw[kBatchWaves];
+    if (cb.blk == 0) {
+        int64_t h = 0;
+        double dm = 0.0, bm = 0.0;
+        for (int64_t q = tid; q < S.nitems; q += 256) {
+            h += a.h_part[S.item0 + q];
+            dm = max_nan(dm, a.dmax_part[S.item0 + q]);
+            bm = max_nan(bm, a.binf_part[S.item0 + q]);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            h += __shfl_xor(h, o, 64);
+            dm = max_nan(dm, __shfl_xor(dm, o, 64));
+            bm = max_nan(bm, __shfl_xor(bm, o, 64));
+        }
+        if (lane == 0) {
+            hw[wave] = h;
+            dw[wave] = dm;
+            bw[wave] = bm;
+        }
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    double yv = 0.0;
+#pragma unroll
+    for (int g = 0; g < kBatchWaves; ++g) yv += sh[g][lane];
+    double sq = 0.0;
+    if (col < S.n) {
+        double xo = S.x[col];
+        if (a.apply_step && P.s != 0.0) {
+            xo = step_point(xo, P.s, S.y[col]);
+            S.x[col] = xo;
+        }
+        const bool due = S.V && P.sched_pos < S.ctl->sched_len;
+        Acc *w = reinterpret_cast<Acc *>(S.work);
+        w[col] = (Acc)xo;
+        w[S.ldA + col] = due ? (Acc)S.V[P.sched_pos * S.ldA + col] : (Acc)0;
+        w[2 * S.ldA + col] = (Acc)yv;
+        S.y[col] = yv;
+        sq = yv * yv;
+    }
+    sq = wave_sum(sq);
+    if (lane == 0) S.ynp[cb.blk] = sq;
+    if (cb.blk == 0 && lane == 0) {
+        Totals t{};
+        for (int g = 0; g < kBatchWaves; ++g) {
+            t.h += hw[g];
+            t.dmax = max_nan(t.dmax, dw[g]);
+            t.binf = max_nan(t.binf, bw[g]);
+        }
+        *S.tot = t;
+    }
+}
+
+// Start of a call, one thread per system: a stop that came from a previous
+// call's tolerance, step limit or missing direction is re-examined, and the
+// step limit of this call is set (-1: none).
+__global__ void begin_batch(const BatchArgs a, int64_t max_steps) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.nsys) return;
+    Ctrl *c = a.sys[i].ctl;
+    State &s = c->st[slot_of(a.j - 1)];
+    if (s.status == ST_CONVERGED || s.status == ST_LIMIT || s.status == ST_NO_DIRECTION) s.status = ST_RUNNING;
+    c->step_limit = max_steps < 0 ? INT64_MAX : s.steps + max_steps;
+}
+
+// Working vectors of a call's first sweep from each system's committed state
+// (one workgroup per system); workgroup 0 empties the item queue.
+template <typename Acc>
+__global__ __launch_bounds__(256) void prime_batch(const BatchArgs a) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.queue = 0;
+    const BatchSys &S = a.sys[blockIdx.x];
+    const State &p = S.ctl->st[slot_of(a.j - 1)];
+    const bool use_p = p.vpend_valid != 0;
+    const double *vrow = (S.V && p.v_idx >= 0) ? S.V + p.v_idx * S.ldA : nullptr;
+    Acc *w = reinterpret_cast<Acc *>(S.work);
+    for (int64_t col = threadIdx.x; col < S.n; col += blockDim.x) {
+        const double v = (use_p ? S.vpend[col] : 0.0) + (vrow ? vrow[col] : 0.0);
+        w[col] = (Acc)S.x[col];
+        w[S.ldA + col] = (Acc)v;
+    }
+}
+
+// End of a call: settle each system's last check (one workgroup per system).
+__global__ __launch_bounds__(256) void settle_batch(const BatchArgs a) {
+    const BatchSys &S = a.sys[blockIdx.x];
+    const State p = S.ctl->st[slot_of(a.j - 1)];
+    if (p.status != ST_RUNNING) {
+        if (threadIdx.x == 0) S.ctl->st[slot_of(a.j)] = p;
+        return;
+    }
+    __shared__ State sst;
+    if (threadIdx.x < 64) {
+        const double yn = ynorm_of(S.ynp, S.R, threadIdx.x);
+        const State cur = decide(p, *S.tot, yn, a.dp, S.ctl->step_limit, S.ctl->sched_len);
+        if (threadIdx.x == 0) {
+            sst = cur;
+            S.ctl->st[slot_of(a.j)] = cur;
+        }
+    }
+    __syncthreads();
+    const double s = sst.s;
+    if (s == 0.0) return;
+    for (int64_t col = threadIdx.x; col < S.n; col += blockDim.x) S.x[col] = step_point(S.x[col], s, S.y[col]);
+}
+
+// Number of systems whose state in slot sl is ST_RUNNING (one workgroup).
+__global__ __launch_bounds__(256) void count_running(const BatchArgs a, int sl, int *out) {
+    int cnt = 0;
+    for (int i = threadIdx.x; i < a.nsys; i += 256) cnt += a.sys[i].ctl->st[sl].status == ST_RUNNING;
+    cnt = wave_sum(cnt);
+    __shared__ int w[4];
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = w[0] + w[1] + w[2] + w[3];
+}
+
+}  // namespace modap

@@ -4,11 +4,12 @@
 // 16-byte multiple), its FP64 row norms, the approximation x, the last y, a
 // one-shot translation slot, an optional drift schedule, the per-workgroup
 // partials, the working vectors of the next sweep and a device control block.
-// One iteration is three kernels on the context's stream: the fused sweep,
-// the fixed-order reduction of y, and the stage kernel that takes the stop
-// decision and the step and writes the next sweep's working vectors.  The
-// host never waits between iterations; solve() reads the control block once
-// per batch.
+// One iteration is two kernels on the context's stream: the fused sweep
+// (which first settles the previous check: stop decision and step length)
+// and the fixed-order reduction of y (which makes the previous step permanent
+// in x and writes the next sweep's working vectors); a stage kernel settles
+// the last check of a call.  The host never waits between iterations; solve()
+// reads the control block once per batch of queued iterations.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -24,6 +25,7 @@
 #include <vector>
 
 #include "aux_kernels.hpp"
+#include "host_common.hpp"
 #include "modap.h"
 #include "sweep_split.hpp"
 #include "modap_device.hpp"
@@ -91,52 +93,7 @@ struct modap_ctx {
 
 namespace {
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int d) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != d) (void)hipSetDevice(d);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
-modap_status fail(modap_ctx *c, modap_status st, const std::string &msg) {
-    if (c) c->err = msg;
-    return st;
-}
-
-modap_status hip_fail(modap_ctx *c, hipError_t e, const char *what) {
-    if (e == hipErrorOutOfMemory) return fail(c, MODAP_E_NOMEM, std::string(what) + ": out of device memory");
-    return fail(c, MODAP_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-#define HIP_TRY(c, expr)                                            \
-    do {                                                            \
-        hipError_t e_ = (expr);                                     \
-        if (e_ != hipSuccess) return hip_fail((c), e_, #expr);      \
-    } while (0)
-
-#define LAUNCH_TRY(c, what)                                         \
-    do {                                                            \
-        hipError_t e_ = hipPeekAtLastError();                       \
-        if (e_ != hipSuccess) {                                     \
-            (void)hipGetLastError();                                \
-            return hip_fail((c), e_, what);                         \
-        }                                                           \
-    } while (0)
-
-size_t elem_size(int dt) { return dt == 0 ? 8 : dt == 1 ? 4 : 2; }
-size_t acc_size(int dt) { return dt == 0 ? 8 : 4; }
-int vec_elems(int dt) { return 16 / (int)elem_size(dt); }
-
-template <typename P>
-void free_dev(P *&p) {
-    if (p) (void)hipFree((void *)p);
-    p = nullptr;
-}
+using namespace modap_host;
 
 const SweepKernel *kernels_for(int dt, int *count) {
     switch (dt) {
@@ -343,11 +300,6 @@ modap_status check_params(modap_ctx *c, const modap_params *p) {
     return MODAP_OK;
 }
 
-bool all_finite(const double *p, int64_t count) {
-    for (int64_t i = 0; i < count; ++i)
-        if (!std::isfinite(p[i])) return false;
-    return true;
-}
 
 modap_status ensure_stage(modap_ctx *c, size_t bytes) {
     if (bytes <= c->stage_bytes) return MODAP_OK;
@@ -1289,3 +1241,68 @@ modap_status modap_get_tile(modap_ctx *c, modap_tile *t) {
 }
 
 }  // extern "C"
+
+// Launchers of the auxiliary kernels for the other translation units.
+namespace modap {
+
+hipError_t aux_row_norms(int dt, const void *A, int64_t ldA, int64_t m, int64_t n, double *nu,
+                         unsigned long long *bad, hipStream_t s) {
+    const int nb = (int)((m + 3) / 4);
+    switch (dt) {
+        case 0: hipLaunchKernelGGL(row_norms<0>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, nu, bad); break;
+        case 1: hipLaunchKernelGGL(row_norms<1>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, nu, bad); break;
+        default: hipLaunchKernelGGL(row_norms<2>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, nu, bad); break;
+    }
+    return hipPeekAtLastError();
+}
+
+hipError_t aux_check_finite(const double *p, int64_t count, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(check_finite, dim3(64), dim3(256), 0, s, p, count, flag);
+    return hipPeekAtLastError();
+}
+
+hipError_t aux_ctl_init(Ctrl *c, hipStream_t s) {
+    hipLaunchKernelGGL(ctl_init, dim3(1), dim3(64), 0, s, c);
+    return hipPeekAtLastError();
+}
+
+hipError_t aux_scatter_rows(int dt, void *A, int64_t ldA, int64_t m, int64_t n, int64_t k, const int64_t *rows,
+                            const void *new_rows, const double *new_b, double *b, double *nu, Ctrl *ctl, int sl,
+                            const double *vpend, hipStream_t s) {
+    switch (dt) {
+        case 0: hipLaunchKernelGGL(scatter_rows<0>, dim3(k), dim3(256), 0, s, A, ldA, m, n, rows, new_rows, new_b, b, nu, ctl, sl, vpend); break;
+        case 1: hipLaunchKernelGGL(scatter_rows<1>, dim3(k), dim3(256), 0, s, A, ldA, m, n, rows, new_rows, new_b, b, nu, ctl, sl, vpend); break;
+        default: hipLaunchKernelGGL(scatter_rows<2>, dim3(k), dim3(256), 0, s, A, ldA, m, n, rows, new_rows, new_b, b, nu, ctl, sl, vpend); break;
+    }
+    return hipPeekAtLastError();
+}
+
+hipError_t aux_vpend_add(Ctrl *c, int sl, double *vpend, const double *v, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(vpend_add, dim3(1), dim3(1024), 0, s, c, sl, vpend, v, n);
+    return hipPeekAtLastError();
+}
+
+hipError_t aux_sched_to_vpend(Ctrl *c, int sl, double *vpend, const double *V, int64_t ldV, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(sched_to_vpend, dim3(1), dim3(1024), 0, s, c, sl, vpend, V, ldV, n);
+    return hipPeekAtLastError();
+}
+
+hipError_t aux_ctl_set_drift(Ctrl *c, int sl, int64_t T, hipStream_t s) {
+    hipLaunchKernelGGL(ctl_set_drift, dim3(1), dim3(64), 0, s, c, sl, T);
+    return hipPeekAtLastError();
+}
+
+hipError_t aux_flush(int dt, const void *A, int64_t ldA, int64_t m, int64_t n, Ctrl *ctl, int sl, double *vpend,
+                     const double *V, double *b, hipStream_t s) {
+    const int nb = (int)((m + 3) / 4);
+    hipLaunchKernelGGL(sched_to_vpend, dim3(1), dim3(1024), 0, s, ctl, sl, vpend, V, ldA, n);
+    switch (dt) {
+        case 0: hipLaunchKernelGGL(flush_translation<0>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, (const Ctrl *)ctl, sl, (const double *)vpend, b); break;
+        case 1: hipLaunchKernelGGL(flush_translation<1>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, (const Ctrl *)ctl, sl, (const double *)vpend, b); break;
+        default: hipLaunchKernelGGL(flush_translation<2>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, (const Ctrl *)ctl, sl, (const double *)vpend, b); break;
+    }
+    hipLaunchKernelGGL(ctl_clear_vpend, dim3(1), dim3(64), 0, s, ctl, sl);
+    return hipPeekAtLastError();
+}
+
+}  // namespace modap

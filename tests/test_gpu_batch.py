@@ -1,0 +1,213 @@
+"""GPU parity of the batched sweep (many systems, one persistent launch).
+
+Each system of a batch is checked against the CPU oracle step by step from
+the GPU's own x (the tolerances of tests/parity.py), and a system's results
+must be the same bits whether it is alone in a batch or mixed with others."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+
+import oracle
+import workloads as W
+from parity import TOL, weighted_abs_rows
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2003_09956_amd as P
+    P.lib()
+    return P
+
+
+# row lengths covering every chunk bucket (1, 2, 4, 8 chunks per lane) with ragged ends
+SHAPES = {"f32": [(64, 150), (255, 700), (300, 1201), (513, 1100), (1000, 2500), (2048, 4100)],
+          "bf16": [(100, 300), (511, 1500), (1024, 2100), (2000, 4000), (4096, 5000)],
+          "f64": [(60, 200), (129, 500), (500, 1500), (1024, 2048)]}
+
+
+def step_bound(sys_, dtype, o, x, lam):
+    tol = TOL[dtype]
+    near = o.r > -tol * o.t
+    s_y = np.linalg.norm(weighted_abs_rows(sys_.A, dtype, np.where(near, o.t / o.nu, 0)))
+    return tol * (np.linalg.norm(x) + lam * s_y / np.linalg.norm(o.y))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f64"])
+def test_batch_steps_match_oracle(P, dtype):
+    """Every system of a mixed batch, three single iterations, each compared
+    with the oracle's step from the GPU's previous x."""
+    systems = [W.gaussian(n, m, seed=n + m, dtype=dtype) for (n, m) in SHAPES[dtype]]
+    lam = 0.3
+    prm = P.params(lam=lam, eps=1e-9)
+    with P.Batch(dtype) as B:
+        ids = [B.add(s.A, s.b, x0=s.z + 0.3) for s in systems]
+        xs = [s.z + 0.3 for s in systems]
+        for k in range(3):
+            say(f"batch step k={k} dtype={dtype}")
+            st = B.iterate(1, prm)
+            assert st.running == len(systems)
+            for sid, sys_ in zip(ids, systems):
+                x1, _, q = B.query(sid)
+                o = oracle.sweep(sys_.A, dtype, sys_.b, xs[sid])
+                xo, status = oracle.step(o.y, o.h, 0, lam, xs[sid])
+                assert status == 0 and q.iters == k + 1
+                err = np.linalg.norm(x1 - xo)
+                assert err <= step_bound(sys_, dtype, o, xs[sid], lam), (sid, k, err)
+                xs[sid] = x1
+
+
+def test_batch_alone_equals_in_mix(P):
+    """Per-item partials make a system's result independent of the batch it
+    shares: the same bits alone and among other systems (FP32 storage, with a
+    drift schedule and a translation update)."""
+    target = W.gaussian(777, 2000, seed=5, dtype="f32")
+    others = [W.gaussian(n, m, seed=n, dtype="f32") for (n, m) in [(100, 400), (2048, 3000), (400, 900)]]
+    V = W.drift(777, 30, sigma=1e-3, seed=5)
+    v1 = np.random.default_rng(1).normal(scale=1e-2, size=777)
+    prm = P.params(lam=0.5, eps=1e-7)
+    out = []
+    for mix in (False, True):
+        with P.Batch("f32") as B:
+            if mix:
+                B.add(others[0].A, others[0].b)
+                B.add(others[1].A, others[1].b, x0=others[1].z + 1)
+            sid = B.add(target.A, target.b, x0=target.z + 0.2)
+            if mix:
+                B.add(others[2].A, others[2].b)
+            B.set_drift(sid, V)
+            say(f"alone/mix mix={mix}")
+            B.iterate(7, prm)
+            B.update(sid, translate=v1)
+            B.iterate(9, prm)
+            x, b, q = B.query(sid, want_b=True)
+            out.append((x, b, q.iters, q.sweeps))
+    assert out[0][2] == out[1][2] and out[0][3] == out[1][3]
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_queued_equals_single_calls(P, dtype):
+    """The in-sweep decision of queued iterations against one iteration per
+    call: same bits for FP64 storage, within the step tolerance for FP32."""
+    systems = [W.gaussian(n, m, seed=3 * n, dtype=dtype) for (n, m) in [(200, 600), (700, 1600), (1000, 2200)]]
+    drifts = [W.drift(s.n, 20, sigma=2e-3, seed=i) for i, s in enumerate(systems)]
+    prm = P.params(lam=0.2, eps=1e-9)
+    res = []
+    for chunks in ([12], [1] * 12, [5, 7]):
+        with P.Batch(dtype) as B:
+            ids = [B.add(s.A, s.b, x0=s.z + 0.5) for s in systems]
+            for sid, V in zip(ids, drifts):
+                B.set_drift(sid, V)
+            for k in chunks:
+                B.iterate(k, prm)
+            res.append([B.query(sid, want_b=True) for sid in ids])
+    for r in res[1:]:
+        for (xa, ba, qa), (xb, bb, qb) in zip(res[0], r):
+            assert qa.iters == qb.iters == 12
+            if dtype == "f64":
+                assert np.array_equal(xa, xb) and np.array_equal(ba, bb)
+            else:
+                assert np.linalg.norm(xa - xb) <= 1e-4 * np.linalg.norm(xa)
+
+
+def test_batch_update_rows_and_translation(P):
+    """Row replacement and a translation in one update, then a sweep: the
+    step equals the oracle's on the updated data."""
+    sys_ = W.gaussian(300, 900, seed=9, dtype="f32")
+    rows, new_rows, new_b = W.replacement_rows(sys_, 30, seed=9)
+    v = np.random.default_rng(2).normal(scale=0.05, size=300)
+    lam = 0.3
+    x0 = sys_.z + 0.3
+    with P.Batch("f32") as B:
+        sid = B.add(sys_.A, sys_.b, x0=x0)
+        B.update(sid, rows=rows, new_rows=new_rows, new_b=new_b, translate=v)
+        say("batch update")
+        B.iterate(1, P.params(lam=lam, eps=1e-9))
+        x1, b1, _ = B.query(sid, want_b=True)
+    A2, b2 = oracle.replace_rows(sys_.A, "f32", sys_.b, rows, new_rows, new_b)
+    b2 = oracle.translate(A2, "f32", b2, v)
+    o = oracle.sweep(A2, "f32", b2, x0)
+    xo, status = oracle.step(o.y, o.h, 0, lam, x0)
+    assert status == 0
+    tol = TOL["f32"]
+    assert np.linalg.norm(x1 - xo) <= step_bound(W.System(A2, b2, x0, "f32", sys_.z, {}), "f32", o, x0, lam)
+    scale = np.abs(W.stored_to_f64(A2, "f32")) @ np.abs(v) + np.abs(b2)
+    assert np.max(np.abs(b1 - b2) / scale) <= tol
+
+
+def test_batch_solve_reaches_feasibility(P):
+    """Systems of several sizes solved together, each stopping on its own:
+    box-plus-sum systems (a ball of radius 100 inside, so ModAP with lambda = 1
+    terminates) and a Gaussian system that starts feasible (no step).  Each
+    final x is eps-feasible for its own data, checked by the oracle, and the
+    step counts equal those of the same systems solved one at a time."""
+    systems = [W.box_sum(n, seed=n, dtype="f32") for n in (64, 100, 256, 300, 512)]
+    g = W.gaussian(700, 1500, seed=3, dtype="f32")
+    systems.append(W.System(g.A, g.b, g.z.copy(), "f32", g.z, {}))
+    eps = 1e-6
+    prm = P.params(lam=1.0, eps=eps, max_iters=40000)
+    with P.Batch("f32") as B:
+        ids = [B.add(s.A, s.b, x0=s.x0) for s in systems]
+        say("batch solve")
+        st = B.solve(prm)
+        assert st.running == 0
+        steps = []
+        for sid, sys_ in zip(ids, systems):
+            x, b, q = B.query(sid, want_b=True)
+            assert q.state == 1, (sid, q.as_dict())
+            steps.append(q.iters)
+            o = oracle.sweep(sys_.A, "f32", b, x)
+            assert o.dmax <= eps * o.binf + TOL["f32"] * np.max(o.t / np.sqrt(o.nu))
+    assert steps[-1] == 0 and len(set(steps[:-1])) > 1
+    for sys_, k in zip(systems[:2], steps[:2]):
+        with P.Batch("f32") as B1:
+            sid = B1.add(sys_.A, sys_.b, x0=sys_.x0)
+            B1.solve(prm)
+            assert B1.query(sid)[2].iters == k
+
+
+def test_batch_autotune_keeps_results(P):
+    """The autotuner only changes speed: a tuned batch gives the oracle's step."""
+    systems = [W.gaussian(n, m, seed=n, dtype="f32") for (n, m) in [(128, 800), (900, 3000), (2000, 2500)]]
+    lam = 0.4
+    with P.Batch("f32") as B:
+        ids = [B.add(s.A, s.b, x0=s.z + 0.3) for s in systems]
+        say("batch autotune")
+        best = B.autotune(2)
+        assert best["grid"] > 0 and all(k >= 32 for k in best["item_kib"])
+        assert B.get_tile() == best
+        B.iterate(1, P.params(lam=lam, eps=1e-9))
+        for sid, sys_ in zip(ids, systems):
+            x1, _, _ = B.query(sid)
+            o = oracle.sweep(sys_.A, "f32", sys_.b, sys_.z + 0.3)
+            xo, _ = oracle.step(o.y, o.h, 0, lam, sys_.z + 0.3)
+            assert np.linalg.norm(x1 - xo) <= step_bound(sys_, "f32", o, sys_.z + 0.3, lam)
+
+
+def test_batch_errors(P):
+    with P.Batch("f32") as B:
+        with pytest.raises(P.ModapError, match="E_STATE"):
+            B.iterate(1)
+        sys_ = W.gaussian(3000, 10, seed=1, dtype="f32")
+        with pytest.raises(P.ModapError, match="E_INVAL"):
+            B.add(sys_.A, sys_.b)                       # rows longer than the batched sweep covers
+        small = W.gaussian(50, 80, seed=2, dtype="f32")
+        sid = B.add(small.A, small.b)
+        with pytest.raises(P.ModapError, match="E_INVAL"):
+            B.query(sid + 5)
+        B.remove(sid)
+        with pytest.raises(P.ModapError, match="E_INVAL"):
+            B.remove(sid)

@@ -213,3 +213,21 @@ def serving_arrivals(rate: float, horizon_s: float, seed: int = 0,
         n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
         out.append((t, n, 4 * n, int(seed) * 1_000_003 + k))
         k += 1
+
+
+def gaussian_device(n: int, m: int, seed: int = 0, dtype: str = "f32", device: str = "cuda"):
+    """The ``gaussian`` construction generated on the GPU with torch's seeded
+    generator (for workloads too large to build on the host quickly; its
+    random numbers differ from ``gaussian``'s): rows ~ N(0,1) normalised in
+    FP64 and rounded (RNE) to the storage type, ``z ~ U(-1,1)``, and
+    ``b = A_stored z + U(0,1)`` in FP64.  Returns (A, b, z) device tensors; a
+    BF16 A is a ``torch.bfloat16`` tensor (its bits are the storage)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 7919 + 104729)
+    A = torch.randn((m, n), generator=g, device=device, dtype=torch.float64)
+    A /= torch.linalg.vector_norm(A, dim=1, keepdim=True)
+    A = A.to({"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype])
+    z = torch.rand(n, generator=g, device=device, dtype=torch.float64) * 2.0 - 1.0
+    b = A.to(torch.float64) @ z + torch.rand(m, generator=g, device=device, dtype=torch.float64)
+    return A.contiguous(), b.contiguous(), z
