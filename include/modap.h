@@ -318,6 +318,88 @@ modap_status modap_batch_autotune(modap_batch *batch, int reps, modap_batch_tile
 /* Message describing the last failing call on the batch. */
 const char *modap_batch_last_error(modap_batch *batch);
 
+/* ------------------------------------------------------------------------
+ * Solve server: continuous batching of requests on one GPU.
+ *
+ * Each request is a system A x <= b (storage type of the server) with a
+ * starting point and an optional drift schedule, solved with the server's
+ * parameters.  Requests wait in arrival order until their device footprint
+ * fits the HBM budget; an admitted request whose rows fit the batched sweep
+ * joins the server's batch, a larger one gets a context on its own stream,
+ * so the work of all live requests overlaps on the device.  The caller drives
+ * the server: each modap_server_round queues iters_per_round iterations for
+ * every live request, waits for them, and retires the requests that stopped
+ * (eps-feasible, no direction, NaN, or max_iters steps), freeing their device
+ * memory for waiting requests.  A request's result depends only on its own
+ * data, updates and rounds, not on the other requests served with it.
+ * Times are seconds on the caller's clock (`now` arguments).
+ * ------------------------------------------------------------------------ */
+typedef struct modap_server modap_server;
+
+typedef struct {
+    int32_t state;          /* 0 queued, 1 live, 2 done, 3 failed at admission */
+    int32_t status;         /* done: the system's state (1 eps-feasible, 2 no direction, 3 NaN,
+                               4 step limit); failed: -modap_status */
+    int32_t batched;        /* served by the batch (1) or by a context of its own (0) */
+    int32_t pad;
+    int64_t iters;          /* steps taken */
+    int64_t sweeps;         /* checks done */
+    double max_viol;        /* last check: max_i max(r_i,0)/||a_i|| */
+    double eps_abs;         /* the threshold applied */
+    double t_submit, t_admit, t_done;   /* caller-clock seconds (-1 = not yet) */
+    double hbm_bytes;       /* algorithmic bytes of the request's sweeps */
+    double footprint;       /* device bytes held while live */
+} modap_request_info;
+
+/* Create a server on `device` for systems stored in `storage`, admitting
+ * requests while the sum of their footprints stays within hbm_budget_bytes.
+ * params: lambda, eps, eps_relative, step and max_iters of every request.
+ * Errors: E_INVAL, E_DEVICE, E_NOMEM. */
+modap_status modap_server_create(int device, modap_dtype storage, double hbm_budget_bytes,
+                                 const modap_params *params, int iters_per_round, modap_server **out);
+
+/* Release the server and every request (live ones are dropped).  NULL is a no-op. */
+void modap_server_destroy(modap_server *server);
+
+/* Queue a request: A [m x n] (lda = n), b [m], x0 [n] or NULL, and a drift
+ * schedule V [T x ldv] (T = 0: none).  Unlike the other calls, the caller's
+ * buffers are READ LATER, when the request is admitted by a round; they must
+ * stay valid and unchanged until modap_server_info reports it live, done or
+ * failed.  Device buffers are read on the server's own streams: their
+ * producer must have finished writing them before that round.  *ticket
+ * identifies the request.  Errors: E_INVAL, E_NOMEM (the request alone
+ * exceeds the budget). */
+modap_status modap_server_submit(modap_server *server, int64_t m, int64_t n, const void *A,
+                                 const double *b, const double *x0, int64_t T, const double *V,
+                                 int64_t ldv, int ptrs_on_device, double now, int64_t *ticket);
+
+/* Data update of a live request (see modap_update_coeffs), applied before
+ * its next iteration.  Errors: E_INVAL (unknown ticket), E_STATE (not live),
+ * E_ZERO_ROW. */
+modap_status modap_server_update(modap_server *server, int64_t ticket, int64_t k, const int64_t *rows,
+                                 const void *new_rows, const double *new_b, const double *translate_v,
+                                 int ptrs_on_device);
+
+/* One round: admit waiting requests that fit, iterate every live request
+ * iters_per_round times, wait, retire the requests that stopped.
+ * *outstanding (may be NULL) receives the number of queued plus live
+ * requests.  Errors: E_DEVICE and the errors of the calls it makes. */
+modap_status modap_server_round(modap_server *server, double now, int64_t *outstanding);
+
+/* State and statistics of a request.  Errors: E_INVAL. */
+modap_status modap_server_info(modap_server *server, int64_t ticket, modap_request_info *out);
+
+/* The final x ([n] host memory) of a finished request.  Errors: E_INVAL, E_STATE. */
+modap_status modap_server_result(modap_server *server, int64_t ticket, double *x);
+
+/* Totals: algorithmic bytes of all sweeps so far, rounds run, device bytes
+ * held by live requests (any pointer may be NULL). */
+modap_status modap_server_totals(modap_server *server, double *hbm_bytes, int64_t *rounds,
+                                 double *memory_in_use);
+
+/* Message describing the last failing call on the server. */
+const char *modap_server_last_error(modap_server *server);
+
 /* Message for a status code (static storage). */
 const char *modap_strerror(modap_status status);
 

@@ -35,7 +35,9 @@ EXPORTS = ["modap_create", "modap_destroy", "modap_set_system", "modap_set_x", "
            "modap_batch_create", "modap_batch_destroy", "modap_batch_add", "modap_batch_remove",
            "modap_batch_set_drift", "modap_batch_update", "modap_batch_iterate", "modap_batch_solve",
            "modap_batch_query", "modap_batch_set_tile", "modap_batch_get_tile", "modap_batch_autotune",
-           "modap_batch_last_error"]
+           "modap_batch_last_error", "modap_server_create", "modap_server_destroy", "modap_server_submit",
+           "modap_server_update", "modap_server_round", "modap_server_info", "modap_server_result",
+           "modap_server_totals", "modap_server_last_error"]
 
 
 class Params(C.Structure):
@@ -80,6 +82,18 @@ class BatchTile(C.Structure):
 
     def as_dict(self):
         return {"item_kib": list(self.item_kib), "grid": self.grid}
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("batched", C.c_int32), ("pad", C.c_int32),
+                ("iters", C.c_int64), ("sweeps", C.c_int64), ("max_viol", C.c_double), ("eps_abs", C.c_double),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("hbm_bytes", C.c_double), ("footprint", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        d["state_name"] = ("queued", "live", "done", "failed")[self.state]
+        return d
 
 
 class ModapError(RuntimeError):
@@ -133,9 +147,21 @@ def lib():
         L.modap_batch_autotune.argtypes = [vp, i32, C.POINTER(BatchTile)]
         L.modap_batch_last_error.argtypes = [vp]
         L.modap_batch_last_error.restype = C.c_char_p
+        L.modap_server_create.argtypes = [i32, i32, C.c_double, C.POINTER(Params), i32, C.POINTER(vp)]
+        L.modap_server_destroy.argtypes = [vp]
+        L.modap_server_destroy.restype = None
+        L.modap_server_submit.argtypes = [vp, i64, i64, vp, dp, dp, i64, dp, i64, i32, C.c_double,
+                                          C.POINTER(C.c_int64)]
+        L.modap_server_update.argtypes = [vp, i64, i64, vp, vp, dp, dp, i32]
+        L.modap_server_round.argtypes = [vp, C.c_double, C.POINTER(C.c_int64)]
+        L.modap_server_info.argtypes = [vp, i64, C.POINTER(RequestInfo)]
+        L.modap_server_result.argtypes = [vp, i64, dp]
+        L.modap_server_totals.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.modap_server_last_error.argtypes = [vp]
+        L.modap_server_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("modap_destroy", "modap_strerror", "modap_last_error", "modap_batch_destroy",
-                            "modap_batch_last_error"):
+                            "modap_batch_last_error", "modap_server_destroy", "modap_server_last_error"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -470,3 +496,92 @@ class Batch:
         t = BatchTile()
         self._check(lib().modap_batch_autotune(self._h, int(reps), C.byref(t)))
         return t.as_dict()
+
+
+class Server:
+    """Continuous-batching solve server (modap_server_* of the C ABI).  The
+    caller drives it with round(now); arrays of a submitted request are kept
+    referenced here until the request has been admitted."""
+
+    def __init__(self, dtype="bf16", budget_bytes=64e9, prm=None, iters_per_round=8, device: int = 0):
+        L = lib()
+        self.device = int(device)
+        self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        prm = prm or params()
+        h = C.c_void_p()
+        st = L.modap_server_create(self.device, self.dtype, float(budget_bytes), C.byref(prm), int(iters_per_round),
+                                   C.byref(h))
+        if st != OK:
+            raise ModapError(st, L.modap_strerror(st).decode())
+        self._h = h
+        self._held = {}
+        self.shapes = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().modap_server_destroy(self._h)
+            self._h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st):
+        if st != OK:
+            raise ModapError(st, lib().modap_server_last_error(self._h).decode())
+
+    def submit(self, A, b, x0=None, V=None, now=0.0):
+        m, n = int(A.shape[0]), int(A.shape[1])
+        g = _Args(self.device)
+        pa = g.ptr(A, _NP_STORE[self.dtype], m * n)
+        pb = g.ptr(b, np.float64, m)
+        px = g.ptr(x0, np.float64, n)
+        T = 0 if V is None else int(V.shape[0])
+        pv = g.ptr(V, np.float64, T * n) if T else None
+        t = C.c_int64()
+        self._check(lib().modap_server_submit(self._h, m, n, pa, pb, px, T, pv, n, g.on_dev, float(now),
+                                              C.byref(t)))
+        self._held[t.value] = g.keep       # read by the library when the request is admitted
+        self.shapes[t.value] = (m, n)
+        return t.value
+
+    def update(self, ticket, rows=None, new_rows=None, new_b=None, translate=None):
+        n = self.shapes.get(int(ticket), (0, 0))[1]
+        g = _Args(self.device)
+        k = 0 if rows is None else int(len(rows))
+        pr = g.ptr(rows, np.int64, k) if k else None
+        pn = g.ptr(new_rows, _NP_STORE[self.dtype], k * n) if k else None
+        pb = g.ptr(new_b, np.float64, k) if k else None
+        pv = g.ptr(translate, np.float64, n)
+        self._check(lib().modap_server_update(self._h, int(ticket), k, pr, pn, pb, pv, g.on_dev))
+
+    def round(self, now=0.0):
+        out = C.c_int64()
+        self._check(lib().modap_server_round(self._h, float(now), C.byref(out)))
+        for t in [t for t in self._held if self.info(t)["state"] != 0]:
+            del self._held[t]
+        return out.value
+
+    def info(self, ticket):
+        r = RequestInfo()
+        self._check(lib().modap_server_info(self._h, int(ticket), C.byref(r)))
+        return r.as_dict()
+
+    def result(self, ticket):
+        x = np.empty(self.shapes[int(ticket)][1])
+        self._check(lib().modap_server_result(self._h, int(ticket), x.ctypes.data_as(C.c_void_p)))
+        return x
+
+    def totals(self):
+        b, r, u = C.c_double(), C.c_int64(), C.c_double()
+        self._check(lib().modap_server_totals(self._h, C.byref(b), C.byref(r), C.byref(u)))
+        return {"hbm_bytes": b.value, "rounds": r.value, "memory_in_use": u.value}

@@ -1,0 +1,360 @@
+// Solve server: continuous batching of many requests on one GPU
+// (modap_server_* in include/modap.h).
+//
+// Requests wait in arrival order until their device footprint fits the HBM
+// budget.  An admitted request whose rows fit the batched sweep joins the
+// server's batch (one persistent launch for all of them); a larger one gets a
+// single-system context on a stream of its own, so its kernels overlap with
+// the batch's and with the other large requests'.  A round queues the same
+// number of iterations for every live request, waits for them, and retires
+// the requests that stopped (their x is kept on the host, their device memory
+// freed), which lets waiting requests in.  A request's iterations and
+// updates depend only on its own rounds, so its result does not depend on the
+// other requests it was served with.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "host_common.hpp"
+#include "modap.h"
+
+using namespace modap_host;
+
+namespace {
+
+enum ReqState { RQ_QUEUED = 0, RQ_LIVE = 1, RQ_DONE = 2, RQ_FAILED = 3 };
+
+struct Req {
+    int state = RQ_QUEUED;
+    int64_t m = 0, n = 0, ldA = 0;
+    double footprint = 0.0;
+    // submission (caller memory, read at admission)
+    const void *A = nullptr;
+    const double *b = nullptr, *x0 = nullptr, *V = nullptr;
+    int64_t T = 0, ldv = 0;
+    int on_dev = 0;
+    // live
+    bool in_batch = false;
+    int64_t bid = -1;
+    modap_ctx *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    int64_t sweeps_seen = 0;
+    // outcome
+    int32_t status = 0;
+    int64_t iters = 0, sweeps = 0;
+    double max_viol = 0.0, eps_abs = 0.0;
+    double t_submit = 0.0, t_admit = -1.0, t_done = -1.0;
+    double bytes = 0.0;
+    std::string error;
+    std::vector<double> x;
+};
+
+}  // namespace
+
+struct modap_server {
+    int device = 0;
+    int dt = 2;
+    size_t es = 2;
+    double budget = 0.0, used = 0.0;
+    modap_params params{};
+    int iters_per_round = 8;
+    int64_t max_sweeps = 0;
+    modap_batch *batch = nullptr;
+    hipStream_t batch_stream = nullptr;
+    int batch_live = 0;
+    std::vector<Req> reqs;
+    std::deque<int64_t> pending;
+    double bytes = 0.0;
+    int64_t rounds = 0;
+    std::string err;
+};
+
+namespace {
+
+int64_t padded(int dt, int64_t n) {
+    const int64_t v = vec_elems(dt);
+    return (n + v - 1) / v * v;
+}
+
+// Rows the batched sweep covers (64 lanes x 16-byte vectors x 8 chunks).
+int64_t batch_row_limit(int dt) { return 64 * (int64_t)vec_elems(dt) * 8; }
+
+// Device bytes a request holds while live: A, b, ||a||^2, r, the FP64
+// vectors (x, y, translation, two evaluation vectors), the working vectors,
+// the y partials of one sweep (about one row of Acc per row band) and the
+// drift schedule.
+double footprint(int dt, int64_t m, int64_t n, int64_t T) {
+    const double ldA = (double)padded(dt, n);
+    const double acc = (double)acc_size(dt);
+    return (double)m * ldA * (double)elem_size(dt) + 24.0 * (double)m + 5.0 * 8.0 * ldA + 6.0 * acc * ldA +
+           acc * ldA * (double)((m + 63) / 64) + 8.0 * ldA * (double)T + 65536.0;
+}
+
+double elapsed_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void drop(modap_server *s, Req &r) {
+    if (r.in_batch && r.bid >= 0) {
+        (void)modap_batch_remove(s->batch, r.bid);
+        --s->batch_live;
+    }
+    if (r.ctx) modap_destroy(r.ctx);
+    if (r.stream) (void)hipStreamDestroy(r.stream);
+    r.ctx = nullptr;
+    r.stream = nullptr;
+    r.bid = -1;
+    r.A = nullptr;
+    r.b = r.x0 = r.V = nullptr;
+    s->used -= r.footprint;
+}
+
+// Admit request r: copy its data into the batch or a new context.  On
+// failure everything created here is released again.
+modap_status admit(modap_server *s, Req &r, double now) {
+    modap_status st;
+    if (r.ldA <= batch_row_limit(s->dt)) {
+        int64_t id = -1;
+        if ((st = modap_batch_add(s->batch, r.m, r.n, r.A, r.n, r.b, r.x0, r.on_dev, &id))) {
+            r.error = modap_batch_last_error(s->batch);
+            return st;
+        }
+        if (r.T > 0 && (st = modap_batch_set_drift(s->batch, id, r.T, r.V, r.ldv, r.on_dev))) {
+            r.error = modap_batch_last_error(s->batch);
+            (void)modap_batch_remove(s->batch, id);
+            return st;
+        }
+        r.in_batch = true;
+        r.bid = id;
+        ++s->batch_live;
+    } else {
+        if (hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess) {
+            r.stream = nullptr;
+            r.error = "hipStreamCreateWithFlags failed";
+            return MODAP_E_DEVICE;
+        }
+        st = modap_create(s->device, r.stream, &r.ctx);
+        if (!st) st = modap_set_system(r.ctx, r.m, r.n, (modap_dtype)s->dt, r.A, r.n, r.b, r.x0, r.on_dev);
+        if (!st && r.T > 0) st = modap_set_drift(r.ctx, r.T, r.V, r.ldv, r.on_dev);
+        if (st) {
+            r.error = r.ctx ? modap_last_error(r.ctx) : "context creation failed";
+            if (r.ctx) modap_destroy(r.ctx);
+            (void)hipStreamDestroy(r.stream);
+            r.ctx = nullptr;
+            r.stream = nullptr;
+            return st;
+        }
+    }
+    r.state = RQ_LIVE;
+    r.t_admit = now;
+    s->used += r.footprint;
+    return MODAP_OK;
+}
+
+void finish(modap_server *s, Req &r, const modap_stats &q, double now) {
+    r.status = q.state;
+    r.iters = q.iters;
+    r.sweeps = q.sweeps;
+    r.max_viol = q.max_viol;
+    r.eps_abs = q.eps_abs;
+    r.t_done = now;
+    r.state = RQ_DONE;
+}
+
+}  // namespace
+
+extern "C" {
+
+modap_status modap_server_create(int device, modap_dtype storage, double hbm_budget_bytes, const modap_params *p,
+                                 int iters_per_round, modap_server **out) {
+    if (!out) return MODAP_E_INVAL;
+    *out = nullptr;
+    if (!p || !(hbm_budget_bytes > 0.0) || iters_per_round < 1) return MODAP_E_INVAL;
+    if (!(p->lambda > 0.0) || !std::isfinite(p->lambda) || !(p->eps > 0.0) || !std::isfinite(p->eps) ||
+        (p->step != MODAP_STEP_FIXED && p->step != MODAP_STEP_AVG) || p->max_iters < 1)
+        return MODAP_E_INVAL;
+    modap_server *s = new (std::nothrow) modap_server();
+    if (!s) return MODAP_E_NOMEM;
+    s->device = device;
+    s->dt = (int)storage;
+    s->es = elem_size(s->dt);
+    s->budget = hbm_budget_bytes;
+    s->params = *p;
+    s->params.profile = 0;
+    s->params.track = 0;
+    s->iters_per_round = iters_per_round;
+    s->max_sweeps = p->max_iters + 1;
+    DeviceGuard g(device);
+    if (hipStreamCreateWithFlags(&s->batch_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete s;
+        return MODAP_E_DEVICE;
+    }
+    modap_status st = modap_batch_create(device, s->batch_stream, storage, &s->batch);
+    if (st) {
+        (void)hipStreamDestroy(s->batch_stream);
+        delete s;
+        return st;
+    }
+    *out = s;
+    return MODAP_OK;
+}
+
+void modap_server_destroy(modap_server *s) {
+    if (!s) return;
+    DeviceGuard g(s->device);
+    for (Req &r : s->reqs)
+        if (r.state == RQ_LIVE) drop(s, r);
+    modap_batch_destroy(s->batch);
+    if (s->batch_stream) (void)hipStreamDestroy(s->batch_stream);
+    delete s;
+}
+
+modap_status modap_server_submit(modap_server *s, int64_t m, int64_t n, const void *A, const double *b,
+                                 const double *x0, int64_t T, const double *V, int64_t ldv, int ptrs_on_device,
+                                 double now, int64_t *ticket) {
+    if (!s) return MODAP_E_INVAL;
+    if (!ticket) return fail(s, MODAP_E_INVAL, "ticket is NULL");
+    if (m < 1 || n < 1 || !A || !b) return fail(s, MODAP_E_INVAL, "bad sizes or NULL data");
+    if (T < 0 || (T > 0 && (!V || ldv < n))) return fail(s, MODAP_E_INVAL, "bad drift schedule");
+    Req r;
+    r.m = m;
+    r.n = n;
+    r.ldA = padded(s->dt, n);
+    r.footprint = footprint(s->dt, m, n, T);
+    if (r.footprint > s->budget) return fail(s, MODAP_E_NOMEM, "the request alone exceeds the HBM budget");
+    r.A = A;
+    r.b = b;
+    r.x0 = x0;
+    r.T = T;
+    r.V = V;
+    r.ldv = ldv;
+    r.on_dev = ptrs_on_device;
+    r.t_submit = now;
+    *ticket = (int64_t)s->reqs.size();
+    s->reqs.push_back(std::move(r));
+    s->pending.push_back(*ticket);
+    return MODAP_OK;
+}
+
+modap_status modap_server_update(modap_server *s, int64_t ticket, int64_t k, const int64_t *rows,
+                                 const void *new_rows, const double *new_b, const double *translate_v,
+                                 int ptrs_on_device) {
+    if (!s) return MODAP_E_INVAL;
+    if (ticket < 0 || ticket >= (int64_t)s->reqs.size()) return fail(s, MODAP_E_INVAL, "unknown ticket");
+    Req &r = s->reqs[(size_t)ticket];
+    if (r.state != RQ_LIVE) return fail(s, MODAP_E_STATE, "the request is not live");
+    modap_status st;
+    if (r.in_batch) {
+        if ((st = modap_batch_update(s->batch, r.bid, k, rows, new_rows, new_b, translate_v, ptrs_on_device)))
+            return fail(s, st, modap_batch_last_error(s->batch));
+    } else if ((st = modap_update_coeffs(r.ctx, k, rows, new_rows, new_b, translate_v, ptrs_on_device))) {
+        return fail(s, st, modap_last_error(r.ctx));
+    }
+    return MODAP_OK;
+}
+
+modap_status modap_server_round(modap_server *s, double now, int64_t *outstanding) {
+    if (!s) return MODAP_E_INVAL;
+    DeviceGuard g(s->device);
+    const auto t0 = std::chrono::steady_clock::now();
+    modap_status st;
+    // admission in arrival order while the footprint fits
+    while (!s->pending.empty()) {
+        Req &r = s->reqs[(size_t)s->pending.front()];
+        if (s->used + r.footprint > s->budget) break;
+        s->pending.pop_front();
+        st = admit(s, r, now + elapsed_since(t0));
+        r.A = nullptr;  // the caller's memory is no longer read
+        r.b = r.x0 = r.V = nullptr;
+        if (st) {
+            r.state = RQ_FAILED;
+            r.status = -(int32_t)st;
+            if (r.error.empty()) r.error = "admission failed";
+        }
+    }
+    // the same number of iterations for every live request
+    const int64_t k = s->iters_per_round;
+    if (s->batch_live > 0 && (st = modap_batch_iterate(s->batch, &s->params, k, nullptr)))
+        return fail(s, st, modap_batch_last_error(s->batch));
+    for (Req &r : s->reqs)
+        if (r.state == RQ_LIVE && !r.in_batch && (st = modap_iterate(r.ctx, &s->params, k, nullptr)))
+            return fail(s, st, modap_last_error(r.ctx));
+    // wait, then retire the requests that stopped
+    HIP_TRY(s, hipStreamSynchronize(s->batch_stream));
+    for (Req &r : s->reqs)
+        if (r.state == RQ_LIVE && !r.in_batch) HIP_TRY(s, hipStreamSynchronize(r.stream));
+    const double t_end = now + elapsed_since(t0);
+    for (Req &r : s->reqs) {
+        if (r.state != RQ_LIVE) continue;
+        modap_stats q{};
+        st = r.in_batch ? modap_batch_query(s->batch, r.bid, nullptr, nullptr, &q, 0)
+                        : modap_query(r.ctx, nullptr, nullptr, &q, 0);
+        if (st) return fail(s, st, "query of a live request failed");
+        const double per_sweep = (double)r.m * (double)r.n * (double)s->es + 24.0 * (double)r.m;
+        r.bytes += (double)(q.sweeps - r.sweeps_seen) * per_sweep;
+        s->bytes += (double)(q.sweeps - r.sweeps_seen) * per_sweep;
+        r.sweeps_seen = q.sweeps;
+        const bool stopped = q.state != 0;
+        const bool capped = q.sweeps >= s->max_sweeps;
+        if (!stopped && !capped) continue;
+        r.x.resize((size_t)r.n);
+        st = r.in_batch ? modap_batch_query(s->batch, r.bid, r.x.data(), nullptr, &q, 0)
+                        : modap_query(r.ctx, r.x.data(), nullptr, &q, 0);
+        if (st) return fail(s, st, "reading a finished request failed");
+        finish(s, r, q, t_end);
+        if (!stopped) r.status = 4;  // the step limit of the server's parameters
+        drop(s, r);
+    }
+    ++s->rounds;
+    if (outstanding) {
+        int64_t cnt = (int64_t)s->pending.size();
+        for (const Req &r : s->reqs) cnt += r.state == RQ_LIVE;
+        *outstanding = cnt;
+    }
+    return MODAP_OK;
+}
+
+modap_status modap_server_info(modap_server *s, int64_t ticket, modap_request_info *out) {
+    if (!s) return MODAP_E_INVAL;
+    if (ticket < 0 || ticket >= (int64_t)s->reqs.size() || !out) return fail(s, MODAP_E_INVAL, "unknown ticket");
+    const Req &r = s->reqs[(size_t)ticket];
+    *out = modap_request_info{};
+    out->state = r.state;
+    out->status = r.status;
+    out->batched = r.in_batch || (r.state != RQ_QUEUED && r.ldA <= batch_row_limit(s->dt));
+    out->iters = r.iters;
+    out->sweeps = r.state == RQ_DONE ? r.sweeps : r.sweeps_seen;
+    out->max_viol = r.max_viol;
+    out->eps_abs = r.eps_abs;
+    out->t_submit = r.t_submit;
+    out->t_admit = r.t_admit;
+    out->t_done = r.t_done;
+    out->hbm_bytes = r.bytes;
+    out->footprint = r.footprint;
+    return MODAP_OK;
+}
+
+modap_status modap_server_result(modap_server *s, int64_t ticket, double *x) {
+    if (!s) return MODAP_E_INVAL;
+    if (ticket < 0 || ticket >= (int64_t)s->reqs.size() || !x) return fail(s, MODAP_E_INVAL, "unknown ticket");
+    const Req &r = s->reqs[(size_t)ticket];
+    if (r.state != RQ_DONE) return fail(s, MODAP_E_STATE, "the request has not finished");
+    for (size_t i = 0; i < r.x.size(); ++i) x[i] = r.x[i];
+    return MODAP_OK;
+}
+
+modap_status modap_server_totals(modap_server *s, double *hbm_bytes, int64_t *rounds, double *memory_in_use) {
+    if (!s) return MODAP_E_INVAL;
+    if (hbm_bytes) *hbm_bytes = s->bytes;
+    if (rounds) *rounds = s->rounds;
+    if (memory_in_use) *memory_in_use = s->used;
+    return MODAP_OK;
+}
+
+const char *modap_server_last_error(modap_server *s) { return s ? s->err.c_str() : "server is NULL"; }
+
+}  // extern "C"
