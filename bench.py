@@ -53,6 +53,18 @@ WORKLOADS = {
                          "drift |v|=1e-4 per iteration, lambda=1, eps=1e-6*||b||inf, ModAP fixed-length step"),
 }
 ELEM_BYTES = {"f64": 8, "f32": 4, "bf16": 2}
+# Workloads of many systems: the batched family (512 FP32 systems, n ~ U{64..2048},
+# m ~ U{2n..8n}) and the served family (Poisson arrivals, n log-uniform in
+# [128, 16384], m = 4n, BF16).
+MULTI = {
+    "batch-f32-512": "512 FP32 Gaussian systems (n ~ U{64..2048}, m ~ U{2n..8n}), each with its own drift "
+                     "N(0,1e-3^2) per coordinate per iteration, advanced together (one persistent sweep launch "
+                     "per iteration), lambda=1, eps=1e-6*||b||inf, autotuned tiles",
+    "serve-bf16-poisson": "Poisson arrivals of BF16 Gaussian systems (n log-uniform in [128,16384], m=4n), every "
+                          "10 ms each live system translated (|v|=1e-4) and 1% of its rows replaced, admission by "
+                          "HBM footprint, ModAP lambda=0.1, eps=1e-6*||b||inf; the same arrivals and updates served "
+                          "in FP64 one request at a time for comparison",
+}
 DT_CODE = {"f64": 0, "f32": 1, "bf16": 2}
 
 
@@ -142,8 +154,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttf", action="store_true", help="skip the time-to-feasible solves")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="f32-8192x16384",
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + sorted(MULTI), default="f32-8192x16384",
                     help="system the timed steps run on (default: the FP32 n=8192 m=16384 system)")
+    ap.add_argument("--rate", type=float, default=5.0, help="serving: Poisson arrival rate per second")
+    ap.add_argument("--horizon", type=float, default=10.0, help="serving: seconds of arrivals")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="serving: HBM budget of the server")
     ap.add_argument("--tile", type=str, default=None,
                     help="force the sweep shape block,lanes_per_row,chunks,rows_per_step,depth,interleave,grid "
                          "(skips the autotuner)")
@@ -175,6 +190,10 @@ def main():
         print(json.dumps({"copy_bytes": nbytes, "launches": 5}), flush=True)
         return
     P.lib()
+    if args.workload == "batch-f32-512":
+        return bench_batch(args, P, W, torch)
+    if args.workload == "serve-bf16-poisson":
+        return bench_serve(args, P, W, torch)
 
     K, WU = args.steps, args.warmup
     dt, n, m, sigma, desc = WORKLOADS[args.workload]
@@ -274,6 +293,148 @@ def main():
                                 "kind": "oracle",
                                 "sample": f"{steps} iterations (translate, sweep, step) of the full n={n} m={m} "
                                           f"{dt} system, {secs:.1f} s, single-threaded extended-precision oracle"}
+    print(json.dumps(line), flush=True)
+
+
+def bench_batch(args, P, W, torch):
+    """One step = one iteration of all 512 systems (one sweep launch, one
+    reduction launch); data generated on the device with a seeded generator."""
+    K, WU = args.steps, args.warmup
+    shapes = W.batch_shapes(512, seed=args.seed)
+    B = P.Batch("f32")
+    bytes_per_step = 0
+    for i, (n, m) in enumerate(shapes):
+        A, b, _ = W.gaussian_device(n, m, seed=args.seed * 100003 + i, dtype="f32")
+        sid = B.add(A, b)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(args.seed * 7 + i)
+        B.set_drift(sid, torch.randn((K + WU, n), generator=g, device="cuda", dtype=torch.float64) * 1e-3)
+        bytes_per_step += m * n * 4 + 24 * m
+        del A, b
+    torch.cuda.synchronize()
+    tile = B.autotune(3)
+    log("batch tile (autotuned)", tile)
+    lam, eps = 1.0, 1e-6
+    n_prof = (K + PROFILE_EVERY - 1) // PROFILE_EVERY
+    B.iterate(WU, P.params(lam=lam, eps=eps, track=True, profile=max(1, WU // max(n_prof, 1))))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = B.iterate(K, P.params(lam=lam, eps=eps, track=True, profile=PROFILE_EVERY))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sweep_us = st.sweep_ms * 1e3 / st.profiled
+    reduce_us = st.reduce_ms * 1e3 / st.profiled
+    B.close()
+    value = bytes_per_step * K / wall / 1e9
+    achieved = bytes_per_step / (sweep_us * 1e-6) / 1e9
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": K, "warmup": WU,
+        "ms_per_step": round(wall * 1e3 / K, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (generated on the device, seeded)",
+        "config": {"workload": MULTI["batch-f32-512"], "systems": 512, "elements": int(sum(n * m for n, m in shapes)),
+                   "bytes_per_step": bytes_per_step, "tile": tile},
+        "pct_of_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "sweep_batch<1>",
+                     "avg_us": round(sweep_us, 3), "reduce_avg_us": round(reduce_us, 3)},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def _replace_rows_device(torch, n, m, k, z, gen, dtype):
+    """k fresh normalised Gaussian rows with b = a.z + U(0,1) (device tensors)."""
+    idx = torch.randperm(m, generator=gen, device="cuda")[:k].sort().values
+    rows = torch.randn((k, n), generator=gen, device="cuda", dtype=torch.float64)
+    rows /= torch.linalg.vector_norm(rows, dim=1, keepdim=True)
+    rows = rows.to({"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype])
+    nb = rows.to(torch.float64) @ z + torch.rand(k, generator=gen, device="cuda", dtype=torch.float64)
+    return idx.contiguous(), rows.contiguous(), nb.contiguous()
+
+
+def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap):
+    """Drive one server over the arrivals: requests generated on the device at
+    their arrival time, every 10 ms each live request translated (|v| = 1e-4)
+    and 1% of its rows replaced by fresh rows that keep its moving hidden point
+    feasible.  Time-to-feasible runs from arrival to the end of the round that
+    saw the request eps-feasible; requests not finished within wall_cap
+    seconds are reported as censored."""
+    import math
+    lam, eps, tick, vnorm, frac, ipr = 0.1, 1e-6, 0.010, 1e-4, 0.01, 8
+    prm = P.params(lam=lam, eps=eps, max_iters=200000)
+    S = P.Server(storage, budget_bytes=args.budget_gb * 1e9, prm=prm, iters_per_round=ipr)
+    if max_live:
+        S.set_max_live(max_live)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(args.seed + 17)
+    reqs = {}
+    i = 0
+    t0 = time.perf_counter()
+    next_tick = tick
+    rounds = 0
+    last_log = 0.0
+    while True:
+        now = time.perf_counter() - t0
+        while i < len(arrivals) and arrivals[i][0] <= now:
+            t_arr, n, m, sd = arrivals[i]
+            A, b, z = W.gaussian_device(n, m, seed=sd, dtype=storage)
+            torch.cuda.synchronize()
+            tk = S.submit(A, b, now=t_arr)
+            reqs[tk] = {"n": n, "m": m, "z": z}
+            i += 1
+        if now >= next_tick:
+            live = [tk for tk in reqs if S.info(tk)["state"] == 1]
+            for tk in live:
+                r = reqs[tk]
+                v = torch.randn(r["n"], generator=gen, device="cuda", dtype=torch.float64) * (vnorm / math.sqrt(r["n"]))
+                r["z"] = r["z"] + v
+                idx, rows, nb = _replace_rows_device(torch, r["n"], r["m"], max(1, math.ceil(frac * r["m"])), r["z"],
+                                                     gen, storage)
+                r["upd"] = (idx, rows, nb, v)
+            torch.cuda.synchronize()
+            for tk in live:
+                idx, rows, nb, v = reqs[tk].pop("upd")
+                S.update(tk, rows=idx, new_rows=rows, new_b=nb, translate=v)
+            next_tick = now + tick
+        left = S.round(now)
+        rounds += 1
+        if now - last_log > 5.0:
+            log(f"{storage} max_live={max_live}: t={now:.1f}s arrivals {i}/{len(arrivals)} outstanding {left}")
+            last_log = now
+        if (i == len(arrivals) and left == 0) or now > wall_cap:
+            break
+    wall = time.perf_counter() - t0
+    infos = [S.info(tk) for tk in reqs]
+    tot = S.totals()
+    S.close()
+    ttf = [inf["t_done"] - inf["t_submit"] for inf in infos if inf["state"] == 2 and inf["status"] == 1]
+    out = {"p50_ms": round(1e3 * percentile(ttf, 50), 3) if ttf else None,
+           "p99_ms": round(1e3 * percentile(ttf, 99), 3) if ttf else None,
+           "feasible": len(ttf), "requests": len(reqs), "censored": sum(1 for inf in infos if inf["state"] < 2),
+           "GBs": round(tot["hbm_bytes"] / wall / 1e9, 2), "rounds": rounds, "wall_s": round(wall, 3),
+           "storage": storage, "max_live": max_live or None}
+    return out, tot["hbm_bytes"], wall, rounds
+
+
+def bench_serve(args, P, W, torch):
+    """Served BF16 (continuous batching) against the plain FP64 form served one
+    request at a time, on the same arrival process and update schedule."""
+    arrivals = W.serving_arrivals(args.rate, args.horizon, seed=args.seed)
+    log(f"{len(arrivals)} arrivals over {args.horizon} s at {args.rate}/s")
+    cap = max(60.0, 6.0 * args.horizon)
+    served, bytes_, wall, rounds = serve_pass(args, P, W, torch, arrivals, "bf16", 0, cap)
+    log("served", served)
+    plain, _, _, _ = serve_pass(args, P, W, torch, arrivals, "f64", 1, cap)
+    log("fp64 one at a time", plain)
+    value = bytes_ / wall / 1e9
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": rounds, "warmup": 0,
+        "ms_per_step": round(wall * 1e3 / max(rounds, 1), 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic (generated on the device, seeded)",
+        "config": {"workload": MULTI["serve-bf16-poisson"], "rate_per_s": args.rate, "horizon_s": args.horizon,
+                   "budget_gb": args.budget_gb, "requests": len(arrivals)},
+        "pct_of_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        "time_to_feasible": {"served_bf16_continuous_batching": served, "fp64_single_system_one_at_a_time": plain},
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -386,6 +386,10 @@ modap_status modap_server_update(modap_server *server, int64_t ticket, int64_t k
  * requests.  Errors: E_DEVICE and the errors of the calls it makes. */
 modap_status modap_server_round(modap_server *server, double now, int64_t *outstanding);
 
+/* Admit at most max_live requests at a time (0: no limit besides the
+ * budget); 1 serves the requests one after the other.  Errors: E_INVAL. */
+modap_status modap_server_set_max_live(modap_server *server, int64_t max_live);
+
 /* State and statistics of a request.  Errors: E_INVAL. */
 modap_status modap_server_info(modap_server *server, int64_t ticket, modap_request_info *out);
 

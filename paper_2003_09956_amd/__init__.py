@@ -37,7 +37,7 @@ EXPORTS = ["modap_create", "modap_destroy", "modap_set_system", "modap_set_x", "
            "modap_batch_query", "modap_batch_set_tile", "modap_batch_get_tile", "modap_batch_autotune",
            "modap_batch_last_error", "modap_server_create", "modap_server_destroy", "modap_server_submit",
            "modap_server_update", "modap_server_round", "modap_server_info", "modap_server_result",
-           "modap_server_totals", "modap_server_last_error"]
+           "modap_server_totals", "modap_server_last_error", "modap_server_set_max_live"]
 
 
 class Params(C.Structure):
@@ -159,6 +159,7 @@ def lib():
         L.modap_server_totals.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.modap_server_last_error.argtypes = [vp]
         L.modap_server_last_error.restype = C.c_char_p
+        L.modap_server_set_max_live.argtypes = [vp, i64]
         for name in EXPORTS:
             if name not in ("modap_destroy", "modap_strerror", "modap_last_error", "modap_batch_destroy",
                             "modap_batch_last_error", "modap_server_destroy", "modap_server_last_error"):
@@ -580,6 +581,9 @@ class Server:
         x = np.empty(self.shapes[int(ticket)][1])
         self._check(lib().modap_server_result(self._h, int(ticket), x.ctypes.data_as(C.c_void_p)))
         return x
+
+    def set_max_live(self, k):
+        self._check(lib().modap_server_set_max_live(self._h, int(k)))
 
     def totals(self):
         b, r, u = C.c_double(), C.c_int64(), C.c_double()

@@ -62,6 +62,8 @@ struct modap_server {
     double budget = 0.0, used = 0.0;
     modap_params params{};
     int iters_per_round = 8;
+    int64_t max_live = 0;       // 0: no limit besides the budget
+    int64_t live = 0;
     int64_t max_sweeps = 0;
     modap_batch *batch = nullptr;
     hipStream_t batch_stream = nullptr;
@@ -111,6 +113,7 @@ void drop(modap_server *s, Req &r) {
     r.A = nullptr;
     r.b = r.x0 = r.V = nullptr;
     s->used -= r.footprint;
+    --s->live;
 }
 
 // Admit request r: copy its data into the batch or a new context.  On
@@ -152,6 +155,7 @@ modap_status admit(modap_server *s, Req &r, double now) {
     r.state = RQ_LIVE;
     r.t_admit = now;
     s->used += r.footprint;
+    ++s->live;
     return MODAP_OK;
 }
 
@@ -266,6 +270,7 @@ modap_status modap_server_round(modap_server *s, double now, int64_t *outstandin
     while (!s->pending.empty()) {
         Req &r = s->reqs[(size_t)s->pending.front()];
         if (s->used + r.footprint > s->budget) break;
+        if (s->max_live > 0 && s->live >= s->max_live) break;
         s->pending.pop_front();
         st = admit(s, r, now + elapsed_since(t0));
         r.A = nullptr;  // the caller's memory is no longer read
@@ -315,6 +320,13 @@ modap_status modap_server_round(modap_server *s, double now, int64_t *outstandin
         for (const Req &r : s->reqs) cnt += r.state == RQ_LIVE;
         *outstanding = cnt;
     }
+    return MODAP_OK;
+}
+
+modap_status modap_server_set_max_live(modap_server *s, int64_t max_live) {
+    if (!s) return MODAP_E_INVAL;
+    if (max_live < 0) return fail(s, MODAP_E_INVAL, "max_live < 0");
+    s->max_live = max_live;
     return MODAP_OK;
 }
 
