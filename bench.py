@@ -60,6 +60,10 @@ MULTI = {
     "batch-f32-512": "512 FP32 Gaussian systems (n ~ U{64..2048}, m ~ U{2n..8n}), each with its own drift "
                      "N(0,1e-3^2) per coordinate per iteration, advanced together (one persistent sweep launch "
                      "per iteration), lambda=1, eps=1e-6*||b||inf, autotuned tiles",
+    "catchup-box": "box-plus-sum system (FP64, dense, m=2n+1) translated along (1,...,1) at r units per "
+                   "coordinate per wall-clock second; the highest r at which ModAP (lambda=1) still reaches "
+                   "eps-feasibility (distance 1e-6) from x0=0 one unit outside (the translation experiment of "
+                   "section 5)",
     "serve-bf16-poisson": "Poisson arrivals of BF16 Gaussian systems (n log-uniform in [128,16384], m=4n), every "
                           "10 ms each live system translated (|v|=1e-4) and 1% of its rows replaced, admission by "
                           "HBM footprint, ModAP lambda=0.1, eps=1e-6*||b||inf; the same arrivals and updates served "
@@ -159,6 +163,8 @@ def main():
     ap.add_argument("--rate", type=float, default=5.0, help="serving: Poisson arrival rate per second")
     ap.add_argument("--horizon", type=float, default=10.0, help="serving: seconds of arrivals")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving: HBM budget of the server")
+    ap.add_argument("--n", type=int, default=32000, help="translation experiment: number of variables")
+    ap.add_argument("--lam", type=float, default=1.0, help="translation experiment: ModAP step length")
     ap.add_argument("--tile", type=str, default=None,
                     help="force the sweep shape block,lanes_per_row,chunks,rows_per_step,depth,interleave,grid "
                          "(skips the autotuner)")
@@ -194,6 +200,8 @@ def main():
         return bench_batch(args, P, W, torch)
     if args.workload == "serve-bf16-poisson":
         return bench_serve(args, P, W, torch)
+    if args.workload == "catchup-box":
+        return bench_catchup(args, P, W, torch)
 
     K, WU = args.steps, args.warmup
     dt, n, m, sigma, desc = WORKLOADS[args.workload]
@@ -349,6 +357,77 @@ def _replace_rows_device(torch, n, m, k, z, gen, dtype):
     rows = rows.to({"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype])
     nb = rows.to(torch.float64) @ z + torch.rand(k, generator=gen, device="cuda", dtype=torch.float64)
     return idx.contiguous(), rows.contiguous(), nb.contiguous()
+
+
+def catchup_trial(P, s, A, b, n, rate, lam, limit_s, chunk=4):
+    """One run: the polytope starts one unit per coordinate above x0 = 0 and
+    moves at `rate` per coordinate per second of wall clock (translations
+    applied between chunks of iterations, each by rate * elapsed time).
+    Returns (caught, seconds, iterations)."""
+    import numpy as np
+    import torch
+    s.set_system(A, b, dtype="f64")
+    # eps is an absolute distance here: ||b||_inf is dominated by the sum row
+    prm = P.params(lam=lam, eps=1e-6, eps_relative=False, max_iters=10 ** 9)
+    ones = torch.ones(n, device="cuda", dtype=torch.float64)
+    t0 = time.perf_counter()
+    last = t0
+    iters = 0
+    while True:
+        st = s.iterate(chunk, prm)
+        iters += chunk
+        if st.converged:
+            return True, time.perf_counter() - t0, int(st.sweeps)
+        now = time.perf_counter()
+        if now - t0 > limit_s:
+            return False, now - t0, int(st.sweeps)
+        s.update_coeffs(translate=ones * (rate * (now - last)))
+        last = now
+
+
+def bench_catchup(args, P, W, torch):
+    """Highest translation rate at which the iteration catches the moving
+    polytope, found by bisection on measured runs."""
+    import math
+    n = args.n
+    A, b = W.box_sum_device(n, "f64", offset=1.0)
+    torch.cuda.synchronize()
+    lam = args.lam
+    limit = 30.0
+    trials = []
+    with P.Solver(0) as s:
+        # iteration time with the polytope at rest, from the same start
+        s.set_system(A, b, dtype="f64")
+        st = s.iterate(20, P.params(lam=lam, eps=1e-6, eps_relative=False, max_iters=10 ** 9, profile=1,
+                                    track=True))
+        t_iter = (st.sweep_ms + st.reduce_ms) / st.profiled / 1e3
+        r_est = lam / (math.sqrt(n) * t_iter)
+        lo, hi = 0.0, None
+        r = 0.5 * r_est
+        for _ in range(7):
+            caught, secs, sweeps = catchup_trial(P, s, A, b, n, r, lam, limit)
+            trials.append({"rate_per_coord": round(r, 4), "caught": caught, "seconds": round(secs, 3),
+                           "sweeps": sweeps})
+            log("catch-up trial", trials[-1])
+            if caught:
+                lo = r
+                r = r * 1.5 if hi is None else 0.5 * (r + hi)
+            else:
+                hi = r
+                r = 0.5 * (lo + r)
+        tile = s.get_tile()
+    bytes_per_iter = (2 * n + 1) * n * 8 + 24 * (2 * n + 1)
+    line = {
+        "metric": METRIC, "value": round(bytes_per_iter / t_iter / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": 20, "warmup": 0, "ms_per_step": round(t_iter * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic (generated on the device)",
+        "config": {"workload": MULTI["catchup-box"], "n": n, "m": 2 * n + 1, "lambda": lam, "tile": tile,
+                   "A_bytes": (2 * n + 1) * n * 8},
+        "max_caught_rate": {"per_coord": round(lo, 4), "total": round(lo * math.sqrt(n), 2),
+                            "first_missed_per_coord": round(hi, 4) if hi is not None else None,
+                            "model_lambda_over_sqrt_n_t_iter": round(r_est, 4), "trials": trials},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap):

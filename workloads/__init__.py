@@ -231,3 +231,23 @@ def gaussian_device(n: int, m: int, seed: int = 0, dtype: str = "f32", device: s
     z = torch.rand(n, generator=g, device=device, dtype=torch.float64) * 2.0 - 1.0
     b = A.to(torch.float64) @ z + torch.rand(m, generator=g, device=device, dtype=torch.float64)
     return A.contiguous(), b.contiguous(), z
+
+
+def box_sum_device(n: int, dtype: str = "f64", offset: float = 0.0, upper: float = 200.0, device: str = "cuda"):
+    """The ``box_sum`` rows built on the GPU (dense; for the large sizes of the
+    translation experiment), the polytope translated by ``offset`` along
+    (1, ..., 1): rows ``[I; -I; 1^T]``, ``b = [upper + offset; -offset;
+    upper (n - 1) + n offset]``.  Returns (A, b) device tensors."""
+    import torch
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    m = 2 * n + 1
+    A = torch.zeros((m, n), device=device, dtype=tdt)
+    idx = torch.arange(n, device=device)
+    A[idx, idx] = 1
+    A[n + idx, idx] = -1
+    A[2 * n] = 1
+    b = torch.empty(m, device=device, dtype=torch.float64)
+    b[:n] = upper + offset
+    b[n:2 * n] = -offset
+    b[2 * n] = upper * (n - 1) + n * offset
+    return A, b
