@@ -197,11 +197,11 @@ __device__ void batch_item(const BatchArgs &a, const BatchSys &S, int64_t k,
                 for (int e = 0; e < VEC; ++e) tdot = fma(vv[e], av[e], tdot);
             }
         }
-        dot = wave_sum(dot);
+        dot = wave_total(dot);
         const int64_t row = row_of(t);
         double bb = bi;
         if (apply_v) {
-            bb += (double)wave_sum(tdot);
+            bb += (double)wave_total(tdot);
             if (a.write_b && lane == 0) S.b[row] = bb;
         }
         const double r = (double)dot - bb;

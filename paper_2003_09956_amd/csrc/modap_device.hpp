@@ -177,6 +177,45 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// A DPP lane move inside each row of 16 lanes (CTRL is the gfx9 DPP control:
+// 0x00-0xFF quad permutations, 0x140 row mirror, 0x141 half-row mirror).
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wavefront whose lanes are all active, the same
+// bits in every lane, without the LDS permute unit: DPP adds finish each row
+// of 16 lanes (partners xor 1, xor 2, then the half-row and row mirrors; the
+// two operands of every add are the same pair in both lanes, so all 16 lanes
+// hold identical sums), then the four row sums are read as scalars and added
+// as (row0 + row1) + (row2 + row3).  Used on the per-row paths, where the
+// permute round trips of wave_sum sit on the critical path.
+template <typename T>
+__device__ __forceinline__ T wave_total(T v) {
+    v += dpp_move<0xB1>(v);   // quad permutation [1,0,3,2]
+    v += dpp_move<0x4E>(v);   // quad permutation [2,3,0,1]
+    v += dpp_move<0x141>(v);  // half-row mirror
+    v += dpp_move<0x140>(v);  // row mirror
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
 // NaN-propagating maximum (fmax would drop a NaN).
 __device__ __forceinline__ double max_nan(double a, double b) {
     return (b > a || b != b) ? b : a;

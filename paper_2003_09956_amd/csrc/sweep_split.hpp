@@ -122,8 +122,8 @@ __global__ __launch_bounds__(BLOCK) void split_dot(const SplitArgs a) {
                 if (HAS_V) td = fma(vr[c][e], av[e], td);
             }
         }
-        d = wave_sum(d);
-        if (HAS_V) td = wave_sum(td);
+        d = wave_total(d);
+        if (HAS_V) td = wave_total(td);
         const int pp = (int)(t & 1);
         if (lane == 0) {
             red[pp][wave][0] = d;

@@ -215,8 +215,8 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
         }
 #pragma unroll
         for (int q = 0; q < RS; ++q) {
-            dot[q] = wave_sum(dot[q]);
-            if (HAS_V) tdot[q] = wave_sum(tdot[q]);
+            dot[q] = wave_total(dot[q]);
+            if (HAS_V) tdot[q] = wave_total(tdot[q]);
         }
         if (WPG > 1) {
             const int pp = (int)(t & 1);
