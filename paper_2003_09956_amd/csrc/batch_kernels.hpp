@@ -94,7 +94,8 @@ __device__ void batch_item(const BatchArgs &a, const BatchSys &S, int64_t k,
     constexpr int CW = 64 * VEC;                   // columns per chunk
     constexpr int AV = 16 / (int)sizeof(Acc);      // Acc per 16-byte vector
     constexpr int COLS = C * CW;                   // staged columns (>= ldA)
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wavefront
     const int64_t band = k - S.item0;
     const int64_t r0 = band * S.rows_per_item;
     const int64_t r1 = min(S.m, r0 + S.rows_per_item);
@@ -107,19 +108,24 @@ __device__ void batch_item(const BatchArgs &a, const BatchSys &S, int64_t k,
     const int64_t nrows = r1 - r0;
     const int64_t nmine = nrows > wave ? (nrows - wave + kBatchWaves - 1) / kBatchWaves : 0;
     auto row_of = [&](int64_t t) -> int64_t { return r0 + wave + t * kBatchWaves; };
+    // Rows are read through a buffer resource per row (range = the padded
+    // row, so columns past it read as zeros), b and nu ahead of the row.  A
+    // step past the wavefront's last row reads the item's first row again
+    // (from L2): every pass of the row loop issues the same loads, so the
+    // compiler can count exactly which of them a row still waits for.
+    const uint32_t row_range = (uint32_t)row_bytes;
     auto load_row = [&](uint4 (&buf)[C], double &bi, double &ni, int64_t t) {
-        const int64_t row = min(row_of(t), r1 - 1);
-        const char *rp = Ab + row * row_bytes;
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-            buf[c] = load_stream(rp + min((int64_t)col_of(c), ldA - VEC) * (int64_t)sizeof(T));
+        const int64_t row = t < nmine ? row_of(t) : r0;
         bi = S.b[row];
         ni = S.nu[row];
+        const __amdgpu_buffer_rsrc_t rr = row_resource(Ab + row * row_bytes, row_range);
+#pragma unroll
+        for (int c = 0; c < C; ++c) buf[c] = load_row_vec(rr, (uint32_t)(col_of(c) * (int)sizeof(T)));
     };
     uint4 bufA[C], bufB[C];
-    double bA = 0.0, nA = 1.0, bB = 0.0, nB = 1.0;
-    if (nmine > 0) load_row(bufA, bA, nA, 0);
-    if (nmine > 1) load_row(bufB, bB, nB, 1);
+    double bA, nA, bB, nB;
+    load_row(bufA, bA, nA, 0);
+    load_row(bufB, bB, nB, 1);
 
     Pending pd{S.ctl, a.j, S.tot, S.ynp, S.R, a.decide, a.dp};
     const State st = sweep_state(pd, lane, band == 0 && tid == 0);
@@ -171,10 +177,19 @@ __device__ void batch_item(const BatchArgs &a, const BatchSys &S, int64_t k,
         for (int e = 0; e < VEC; ++e) yacc[c][e] = (Acc)0;
     int64_t h = 0;
     double dmax = 0.0, binf = 0.0;
+    // The translated b of the wavefront's rows is collected in a register,
+    // lane i holding that of the wavefront's row 64 q + i, and written for
+    // 64 rows at a time: a global store inside the row loop would leave
+    // loads and stores outstanding together, and the compiler would then wait
+    // for every outstanding load before each use of a row.
+    const bool keep_b = apply_v && a.write_b;
+    double bkeep = 0.0;
+    auto write_b = [&](int64_t t_last) {
+        const int64_t t0 = t_last & ~(int64_t)63;
+        if (t0 + lane <= t_last) S.b[row_of(t0 + lane)] = bkeep;
+        __builtin_amdgcn_s_waitcnt(0);  // the stores are done before rows are counted again
+    };
     auto process = [&](uint4 (&buf)[C], double bi, double ni, int64_t t) {
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-            if (col_of(c) >= ldA) buf[c] = make_uint4(0u, 0u, 0u, 0u);
         Acc dot = (Acc)0, tdot = (Acc)0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -198,12 +213,9 @@ __device__ void batch_item(const BatchArgs &a, const BatchSys &S, int64_t k,
             }
         }
         dot = wave_total(dot);
-        const int64_t row = row_of(t);
         double bb = bi;
-        if (apply_v) {
-            bb += (double)wave_total(tdot);
-            if (a.write_b && lane == 0) S.b[row] = bb;
-        }
+        if (apply_v) bb += (double)wave_total(tdot);
+        if (keep_b && lane == (int)(t & 63)) bkeep = bb;
         const double r = (double)dot - bb;
         binf = max_nan(binf, fabs(bb));
         if (r > 0.0) {
@@ -221,13 +233,17 @@ __device__ void batch_item(const BatchArgs &a, const BatchSys &S, int64_t k,
             dmax = r;
         }
     };
-    for (int64_t t = 0; t < nmine; t += 2) {
+    int64_t t = 0;
+    for (; t + 2 <= nmine; t += 2) {
+        process(bufA, bA, nA, t);   // t is even: never the 64th row of a group
+        load_row(bufA, bA, nA, t + 2);
+        process(bufB, bB, nB, t + 1);
+        if (keep_b && (((t + 2) & 63) == 0 || t + 2 == nmine)) write_b(t + 1);
+        load_row(bufB, bB, nB, t + 3);
+    }
+    if (t < nmine) {
         process(bufA, bA, nA, t);
-        if (t + 2 < nmine) load_row(bufA, bA, nA, t + 2);
-        if (t + 1 < nmine) {
-            process(bufB, bB, nB, t + 1);
-            if (t + 3 < nmine) load_row(bufB, bB, nB, t + 3);
-        }
+        if (keep_b) write_b(t);
     }
 
     // The wavefronts' partials are summed pairwise in LDS (the staging space

@@ -8,8 +8,7 @@
     MODAP_SHAPE(256, 256, 2, 1, 2), MODAP_SHAPE(256, 256, 4, 1, 2), MODAP_SHAPE(256, 256, 2, 2, 2),       \
     MODAP_SHAPE(512, 512, 2, 1, 2), MODAP_SHAPE(512, 512, 4, 1, 2), MODAP_SHAPE(512, 512, 2, 2, 2),       \
     MODAP_SHAPE(1024, 1024, 1, 1, 2), MODAP_SHAPE(1024, 1024, 1, 1, 4),                                   \
-    MODAP_SHAPE(256, 256, 4, 1, 3), MODAP_SHAPE(256, 256, 4, 1, 4), MODAP_SHAPE(512, 512, 2, 2, 3),       \
-    MODAP_SHAPE(512, 512, 4, 1, 3), MODAP_SHAPE(512, 512, 4, 1, 4)
+    MODAP_SHAPE(256, 256, 4, 1, 3), MODAP_SHAPE(512, 512, 2, 2, 3), MODAP_SHAPE(512, 512, 4, 1, 3)
 // split-row form: 256 lanes x 4 chunks per column tile
 #define MODAP_SPLIT_C 4
 #include "sweep_inst.inc"

@@ -11,7 +11,7 @@
     MODAP_SHAPE(512, 512, 2, 2, 2), MODAP_SHAPE(512, 512, 4, 2, 2), MODAP_SHAPE(512, 512, 2, 4, 2),       \
     MODAP_SHAPE(1024, 1024, 2, 1, 2), MODAP_SHAPE(512, 256, 8, 1, 2), MODAP_SHAPE(512, 256, 4, 1, 2),     \
     MODAP_SHAPE(512, 512, 4, 1, 3), MODAP_SHAPE(512, 512, 4, 1, 4),                                      \
-    MODAP_SHAPE(512, 512, 4, 2, 3), MODAP_SHAPE(1024, 1024, 2, 1, 3), MODAP_SHAPE(1024, 1024, 2, 1, 4)
+    MODAP_SHAPE(1024, 1024, 2, 1, 3)
 // split-row form: 256 lanes x 8 chunks per column tile
 #define MODAP_SPLIT_C 8
 #include "sweep_inst.inc"

@@ -7,7 +7,7 @@
     MODAP_SHAPE(256, 64, 1, 2, 2), MODAP_SHAPE(256, 64, 2, 2, 2), MODAP_SHAPE(256, 64, 4, 2, 2),          \
     MODAP_SHAPE(256, 256, 2, 1, 2), MODAP_SHAPE(256, 256, 4, 1, 2), MODAP_SHAPE(256, 256, 8, 1, 2),       \
     MODAP_SHAPE(256, 256, 2, 2, 2), MODAP_SHAPE(256, 256, 4, 2, 2),                                    \
-    MODAP_SHAPE(512, 512, 2, 1, 2), MODAP_SHAPE(512, 512, 4, 1, 2), MODAP_SHAPE(512, 512, 8, 1, 2),       \
+    MODAP_SHAPE(512, 512, 2, 1, 2), MODAP_SHAPE(512, 512, 4, 1, 2),                                      \
     MODAP_SHAPE(512, 512, 2, 2, 2), MODAP_SHAPE(512, 512, 4, 2, 2)
 // split-row form: 256 lanes x 8 chunks per column tile
 #define MODAP_SPLIT_C 8

@@ -98,18 +98,21 @@ __global__ __launch_bounds__(BLOCK) void split_dot(const SplitArgs a) {
     }
     const char *Ab = reinterpret_cast<const char *>(a.A);
     const int64_t row_bytes = a.ldA * (int64_t)sizeof(T);
+    // Rows through a buffer resource each (columns past the padded row read
+    // as zeros).  Loads past the band re-read its last row, so every pass of
+    // the row loop issues the same loads and the compiler can count which of
+    // them a row still waits for.
+    const uint32_t row_range = (uint32_t)row_bytes;
     auto load_row = [&](uint4 (&buf)[C], int64_t row) {
-        const char *rp = Ab + min(row, r1 - 1) * row_bytes;
+        const __amdgpu_buffer_rsrc_t rr = row_resource(Ab + min(row, r1 - 1) * row_bytes, row_range);
 #pragma unroll
-        for (int c = 0; c < C; ++c) buf[c] = load_stream(rp + min(col_of(c), a.ldA - VEC) * (int64_t)sizeof(T));
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-            if (col_of(c) >= a.ldA) buf[c] = make_uint4(0u, 0u, 0u, 0u);
+        for (int c = 0; c < C; ++c) buf[c] = load_row_vec(rr, (uint32_t)(col_of(c) * (int64_t)sizeof(T)));
     };
     Acc *pd = reinterpret_cast<Acc *>(a.pdot);
     Acc *pt = pd + (int64_t)a.ntiles * a.m;
     __shared__ Acc red[2][NW][2];
     uint4 bufA[C], bufB[C];
+    Acc kd = (Acc)0, kt = (Acc)0;
     auto process = [&](const uint4 (&buf)[C], int64_t row, int64_t t) {
         Acc d = (Acc)0, td = (Acc)0;
 #pragma unroll
@@ -130,26 +133,43 @@ __global__ __launch_bounds__(BLOCK) void split_dot(const SplitArgs a) {
             red[pp][wave][1] = td;
         }
         __syncthreads();
-        if (tid == 0 && row < r1) {
+        // thread t mod BLOCK keeps the tile dots of the band's row t; they
+        // are written BLOCK rows at a time (no global store in the row loop,
+        // so that only loads are outstanding there)
+        if (tid == (int)(t & (BLOCK - 1))) {
             Acc s = (Acc)0, ts = (Acc)0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 s += red[pp][w][0];
                 ts += red[pp][w][1];
             }
-            pd[(int64_t)blockIdx.y * a.m + row] = s;
-            pt[(int64_t)blockIdx.y * a.m + row] = ts;
+            kd = s;
+            kt = ts;
         }
+    };
+    auto write_out = [&](int64_t t_last) {
+        const int64_t t0 = t_last & ~(int64_t)(BLOCK - 1);
+        if (t0 + tid <= t_last) {
+            pd[(int64_t)blockIdx.y * a.m + r0 + t0 + tid] = kd;
+            pt[(int64_t)blockIdx.y * a.m + r0 + t0 + tid] = kt;
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // the stores are done before rows are counted again
     };
     const int64_t nrows = r1 - r0;
     load_row(bufA, r0);
-    for (int64_t t = 0; t < nrows; t += 2) {
-        if (t + 1 < nrows) load_row(bufB, r0 + t + 1);
+    load_row(bufB, r0 + 1);
+    int64_t t = 0;
+    for (; t + 2 <= nrows; t += 2) {
         process(bufA, r0 + t, t);
-        if (t + 1 < nrows) {
-            if (t + 2 < nrows) load_row(bufA, r0 + t + 2);
-            process(bufB, r0 + t + 1, t + 1);
-        }
+        if (((t + 1) & (BLOCK - 1)) == 0) write_out(t);
+        load_row(bufA, r0 + t + 2);
+        process(bufB, r0 + t + 1, t + 1);
+        if (((t + 2) & (BLOCK - 1)) == 0 || t + 2 == nrows) write_out(t + 1);
+        load_row(bufB, r0 + t + 3);
+    }
+    if (t < nrows) {
+        process(bufA, r0 + t, t);
+        write_out(t);
     }
 }
 
@@ -266,17 +286,18 @@ __global__ __launch_bounds__(BLOCK) void split_axpy(const SplitArgs a) {
         for (int e = 0; e < VEC; ++e) yacc[c][e] = (Acc)0;
     const char *Ab = reinterpret_cast<const char *>(a.A);
     const int64_t row_bytes = a.ldA * (int64_t)sizeof(T);
-    auto load_row = [&](uint4 (&buf)[C], int k) {
+    // as in split_dot: a buffer resource per row, and loads past the list
+    // re-read its last row so that every pass of the loop issues the same loads
+    const uint32_t row_range = (uint32_t)row_bytes;
+    auto load_row = [&](uint4 (&buf)[C], double &wk, int k) {
         const int64_t row = r0 + list[min(k, nv - 1)];
-        const char *rp = Ab + row * row_bytes;
+        wk = a.w[row];   // ahead of the row (loads return in order)
+        const __amdgpu_buffer_rsrc_t rr = row_resource(Ab + row * row_bytes, row_range);
 #pragma unroll
-        for (int c = 0; c < C; ++c) buf[c] = load_stream(rp + min(col_of(c), a.ldA - VEC) * (int64_t)sizeof(T));
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-            if (col_of(c) >= a.ldA) buf[c] = make_uint4(0u, 0u, 0u, 0u);
+        for (int c = 0; c < C; ++c) buf[c] = load_row_vec(rr, (uint32_t)(col_of(c) * (int64_t)sizeof(T)));
     };
-    auto accumulate = [&](const uint4 (&buf)[C], int k) {
-        const Acc wk = (Acc)a.w[r0 + list[k]];
+    auto accumulate = [&](const uint4 (&buf)[C], double w) {
+        const Acc wk = (Acc)w;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             Acc av[VEC];
@@ -286,14 +307,18 @@ __global__ __launch_bounds__(BLOCK) void split_axpy(const SplitArgs a) {
         }
     };
     uint4 bufA[C], bufB[C];
-    if (nv > 0) load_row(bufA, 0);
-    for (int k = 0; k < nv; k += 2) {
-        if (k + 1 < nv) load_row(bufB, k + 1);
-        accumulate(bufA, k);
-        if (k + 1 < nv) {
-            if (k + 2 < nv) load_row(bufA, k + 2);
-            accumulate(bufB, k + 1);
+    double wA, wB;
+    if (nv > 0) {
+        load_row(bufA, wA, 0);
+        load_row(bufB, wB, 1);
+        int k = 0;
+        for (; k + 2 <= nv; k += 2) {
+            accumulate(bufA, wA);
+            load_row(bufA, wA, k + 2);
+            accumulate(bufB, wB);
+            load_row(bufB, wB, k + 3);
         }
+        if (k < nv) accumulate(bufA, wA);
     }
     Acc *part = reinterpret_cast<Acc *>(a.part) + (int64_t)blockIdx.x * a.ldPart;
 #pragma unroll

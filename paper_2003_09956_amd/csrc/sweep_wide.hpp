@@ -44,6 +44,20 @@ __device__ __forceinline__ uint4 load_stream(const char *p) {
     return make_uint4(t.x, t.y, t.z, t.w);
 }
 
+// A buffer resource for one row: wave-uniform base (scalar registers), range
+// = the padded row in bytes, raw addressing (word 3 is the gfx9 value for
+// untyped dword access).  A load addressed past the range returns zeros.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_resource(const char *row, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(row), (short)0, (int)bytes, 0x00020000);
+}
+
+// One 16-byte vector of a row through its resource, non-temporal (aux bit 1),
+// at a 32-bit per-lane byte offset.
+__device__ __forceinline__ uint4 load_row_vec(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 2);
+    return make_uint4(t.x, t.y, t.z, t.w);
+}
+
 template <int DT>
 __device__ __forceinline__ void unpack(const uint4 &u, typename Store<DT>::Acc (&o)[Store<DT>::VEC]);
 
@@ -90,7 +104,9 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int grp = tid / LPR;
+    // the row group is the same for every lane of a wavefront (LPR is a
+    // multiple of 64): say so, so that row addresses stay in scalar registers
+    const int grp = __builtin_amdgcn_readfirstlane(tid / LPR);
     const int gl = tid % LPR;
     const int rot = (int)(blockIdx.x % C);
 
@@ -113,26 +129,32 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
     auto row_of = [&](int64_t t, int q) -> int64_t { return r0 + t * a.step_stride + grp * RS + q; };
     // Loads are issued unconditionally (addresses clamped into the row band and
     // the padded row) so that no branch separates them; rows past the band
-    // and columns past the padded row are discarded afterwards.
+    // and columns past the padded row are discarded afterwards.  A step past
+    // the last one (the ring's look-ahead at the end of the band) reads row 0,
+    // which every workgroup shares from L2, instead of a row of its own:
+    // every pass of the row loop then issues the same loads, which lets the
+    // compiler count exactly which of them a row still waits for.
+    //
+    // Each row is read through a buffer resource whose range is the padded
+    // row: the chunks of a lane that lie past it read as zeros, which is what
+    // the products need there, and the per-lane address is a 32-bit offset.
+    const uint32_t row_range = (uint32_t)row_bytes;
+    uint32_t coff[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) coff[c] = (uint32_t)(col_of(c) * (int64_t)sizeof(T));
     auto load_rows = [&](uint4 (&buf)[RS][C], double (&bi)[RS], double (&nui)[RS], int64_t t) {
+        const bool live = t < nsteps;
 #pragma unroll
         for (int q = 0; q < RS; ++q) {
-            const int64_t row = min(row_of(t, q), r1 - 1);
-            const char *rp = Ab + row * row_bytes;
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                buf[q][c] = load_stream(rp + min(col_of(c), a.ldA - VEC) * (int64_t)sizeof(T));
+            const int64_t row = live ? min(row_of(t, q), r1 - 1) : 0;
+            // b and nu first: loads return in order, so once the row has
+            // arrived they have too, and no register of a reduced row is
+            // still waiting for data when the buffer is refilled
             bi[q] = a.b_in[row];
             nui[q] = a.nu[row];
-        }
-    };
-    auto mask_cols = [&](uint4 (&buf)[RS][C]) {
+            const __amdgpu_buffer_rsrc_t rr = row_resource(Ab + row * row_bytes, row_range);
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            if (col_of(c) >= a.ldA) {
-#pragma unroll
-                for (int q = 0; q < RS; ++q) buf[q][c] = make_uint4(0u, 0u, 0u, 0u);
-            }
+            for (int c = 0; c < C; ++c) buf[q][c] = load_row_vec(rr, coff[c]);
         }
     };
 
@@ -144,8 +166,7 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
     uint4 buf[PD][RS][C];
     double bq[PD][RS], nq[PD][RS];
 #pragma unroll
-    for (int k = 0; k < PD; ++k)
-        if (k < nsteps) load_rows(buf[k], bq[k], nq[k], k);
+    for (int k = 0; k < PD; ++k) load_rows(buf[k], bq[k], nq[k], k);
 
     Acc xr[C][VEC];
     Acc vr[C][VEC];
@@ -196,6 +217,33 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
     double dmax = 0.0, binf = 0.0;
     __shared__ Acc red[2][NW][RS][2];
 
+    // Per-row results bound for global memory (the translated b, and r when
+    // asked for) are staged in LDS and written together every KS steps and
+    // after the last one.  A global store inside the row loop would leave
+    // loads and stores outstanding together; the compiler can then no longer
+    // count which loads have returned and waits for all of them, the
+    // prefetched rows included, before each use of a row.
+    constexpr int SR = NG * RS;                   // rows per step
+    constexpr int KS = SR >= 256 ? 1 : 256 / SR;  // steps per write-out
+    __shared__ double bst[KS * SR], rst[KS * SR];
+    const bool stage_b = apply_v && a.b_out != nullptr;
+    const bool stage_r = a.r_out != nullptr;
+    auto write_out = [&](int64_t t_last) {
+        const int64_t t0 = t_last - t_last % KS;
+        const int cnt = (int)(t_last - t0 + 1) * SR;
+        __syncthreads();
+        for (int i = tid; i < cnt; i += BLOCK) {
+            const int64_t row = r0 + (t0 + i / SR) * a.step_stride + i % SR;
+            if (row < r1) {
+                if (stage_b) a.b_out[row] = bst[i];
+                if (stage_r) a.r_out[row] = rst[i];
+            }
+        }
+        // every store has completed before the loop's loads are counted again
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    };
+
     auto process = [&](const uint4 (&buf)[RS][C], const double (&bi)[RS], const double (&nui)[RS], int64_t t) {
         Acc dot[RS], tdot[RS];
 #pragma unroll
@@ -245,12 +293,11 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
             const int64_t row = row_of(t, q);
             if (row >= r1) continue;
             double bb = bi[q];
-            if (apply_v) {
-                bb += (double)tdot[q];
-                if (a.b_out && gl == 0) a.b_out[row] = bb;
-            }
+            if (apply_v) bb += (double)tdot[q];
             const double r = (double)dot[q] - bb;
-            if (a.r_out && gl == 0) a.r_out[row] = r;
+            const int si = (int)(t % KS) * SR + grp * RS + q;
+            if (stage_b && gl == 0) bst[si] = bb;
+            if (stage_r && gl == 0) rst[si] = r;
             binf = max_nan(binf, fabs(bb));
             if (r > 0.0) {
                 ++h;
@@ -274,15 +321,23 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
     // reduced.  nsteps is the same for the whole workgroup, so every branch
     // below is uniform and the barriers inside process() are reached by all
     // lanes.
-    for (int64_t t = 0; t < nsteps; t += PD) {
+    int64_t t = 0;
+    for (; t + PD <= nsteps; t += PD) {
 #pragma unroll
         for (int k = 0; k < PD; ++k) {
             const int64_t tk = t + k;
-            if (tk < nsteps) {
-                mask_cols(buf[k]);
-                process(buf[k], bq[k], nq[k], tk);
-                if (tk + PD < nsteps) load_rows(buf[k], bq[k], nq[k], tk + PD);
-            }
+            process(buf[k], bq[k], nq[k], tk);
+            if ((stage_b || stage_r) && ((tk + 1) % KS == 0 || tk + 1 == nsteps)) write_out(tk);
+            load_rows(buf[k], bq[k], nq[k], tk + PD);
+        }
+    }
+    // the last nsteps % PD steps, already in the ring
+#pragma unroll
+    for (int k = 0; k < PD - 1; ++k) {
+        const int64_t tk = t + k;
+        if (tk < nsteps) {
+            process(buf[k], bq[k], nq[k], tk);
+            if ((stage_b || stage_r) && ((tk + 1) % KS == 0 || tk + 1 == nsteps)) write_out(tk);
         }
     }
 

@@ -56,7 +56,7 @@ ALL_SHAPES = {  # (block, lanes per row, chunks, rows per step, depth), as compi
     "f64": [
             (256, 64, 1, 1, 2), (256, 64, 2, 1, 2), (256, 64, 4, 1, 2), (256, 64, 1, 2, 2), (256, 64, 2, 2, 2),
             (256, 64, 4, 2, 2), (256, 256, 2, 1, 2), (256, 256, 4, 1, 2), (256, 256, 8, 1, 2), (256, 256, 2, 2, 2),
-            (256, 256, 4, 2, 2), (512, 512, 2, 1, 2), (512, 512, 4, 1, 2), (512, 512, 8, 1, 2),
+            (256, 256, 4, 2, 2), (512, 512, 2, 1, 2), (512, 512, 4, 1, 2),
             (512, 512, 2, 2, 2), (512, 512, 4, 2, 2)],
     "f32": [
             (256, 64, 1, 1, 2), (256, 64, 2, 1, 2), (256, 64, 4, 1, 2), (256, 64, 1, 2, 2), (256, 64, 2, 2, 2),
@@ -64,14 +64,12 @@ ALL_SHAPES = {  # (block, lanes per row, chunks, rows per step, depth), as compi
             (256, 256, 4, 2, 2), (256, 256, 2, 4, 2), (512, 512, 2, 1, 2), (512, 512, 4, 1, 2),
             (512, 512, 8, 1, 2), (512, 512, 2, 2, 2), (512, 512, 4, 2, 2), (512, 512, 2, 4, 2),
             (1024, 1024, 2, 1, 2), (512, 256, 8, 1, 2), (512, 256, 4, 1, 2),
-            (512, 512, 4, 1, 3), (512, 512, 4, 1, 4), (512, 512, 4, 2, 3), (1024, 1024, 2, 1, 3),
-            (1024, 1024, 2, 1, 4)],
+            (512, 512, 4, 1, 3), (512, 512, 4, 1, 4), (1024, 1024, 2, 1, 3)],
     "bf16": [
             (256, 64, 1, 1, 2), (256, 64, 2, 1, 2), (256, 64, 4, 1, 2), (256, 64, 1, 2, 2), (256, 64, 2, 2, 2),
             (256, 256, 2, 1, 2), (256, 256, 4, 1, 2), (256, 256, 2, 2, 2), (512, 512, 2, 1, 2),
             (512, 512, 4, 1, 2), (512, 512, 2, 2, 2), (1024, 1024, 1, 1, 2), (1024, 1024, 1, 1, 4),
-            (256, 256, 4, 1, 3), (256, 256, 4, 1, 4), (512, 512, 2, 2, 3), (512, 512, 4, 1, 3),
-            (512, 512, 4, 1, 4)],
+            (256, 256, 4, 1, 3), (512, 512, 2, 2, 3), (512, 512, 4, 1, 3)],
 }
 VEC = {"f64": 2, "f32": 4, "bf16": 8}
 
