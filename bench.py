@@ -23,7 +23,9 @@ timed steps, m*n*sizeof(A) + 24*m bytes per step (A, b read and written,
 sweep kernel's average duration (HIP events recorded by the dispatches of every
 tenth timed iteration, on the library's stream); time-to-feasible p50/p99 comes
 from solves of the FP64 box-plus-sum system (n=256, m=513, 20 seeds) and of the
-default FP32 system under its drift; `cpu_baseline` times the CPU oracle on a
+default FP32 system from x0 = 0 under 10 drift sequences (at most 3000
+iterations each; a chase not ended by then counts as slower than every ended
+one); `cpu_baseline` times the CPU oracle on a
 bounded number of iterations of the same system.
 """
 from __future__ import annotations
@@ -31,6 +33,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -40,6 +43,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_EVERY = 10      # one iteration in ten carries HIP events on its kernel dispatches
+DRIFT_SEEDS = 10        # drift sequences of the time-to-feasible chase on the default system
+DRIFT_STEPS = 3000      # iterations allowed per chase
 METRIC = "pseudo-projection sweep HBM GB/s (% of peak); p50/p99 time-to-feasible"
 KERNEL_SOURCES = ["paper_2003_09956_amd/csrc/sweep_wide.hpp", "paper_2003_09956_amd/csrc/modap_device.hpp",
                   "paper_2003_09956_amd/csrc/sweep_inst.inc"]
@@ -245,16 +250,27 @@ def main():
         feasible_steps = int(st.sweeps - st.iters)
         log(f"timed {K} steps in {wall * 1e3:.2f} ms; sweep {sweep_us:.1f} us, reduce {reduce_us:.1f} us")
 
-        # time-to-feasible on the same moving system, from x0 = 0
+        # time-to-feasible on the same moving system, from x0 = 0, over
+        # DRIFT_SEEDS drift sequences (whether and when the chase ends is
+        # decided by the random walk of the drift, so one sequence says little)
         ttf_drift = None
         if not args.no_ttf and default_workload:
-            s.set_system(sys_.A, sys_.b, dtype=dt)
-            V2 = W.drift(n, 3000, sigma=sigma, seed=args.seed + 1)
-            s.set_drift(V2)
-            st2, code = s.solve(P.params(lam=lam, eps=eps, max_iters=3000), raise_on_stop=False)
-            ttf_drift = {"caught": code == 0, "ms": st2.seconds * 1e3, "steps": int(st2.iters),
-                         "max_violation": st2.max_viol, "eps_abs": st2.eps_abs}
-            log("ttf under drift", ttf_drift)
+            runs = []
+            for sd in range(DRIFT_SEEDS):
+                s.set_system(sys_.A, sys_.b, dtype=dt)
+                s.set_drift(W.drift(n, DRIFT_STEPS, sigma=sigma, seed=args.seed + 1 + sd))
+                st2, code = s.solve(P.params(lam=lam, eps=eps, max_iters=DRIFT_STEPS), raise_on_stop=False)
+                runs.append((code == 0, st2.seconds * 1e3, int(st2.iters)))
+                log("ttf under drift", sd, runs[-1])
+            # a sequence not caught within DRIFT_STEPS counts as slower than any caught one
+            import numpy as np
+            ms = [r[1] if r[0] else math.inf for r in runs]
+            its = [r[2] if r[0] else math.inf for r in runs]
+            pct = lambda v, q: float(np.percentile(np.asarray(v), q, method="higher"))
+            fin = lambda v: round(v, 3) if math.isfinite(v) else None
+            ttf_drift = {"seeds": DRIFT_SEEDS, "caught": int(sum(r[0] for r in runs)), "max_steps": DRIFT_STEPS,
+                         "p50_ms": fin(pct(ms, 50)), "p99_ms": fin(pct(ms, 99)),
+                         "steps_p50": fin(pct(its, 50))}
 
     value = bytes_per_step * K / wall / 1e9
     achieved = bytes_per_step / (sweep_us * 1e-6) / 1e9

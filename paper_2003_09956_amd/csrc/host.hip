@@ -246,13 +246,10 @@ modap_status configure(modap_ctx *c, const modap_tile &want) {
     const int64_t cov = coverage(c->dt, t.lanes_per_row, t.chunks);
     if (cov < c->ldA) return fail(c, MODAP_E_INVAL, "sweep shape does not cover a row");
     const int per_step = (t.block / t.lanes_per_row) * t.rows_per_step;
-    int grid = t.grid;
-    if (grid <= 0) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kv->func, t.block, 0) != hipSuccess || per_cu < 1)
-            per_cu = 1;
-        grid = c->cu_count * per_cu;
-    }
+    // By default one workgroup per CU: with every row group keeping depth-1
+    // steps of rows in flight, a second workgroup per CU adds no bandwidth
+    // but doubles the partial y written at the end of the sweep.
+    int grid = t.grid > 0 ? t.grid : c->cu_count;
     if (t.interleave != 0 && t.interleave != 1) return fail(c, MODAP_E_INVAL, "tile interleave must be 0 or 1");
     int64_t rpb, block_stride, step_stride;
     if (t.interleave) {
