@@ -60,7 +60,7 @@ struct modap_batch {
     size_t es = 4;
     std::vector<BSys> sys;
     int64_t jn = 0;
-    modap_batch_tile tile{{64, 256, 256, 1024}, 0};   // what the autotuner finds for FP32 rows up to 2048
+    modap_batch_tile tile{{512, 2048, 4096, 4096}, 0};  // near what the autotuner finds for FP32 rows up to 2048
 
     // tables of the current membership (rebuilt when dirty)
     bool dirty = true;
@@ -161,10 +161,17 @@ modap_status ensure_buf(modap_batch *c, P *&p, size_t &cap, size_t count) {
     return MODAP_OK;
 }
 
-// Rows of one work item of a system: about item_kib KiB of A, a multiple of
-// the wavefronts of a workgroup.
+// Rows of one work item of a system: about item_kib KiB of A, but a small
+// system is still cut into kMinItems items of at least kMinItemKib KiB, so
+// that a batch of few systems spreads over the device; a multiple of the
+// wavefronts of a workgroup.  The partition depends on the system and the
+// tile only, never on the other systems of the batch.
+constexpr int64_t kMinItems = 16;
+constexpr int64_t kMinItemKib = 32;
 int64_t rows_per_item(const modap_batch *c, const BSys &s) {
-    const int64_t kib = std::max<int32_t>(1, c->tile.item_kib[bucket_of(s.C)]);
+    const int64_t sys_kib = s.m * s.ldA * (int64_t)c->es / 1024;
+    const int64_t cap = std::max<int32_t>(1, c->tile.item_kib[bucket_of(s.C)]);
+    const int64_t kib = std::min(cap, std::max(kMinItemKib, sys_kib / kMinItems));
     int64_t r = kib * 1024 / (s.ldA * (int64_t)c->es);
     r = std::max<int64_t>(kBatchWaves, (r + kBatchWaves - 1) / kBatchWaves * kBatchWaves);
     return std::min<int64_t>(r, (s.m + kBatchWaves - 1) / kBatchWaves * kBatchWaves);
@@ -746,7 +753,7 @@ modap_status modap_batch_query(modap_batch *c, int64_t id, double *x, double *b,
 modap_status modap_batch_set_tile(modap_batch *c, const modap_batch_tile *t) {
     if (!c) return MODAP_E_INVAL;
     if (!t) {
-        c->tile = modap_batch_tile{{64, 256, 256, 1024}, 0};
+        c->tile = modap_batch_tile{{512, 2048, 4096, 4096}, 0};
     } else {
         for (int q = 0; q < 4; ++q)
             if (t->item_kib[q] < 1) return fail(c, MODAP_E_INVAL, "item_kib must be >= 1");
@@ -800,7 +807,9 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
     };
     modap_batch_tile cur = c->tile;
     cur.grid = 0;
-    const int sizes[] = {32, 64, 128, 256, 512, 1024};
+    // a work item costs a few microseconds beyond its rows (queue, state,
+    // staging, partial): large items pay it rarely, small ones balance better
+    const int sizes[] = {64, 128, 256, 512, 1024, 2048, 4096};
     for (int q = 0; q < 4; ++q) {
         if (!present[q]) continue;
         float win = 1e30f;

@@ -84,7 +84,7 @@ constexpr int kBatchCmax = 8;   // largest C compiled
 // lane's partial y and two rows in flight stay in registers.  Every branch
 // that guards a barrier is uniform over the workgroup.
 template <int DT, int C>
-__device__ void batch_item(const BatchArgs &a, const BatchSys &S, int64_t k,
+__device__ void batch_item(const BatchArgs &a, const BatchSys &Sref, int64_t k,
                            typename Store<DT>::Acc (*lds)[kBatchCmax * 64 * Store<DT>::VEC],
                            int64_t *hsh, double *dsh, double *bsh) {
     using St = Store<DT>;
@@ -96,6 +96,9 @@ __device__ void batch_item(const BatchArgs &a, const BatchSys &S, int64_t k,
     constexpr int COLS = C * CW;                   // staged columns (>= ldA)
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wavefront
+    // The system's fields are read once per item: held in memory, they would
+    // be read again after every store the compiler cannot tell apart from them.
+    const BatchSys S = Sref;
     const int64_t band = k - S.item0;
     const int64_t r0 = band * S.rows_per_item;
     const int64_t r1 = min(S.m, r0 + S.rows_per_item);
@@ -116,8 +119,8 @@ __device__ void batch_item(const BatchArgs &a, const BatchSys &S, int64_t k,
     const uint32_t row_range = (uint32_t)row_bytes;
     auto load_row = [&](uint4 (&buf)[C], double &bi, double &ni, int64_t t) {
         const int64_t row = t < nmine ? row_of(t) : r0;
-        bi = S.b[row];
-        ni = S.nu[row];
+        bi = load_global(S.b + row);
+        ni = load_global(S.nu + row);
         const __amdgpu_buffer_rsrc_t rr = row_resource(Ab + row * row_bytes, row_range);
 #pragma unroll
         for (int c = 0; c < C; ++c) buf[c] = load_row_vec(rr, (uint32_t)(col_of(c) * (int)sizeof(T)));
@@ -142,17 +145,17 @@ __device__ void batch_item(const BatchArgs &a, const BatchSys &S, int64_t k,
     for (int col = tid * AV; col < COLS; col += 256 * AV) {
         Acc xv[AV], vv[AV];
         if (col < ldA) {
-            const uint4 ux = *reinterpret_cast<const uint4 *>(wx + col);
+            const uint4 ux = load_global(reinterpret_cast<const uint4 *>(wx + col));
             __builtin_memcpy(xv, &ux, 16);
             if (s != 0.0) {
                 Acc yv[AV];
-                const uint4 uy = *reinterpret_cast<const uint4 *>(wy + col);
+                const uint4 uy = load_global(reinterpret_cast<const uint4 *>(wy + col));
                 __builtin_memcpy(yv, &uy, 16);
 #pragma unroll
                 for (int q = 0; q < AV; ++q) xv[q] = (Acc)step_point((double)xv[q], s, (double)yv[q]);
             }
             if (apply_v) {
-                const uint4 uv = *reinterpret_cast<const uint4 *>(wv + col);
+                const uint4 uv = load_global(reinterpret_cast<const uint4 *>(wv + col));
                 __builtin_memcpy(vv, &uv, 16);
             } else {
 #pragma unroll
@@ -186,7 +189,7 @@ __device__ void batch_item(const BatchArgs &a, const BatchSys &S, int64_t k,
     double bkeep = 0.0;
     auto write_b = [&](int64_t t_last) {
         const int64_t t0 = t_last & ~(int64_t)63;
-        if (t0 + lane <= t_last) S.b[row_of(t0 + lane)] = bkeep;
+        if (t0 + lane <= t_last) store_global(S.b + row_of(t0 + lane), bkeep);
         __builtin_amdgcn_s_waitcnt(0);  // the stores are done before rows are counted again
     };
     auto process = [&](uint4 (&buf)[C], double bi, double ni, int64_t t) {
@@ -321,12 +324,15 @@ __global__ __launch_bounds__(256) void sweep_batch(const BatchArgs a) {
     __shared__ int64_t hsh[kBatchWaves];
     __shared__ double dsh[kBatchWaves], bsh[kBatchWaves];
     __shared__ int s_item;
-    for (;;) {
-        __syncthreads();  // the previous item's use of LDS is over
-        if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1);
-        __syncthreads();
-        const int k = s_item;
-        if (k >= a.nitems) return;
+    if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1);
+    __syncthreads();
+    int k = s_item;
+    while (k < a.nitems) {
+        // the next item is requested while this one runs; its number reaches
+        // the other threads through LDS after the item's last barrier
+        int next = 0;
+        __syncthreads();  // every thread has read s_item
+        if (threadIdx.x == 0) next = atomicAdd(a.queue, 1);
         const BatchSys &S = a.sys[a.item_sys[k]];
         switch (S.C) {
             case 1: batch_item<DT, 1>(a, S, k, lds, hsh, dsh, bsh); break;
@@ -334,6 +340,9 @@ __global__ __launch_bounds__(256) void sweep_batch(const BatchArgs a) {
             case 4: batch_item<DT, 4>(a, S, k, lds, hsh, dsh, bsh); break;
             default: batch_item<DT, 8>(a, S, k, lds, hsh, dsh, bsh); break;
         }
+        if (threadIdx.x == 0) s_item = next;
+        __syncthreads();  // the item's use of LDS is over, and s_item is set
+        k = s_item;
     }
 }
 

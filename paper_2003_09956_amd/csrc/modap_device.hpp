@@ -165,6 +165,40 @@ struct StageArgs {
 
 __host__ __device__ __forceinline__ int slot_of(int64_t j) { return (int)(j & 1); }
 
+// Accesses through a pointer known to address global memory.  A pointer read
+// from memory is otherwise taken as generic: its accesses become flat ones,
+// which the compiler must count as LDS accesses too when it places waits.
+// (A structure is moved as 16-byte words: an aggregate copy would drop the
+// address space.)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ T load_global(const T *p) {
+    if constexpr (sizeof(T) % 16 == 0 && alignof(T) >= 16) {
+        const __attribute__((address_space(1))) u32x4 *q = (const __attribute__((address_space(1))) u32x4 *)p;
+        u32x4 w[sizeof(T) / 16];
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(T) / 16); ++i) w[i] = q[i];
+        T v;
+        __builtin_memcpy(&v, w, sizeof(T));
+        return v;
+    } else {
+        return *(const __attribute__((address_space(1))) T *)p;
+    }
+}
+template <typename T>
+__device__ __forceinline__ void store_global(T *p, const T &v) {
+    if constexpr (sizeof(T) % 16 == 0 && alignof(T) >= 16) {
+        __attribute__((address_space(1))) u32x4 *q = (__attribute__((address_space(1))) u32x4 *)p;
+        u32x4 w[sizeof(T) / 16];
+        __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(T) / 16); ++i) q[i] = w[i];
+    } else {
+        *(__attribute__((address_space(1))) T *)p = v;
+    }
+}
+
 // x - s*y with one rounding.
 __device__ __forceinline__ double step_point(double x, double s, double y) {
     return __fma_rn(-s, y, x);
@@ -225,7 +259,7 @@ __device__ __forceinline__ double max_nan(double a, double b) {
 // wavefront; every lane returns the same value, in every workgroup.
 __device__ __forceinline__ double ynorm_of(const double *ynp, int R, int lane) {
     double s = 0.0;
-    for (int r = lane; r < R; r += 64) s += ynp[r];
+    for (int r = lane; r < R; r += 64) s += load_global(ynp + r);
     s = wave_sum(s);
     return sqrt(s);
 }
@@ -275,11 +309,15 @@ __device__ __forceinline__ State decide(const State &p, const Totals &t, double 
 // wavefronts (the norm of y is summed across the wavefront); `writer` commits
 // a fresh decision.
 __device__ __forceinline__ State sweep_state(const Pending &pd, int lane, bool writer) {
-    if (!pd.decide) return pd.ctl->st[slot_of(pd.j - 1)];
-    const State p = pd.ctl->st[slot_of(pd.j - 2)];
+    if (!pd.decide) return load_global(&pd.ctl->st[slot_of(pd.j - 1)]);
+    // every load first (none depends on another), then the decision
+    const State p = load_global(&pd.ctl->st[slot_of(pd.j - 2)]);
+    const Totals t = load_global(pd.tot);
+    const int64_t limit = load_global(&pd.ctl->step_limit);
+    const int64_t len = load_global(&pd.ctl->sched_len);
     const double yn = ynorm_of(pd.ynp, pd.R, lane);
-    const State s = decide(p, *pd.tot, yn, pd.dp, pd.ctl->step_limit, pd.ctl->sched_len);
-    if (writer) pd.ctl->st[slot_of(pd.j - 1)] = s;
+    const State s = decide(p, t, yn, pd.dp, limit, len);
+    if (writer) store_global(&pd.ctl->st[slot_of(pd.j - 1)], s);
     return s;
 }
 

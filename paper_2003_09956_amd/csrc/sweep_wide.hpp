@@ -35,8 +35,6 @@
 
 namespace modap {
 
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
 // Rows of A are read exactly once per sweep: stream them past the caches
 // (non-temporal) so that the working vectors, b and the partials keep theirs.
 __device__ __forceinline__ uint4 load_stream(const char *p) {
