@@ -148,6 +148,33 @@ def test_batch_update_rows_and_translation(P):
     assert np.max(np.abs(b1 - b2) / scale) <= tol
 
 
+def test_batch_long_items_write_b_in_the_row_loop(P):
+    """A system cut into items of about 500 rows (125 per wavefront): the
+    translated b the wavefronts keep is written out inside the row loop as
+    well as after it.  Each step and the translated b follow the oracle."""
+    sys_ = W.gaussian(100, 8000, seed=13, dtype="f32")
+    V = W.drift(100, 10, sigma=1e-3, seed=13)
+    lam = 0.3
+    prm = P.params(lam=lam, eps=1e-9)
+    x = sys_.z + 0.3
+    b = sys_.b.copy()
+    with P.Batch("f32") as B:
+        sid = B.add(sys_.A, sys_.b, x0=x)
+        B.set_drift(sid, V)
+        for k in range(3):
+            say(f"batch long items k={k}")
+            B.iterate(1, prm)
+            x1, b1, q = B.query(sid, want_b=True)
+            o = oracle.sweep(sys_.A, "f32", b, x)
+            xo, status = oracle.step(o.y, o.h, 0, lam, x)
+            assert status == 0 and q.iters == k + 1
+            assert np.linalg.norm(x1 - xo) <= step_bound(sys_, "f32", o, x, lam), k
+            b = oracle.translate(sys_.A, "f32", b, V[k])
+            scale = np.abs(W.stored_to_f64(sys_.A, "f32")) @ np.abs(V[:k + 1]).sum(axis=0) + np.abs(sys_.b)
+            assert np.max(np.abs(b1 - b) / scale) <= TOL["f32"], k
+            x = x1
+
+
 def test_batch_solve_reaches_feasibility(P):
     """Systems of several sizes solved together, each stopping on its own:
     box-plus-sum systems (a ball of radius 100 inside, so ModAP with lambda = 1

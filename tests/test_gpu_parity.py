@@ -88,7 +88,9 @@ def test_every_kernel_shape_and_grid(P, dtype):
         for (blk, lpr, ch, rs, pd) in ALL_SHAPES[dtype]:
             if lpr * VEC[dtype] * ch < n:
                 continue
-            for grid, il in ((0, 0), (7, 0), (0, 1), (5, 1)):
+            # grids 2 and 3 give a workgroup more rows than its staged row
+            # outputs hold, so they are written out inside the row loop too
+            for grid, il in ((0, 0), (7, 0), (0, 1), (5, 1), (2, 0), (3, 1)):
                 say(f"shape dtype={dtype} block={blk} lpr={lpr} chunks={ch} rows/step={rs} depth={pd} "
                     f"interleave={il} grid={grid}")
                 s.set_tile(blk, lpr, ch, grid, rs, depth=pd, interleave=il)
@@ -211,12 +213,15 @@ def test_solve_box_sum_fp64_reaches_feasibility_like_oracle(P, seed):
     np.testing.assert_allclose(x, ores.x, rtol=0, atol=1e-9 * np.abs(ores.x).max())
 
 
+@pytest.mark.parametrize("grid", [0, 2])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_drift_schedule_steps_match_oracle(P, dtype):
+def test_drift_schedule_steps_match_oracle(P, dtype, grid):
     """Non-stationary iteration (section 5: the polytope is translated between
     iterations): after step k the system moves by V[k], fused into sweep k+1.
     Each GPU step is compared with the oracle's step from the GPU's own x_k on
-    the oracle's data b_k = b_0 + A (V[0] + ... + V[k-1])."""
+    the oracle's data b_k = b_0 + A (V[0] + ... + V[k-1]).  With two
+    workgroups each holds 350 rows, more than its staged translated b holds
+    at once, so b is also written out inside the row loop."""
     n, m = 256, 700
     sys_ = W.gaussian(n, m, seed=33, dtype=dtype)
     V = W.drift(n, 40, sigma=1e-3, seed=33)
@@ -225,10 +230,14 @@ def test_drift_schedule_steps_match_oracle(P, dtype):
     b = sys_.b.copy()
     with P.Solver() as s:
         s.set_system(sys_.A, sys_.b, dtype=dtype)
+        if grid:
+            t = s.get_tile()
+            s.set_tile(t["block"], t["lanes_per_row"], t["chunks"], grid, t["rows_per_step"], depth=t["depth"])
+            assert s.get_tile()["grid"] == grid
         s.set_drift(V)
         x = sys_.x0.copy()
         for k in range(12):
-            say(f"drift step k={k} dtype={dtype}")
+            say(f"drift step k={k} dtype={dtype} grid={grid}")
             s.iterate(1, prm)
             x1, _, st = s.query()
             o = oracle.sweep(sys_.A, dtype, b, x)
