@@ -26,7 +26,9 @@ from solves of the FP64 box-plus-sum system (n=256, m=513, 20 seeds) and of the
 default FP32 system from x0 = 0 under 10 drift sequences (at most 3000
 iterations each; a chase not ended by then counts as slower than every ended
 one); `cpu_baseline` times the CPU oracle on a
-bounded number of iterations of the same system.
+bounded number of iterations of the same system on one core, and
+`cpu_baseline_all_cores` the same oracle run by one thread per available core
+(at most 16) at once.
 """
 from __future__ import annotations
 
@@ -152,6 +154,31 @@ def cpu_baseline(sys_, V, seconds_budget):
     dt = time.perf_counter() - t0
     assert res.iters == steps
     return steps, dt
+
+
+def cpu_baseline_all_cores(sys_, V, steps, threads):
+    """The same oracle iterations run by `threads` threads at once, each on
+    its own copy of the iterate (A shared, read only).  The oracle is one C
+    call per solve, which releases the interpreter lock, so the threads run
+    in parallel: the host's aggregate sweep throughput with every core busy."""
+    import threading
+    import oracle
+    done = []
+
+    def work():
+        res = oracle.solve(sys_.A, sys_.dtype, sys_.b, sys_.x0, lam=1.0, eps=1e-300, eps_relative=False,
+                           rule=0, max_steps=steps, V=V[:steps])
+        done.append(res.iters)
+
+    ts = [threading.Thread(target=work) for _ in range(threads)]
+    t0 = time.perf_counter()
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    dt = time.perf_counter() - t0
+    assert done == [steps] * threads
+    return dt
 
 
 def main():
@@ -317,6 +344,15 @@ def main():
                                 "kind": "oracle",
                                 "sample": f"{steps} iterations (translate, sweep, step) of the full n={n} m={m} "
                                           f"{dt} system, {secs:.1f} s, single-threaded extended-precision oracle"}
+        # every core the process may use (at most 16, the host share of one GPU)
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        per = max(1, steps // 2)
+        secs_all = cpu_baseline_all_cores(sys_, V, per, threads)
+        line["cpu_baseline_all_cores"] = {
+            "value": round(bytes_per_step * per * threads / secs_all / 1e9, 4), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{threads} threads, each {per} iterations of the same system from its own copy of the "
+                      f"iterate, {secs_all:.1f} s wall"}
     print(json.dumps(line), flush=True)
 
 
