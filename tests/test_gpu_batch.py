@@ -224,6 +224,48 @@ def test_batch_autotune_keeps_results(P):
             assert np.linalg.norm(x1 - xo) <= step_bound(sys_, "f32", o, sys_.z + 0.3, lam)
 
 
+@pytest.mark.timeout(900)
+def test_full_size_batch_c4(P):
+    """The benchmark's 512-system FP32 family (15.8 GB; n ~ U{64..2048},
+    m ~ U{2n..8n}, generated on the device as the benchmark does), one
+    iteration in one launch with the autotuned tile.  The largest and the
+    smallest system and two others are checked against the oracle's step
+    from x0 = 0; every system has taken its step."""
+    import torch
+    shapes = W.batch_shapes(512, seed=0)
+    sizes = [n * m for n, m in shapes]
+    pick = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), 7, 300})
+    lam = 0.3
+    prm = P.params(lam=lam, eps=1e-9)
+    keep = {}
+    with P.Batch("f32") as B:
+        ids = []
+        for i, (n, m) in enumerate(shapes):
+            A, b, z = W.gaussian_device(n, m, seed=i, dtype="f32")
+            ids.append(B.add(A, b))
+            if i in pick:
+                keep[i] = (A.cpu().numpy(), b.cpu().numpy(), z.cpu().numpy())
+            del A, b, z
+        torch.cuda.synchronize()
+        say("c4 full-size batch: autotune and one iteration")
+        B.autotune(1)
+        st = B.iterate(1, prm)
+        assert st.running == 512
+        for i in pick:
+            A, b, z = keep[i]
+            n = A.shape[1]
+            x1, _, q = B.query(ids[i])
+            assert q.iters == 1
+            x0 = np.zeros(n)
+            o = oracle.sweep(A, "f32", b, x0)
+            xo, status = oracle.step(o.y, o.h, 0, lam, x0)
+            assert status == 0 and o.h > 0
+            sys_ = W.System(A, b, x0, "f32", z, {})
+            assert np.linalg.norm(x1 - xo) <= step_bound(sys_, "f32", o, x0, lam), (i, shapes[i])
+        for sid in ids:
+            assert B.query(sid, want_x=False)[2].iters == 1
+
+
 def test_batch_errors(P):
     with P.Batch("f32") as B:
         with pytest.raises(P.ModapError, match="E_STATE"):
