@@ -67,11 +67,14 @@ struct modap_batch {
     std::vector<int32_t> order;            // alive system ids in table order
     std::vector<BatchSys> h_sys;
     std::vector<int32_t> h_item_sys;
+    std::vector<int32_t> h_item_order;     // items by decreasing size (queue order)
     std::vector<BatchCol> h_cols;
     BatchSys *d_sys = nullptr;
     size_t sys_cap = 0;
     int32_t *d_item_sys = nullptr;
     size_t item_cap = 0;
+    int32_t *d_item_order = nullptr;
+    size_t order_cap = 0;
     BatchCol *d_cols = nullptr;
     size_t cols_cap = 0;
     void *part = nullptr;
@@ -183,6 +186,7 @@ modap_status rebuild(modap_batch *c) {
     c->order.clear();
     c->h_sys.clear();
     c->h_item_sys.clear();
+    std::vector<int64_t> item_bytes;
     c->h_cols.clear();
     int64_t items = 0, part = 0;
     double bytes = 0.0;
@@ -211,7 +215,11 @@ modap_status rebuild(modap_batch *c) {
         d.nitems = (s.m + d.rows_per_item - 1) / d.rows_per_item;
         d.part0 = part;
         const int32_t idx = (int32_t)c->h_sys.size();
-        for (int64_t q = 0; q < d.nitems; ++q) c->h_item_sys.push_back(idx);
+        for (int64_t q = 0; q < d.nitems; ++q) {
+            c->h_item_sys.push_back(idx);
+            const int64_t rows = std::min(d.rows_per_item, s.m - q * d.rows_per_item);
+            item_bytes.push_back(rows * s.ldA * (int64_t)c->es);
+        }
         for (int32_t blk = 0; blk < d.R; ++blk) c->h_cols.push_back(BatchCol{idx, blk});
         items += d.nitems;
         part += d.nitems * s.ldA;
@@ -221,6 +229,12 @@ modap_status rebuild(modap_batch *c) {
     }
     c->nitems = (int)items;
     c->bytes_per_iter = bytes;
+    // hand out the largest items first (ties in item order): the workgroups
+    // then end on small items and finish close together
+    c->h_item_order.resize((size_t)items);
+    for (int64_t q = 0; q < items; ++q) c->h_item_order[(size_t)q] = (int32_t)q;
+    std::stable_sort(c->h_item_order.begin(), c->h_item_order.end(),
+                     [&](int32_t u, int32_t v) { return item_bytes[(size_t)u] > item_bytes[(size_t)v]; });
     modap_status st;
     if ((st = ensure_buf(c, c->d_sys, c->sys_cap, std::max<size_t>(1, c->h_sys.size())))) return st;
     size_t cap = c->item_cap;
@@ -235,6 +249,7 @@ modap_status rebuild(modap_batch *c) {
             return st;
         c->item_cap = cap;
     }
+    if ((st = ensure_buf(c, c->d_item_order, c->order_cap, std::max<size_t>(1, (size_t)items)))) return st;
     if ((st = ensure_buf(c, c->d_cols, c->cols_cap, std::max<size_t>(1, c->h_cols.size())))) return st;
     const size_t pbytes = std::max<size_t>(16, (size_t)part * acc_size(c->dt));
     if (pbytes > c->part_bytes) {
@@ -247,6 +262,8 @@ modap_status rebuild(modap_batch *c) {
                                   hipMemcpyHostToDevice, c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->d_item_sys, c->h_item_sys.data(), sizeof(int32_t) * c->h_item_sys.size(),
                                   hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->d_item_order, c->h_item_order.data(),
+                                  sizeof(int32_t) * c->h_item_order.size(), hipMemcpyHostToDevice, c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->d_cols, c->h_cols.data(), sizeof(BatchCol) * c->h_cols.size(),
                                   hipMemcpyHostToDevice, c->stream));
     }
@@ -268,6 +285,7 @@ BatchArgs batch_args(modap_batch *c) {
     a.nsys = (int32_t)c->h_sys.size();
     a.nitems = c->nitems;
     a.item_sys = c->d_item_sys;
+    a.item_order = c->d_item_order;
     a.part = c->part;
     a.h_part = c->h_part;
     a.dmax_part = c->dmax_part;
@@ -442,6 +460,7 @@ void modap_batch_destroy(modap_batch *c) {
     for (BSys &s : c->sys) release_sys(s);
     free_dev(c->d_sys);
     free_dev(c->d_item_sys);
+    free_dev(c->d_item_order);
     free_dev(c->d_cols);
     free_dev(c->part);
     free_dev(c->h_part);

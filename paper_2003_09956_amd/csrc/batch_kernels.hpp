@@ -62,6 +62,7 @@ struct BatchArgs {
     int32_t nsys;
     int32_t nitems;
     const int32_t *item_sys;  // [nitems] the system of each item; a system's items are consecutive
+    const int32_t *item_order;  // [nitems] the item handed out at each queue position
     void *part;               // per-item partial y
     int64_t *h_part;          // [nitems]
     double *dmax_part;        // [nitems]
@@ -314,8 +315,10 @@ __device__ void batch_item(const BatchArgs &a, const BatchSys &Sref, int64_t k,
     }
 }
 
-// Persistent sweep over every item of the batch.  Each workgroup takes items
-// from the queue until it is exhausted (every workgroup reaches the end).
+// Persistent sweep over every item of the batch.  Each workgroup takes queue
+// positions until they are exhausted (every workgroup reaches the end); a
+// position names an item through item_order, largest items first, so that the
+// last items to start are small ones and the workgroups finish together.
 template <int DT>
 __global__ __launch_bounds__(256) void sweep_batch(const BatchArgs a) {
     using Acc = typename Store<DT>::Acc;
@@ -323,16 +326,17 @@ __global__ __launch_bounds__(256) void sweep_batch(const BatchArgs a) {
     __shared__ __attribute__((aligned(16))) Acc lds[2][kBatchCmax * 64 * VEC];
     __shared__ int64_t hsh[kBatchWaves];
     __shared__ double dsh[kBatchWaves], bsh[kBatchWaves];
-    __shared__ int s_item;
-    if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1);
+    __shared__ int s_pos;
+    if (threadIdx.x == 0) s_pos = atomicAdd(a.queue, 1);
     __syncthreads();
-    int k = s_item;
-    while (k < a.nitems) {
-        // the next item is requested while this one runs; its number reaches
+    int pos = s_pos;
+    while (pos < a.nitems) {
+        // the next position is requested while this item runs; it reaches
         // the other threads through LDS after the item's last barrier
         int next = 0;
-        __syncthreads();  // every thread has read s_item
+        __syncthreads();  // every thread has read s_pos
         if (threadIdx.x == 0) next = atomicAdd(a.queue, 1);
+        const int k = load_global(a.item_order + pos);
         const BatchSys &S = a.sys[a.item_sys[k]];
         switch (S.C) {
             case 1: batch_item<DT, 1>(a, S, k, lds, hsh, dsh, bsh); break;
@@ -340,9 +344,9 @@ __global__ __launch_bounds__(256) void sweep_batch(const BatchArgs a) {
             case 4: batch_item<DT, 4>(a, S, k, lds, hsh, dsh, bsh); break;
             default: batch_item<DT, 8>(a, S, k, lds, hsh, dsh, bsh); break;
         }
-        if (threadIdx.x == 0) s_item = next;
-        __syncthreads();  // the item's use of LDS is over, and s_item is set
-        k = s_item;
+        if (threadIdx.x == 0) s_pos = next;
+        __syncthreads();  // the item's use of LDS is over, and s_pos is set
+        pos = s_pos;
     }
 }
 
