@@ -313,10 +313,14 @@ __global__ __launch_bounds__(BLOCK) void split_axpy(const SplitArgs a) {
         load_row(bufB, wB, 1);
         int k = 0;
         for (; k + 2 <= nv; k += 2) {
+            // the scheduling barriers keep each refill right after the use of
+            // its buffer, so that one row is always in flight
             accumulate(bufA, wA);
             load_row(bufA, wA, k + 2);
+            __builtin_amdgcn_sched_barrier(0);
             accumulate(bufB, wB);
             load_row(bufB, wB, k + 3);
+            __builtin_amdgcn_sched_barrier(0);
         }
         if (k < nv) accumulate(bufA, wA);
     }
