@@ -110,7 +110,7 @@ typedef struct {
     int32_t block;          /* threads per workgroup */
     int32_t lanes_per_row;  /* threads that share one row (64 .. block) */
     int32_t chunks;         /* 16-byte vectors per thread per row (kind 0) or per column tile (kind 1) */
-    int32_t grid;           /* workgroups of the sweep (0 on input: the library's choice) */
+    int32_t grid;           /* workgroups of the sweep (0 on input: the library's choice, one per CU) */
     int32_t rows_per_step;  /* rows each row group loads per step */
     int32_t depth;          /* kind 0: steps held per row group; the next depth-1 steps' rows are
                                in flight while one is reduced (0 on input: the library's choice) */
@@ -207,8 +207,10 @@ modap_status modap_set_tile(modap_ctx *ctx, const modap_tile *tile);
 modap_status modap_get_tile(modap_ctx *ctx, modap_tile *tile);
 
 /* Autotuner: time every compiled sweep shape that covers the loaded rows, at
- * several grid sizes, with `reps` stateless sweeps each (the context's state
- * is not changed), keep the fastest and return it in *best (may be NULL).
+ * one and two workgroups per CU and at full occupancy, in both row orders,
+ * with `reps` stateless sweeps each (the context's state is not changed),
+ * and return the choice in *best (may be NULL).  The built-in shape is timed
+ * first and is kept unless another is at least 2% faster.
  * When the environment variable MODAP_TUNE_CACHE names a file, results are
  * appended to it (one line per storage type, padded row length and m) and
  * modap_set_system uses a cached shape for the same key.  Synchronises.
@@ -311,7 +313,7 @@ modap_status modap_batch_set_tile(modap_batch *batch, const modap_batch_tile *ti
 modap_status modap_batch_get_tile(modap_batch *batch, modap_batch_tile *tile);
 
 /* Autotuner of the batch: for each row-length bucket present, the item size
- * (KiB of A per work item, from 32 to 1024) and then the grid are chosen by
+ * (KiB of A per work item, from 64 to 4096) and then the grid are chosen by
  * timing `reps` stateless batch sweeps of the current systems (their state
  * is not changed); the result is kept and returned in *best (may be NULL).
  * Synchronises.  Errors: E_STATE (empty batch), E_INVAL, E_DEVICE. */
