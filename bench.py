@@ -72,9 +72,10 @@ MULTI = {
                    "eps-feasibility (distance 1e-6) from x0=0 one unit outside (the translation experiment of "
                    "section 5)",
     "serve-bf16-poisson": "Poisson arrivals of BF16 Gaussian systems (n log-uniform in [128,16384], m=4n), every "
-                          "10 ms each live system translated (|v|=1e-4) and 1% of its rows replaced, admission by "
-                          "HBM footprint, ModAP lambda=0.1, eps=1e-6*||b||inf; the same arrivals and updates served "
-                          "in FP64 one request at a time for comparison",
+                          "10 ms of wall clock each live system translated (random walk, |v|=1e-4 per tick) and 1% "
+                          "of its rows replaced (ticks elapsed during a round applied together after it), "
+                          "admission by HBM footprint, ModAP lambda=0.1, eps=1e-6*||b||inf; the same arrivals and "
+                          "updates served in FP64 one request at a time for comparison",
 }
 DT_CODE = {"f64": 0, "f32": 1, "bf16": 2}
 
@@ -195,6 +196,8 @@ def main():
     ap.add_argument("--rate", type=float, default=5.0, help="serving: Poisson arrival rate per second")
     ap.add_argument("--horizon", type=float, default=10.0, help="serving: seconds of arrivals")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving: HBM budget of the server")
+    ap.add_argument("--iters-per-round", type=int, default=64,
+                    help="serving: iterations every live request takes per round of the server")
     ap.add_argument("--n", type=int, default=32000, help="translation experiment: number of variables")
     ap.add_argument("--lam", type=float, default=1.0, help="translation experiment: ModAP step length")
     ap.add_argument("--tile", type=str, default=None,
@@ -482,7 +485,7 @@ def bench_catchup(args, P, W, torch):
     print(json.dumps(line), flush=True)
 
 
-def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap):
+def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8):
     """Drive one server over the arrivals: requests generated on the device at
     their arrival time, every 10 ms each live request translated (|v| = 1e-4)
     and 1% of its rows replaced by fresh rows that keep its moving hidden point
@@ -490,7 +493,7 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap):
     saw the request eps-feasible; requests not finished within wall_cap
     seconds are reported as censored."""
     import math
-    lam, eps, tick, vnorm, frac, ipr = 0.1, 1e-6, 0.010, 1e-4, 0.01, 8
+    lam, eps, tick, vnorm, frac = 0.1, 1e-6, 0.010, 1e-4, 0.01
     prm = P.params(lam=lam, eps=eps, max_iters=200000)
     S = P.Server(storage, budget_bytes=args.budget_gb * 1e9, prm=prm, iters_per_round=ipr)
     if max_live:
@@ -513,19 +516,25 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap):
             reqs[tk] = {"n": n, "m": m, "z": z}
             i += 1
         if now >= next_tick:
+            # every tick that has elapsed since the last update counts: k ticks
+            # are one translation by the sum of k steps (a random walk) and the
+            # replacement of k times 1% of the rows, so the systems move at the
+            # same rate per second however long a round takes
+            k = 1 + int((now - next_tick) / tick)
             live = [tk for tk in reqs if S.info(tk)["state"] == 1]
             for tk in live:
                 r = reqs[tk]
-                v = torch.randn(r["n"], generator=gen, device="cuda", dtype=torch.float64) * (vnorm / math.sqrt(r["n"]))
+                v = torch.randn(r["n"], generator=gen, device="cuda", dtype=torch.float64) * (
+                    vnorm * math.sqrt(k / r["n"]))
                 r["z"] = r["z"] + v
-                idx, rows, nb = _replace_rows_device(torch, r["n"], r["m"], max(1, math.ceil(frac * r["m"])), r["z"],
-                                                     gen, storage)
+                nrep = min(r["m"], k * max(1, math.ceil(frac * r["m"])))
+                idx, rows, nb = _replace_rows_device(torch, r["n"], r["m"], nrep, r["z"], gen, storage)
                 r["upd"] = (idx, rows, nb, v)
             torch.cuda.synchronize()
             for tk in live:
                 idx, rows, nb, v = reqs[tk].pop("upd")
                 S.update(tk, rows=idx, new_rows=rows, new_b=nb, translate=v)
-            next_tick = now + tick
+            next_tick += k * tick
         left = S.round(now)
         rounds += 1
         if now - last_log > 5.0:
@@ -552,9 +561,10 @@ def bench_serve(args, P, W, torch):
     arrivals = W.serving_arrivals(args.rate, args.horizon, seed=args.seed)
     log(f"{len(arrivals)} arrivals over {args.horizon} s at {args.rate}/s")
     cap = max(60.0, 6.0 * args.horizon)
-    served, bytes_, wall, rounds = serve_pass(args, P, W, torch, arrivals, "bf16", 0, cap)
+    ipr = args.iters_per_round
+    served, bytes_, wall, rounds = serve_pass(args, P, W, torch, arrivals, "bf16", 0, cap, ipr=ipr)
     log("served", served)
-    plain, _, _, _ = serve_pass(args, P, W, torch, arrivals, "f64", 1, cap)
+    plain, _, _, _ = serve_pass(args, P, W, torch, arrivals, "f64", 1, cap, ipr=ipr)
     log("fp64 one at a time", plain)
     value = bytes_ / wall / 1e9
     line = {
@@ -562,7 +572,7 @@ def bench_serve(args, P, W, torch):
         "ms_per_step": round(wall * 1e3 / max(rounds, 1), 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic (generated on the device, seeded)",
         "config": {"workload": MULTI["serve-bf16-poisson"], "rate_per_s": args.rate, "horizon_s": args.horizon,
-                   "budget_gb": args.budget_gb, "requests": len(arrivals)},
+                   "budget_gb": args.budget_gb, "iters_per_round": ipr, "requests": len(arrivals)},
         "pct_of_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "time_to_feasible": {"served_bf16_continuous_batching": served, "fp64_single_system_one_at_a_time": plain},
     }
