@@ -267,13 +267,10 @@ modap_status rebuild(modap_batch *c) {
         HIP_TRY(c, hipMemcpyAsync(c->d_cols, c->h_cols.data(), sizeof(BatchCol) * c->h_cols.size(),
                                   hipMemcpyHostToDevice, c->stream));
     }
-    // persistent grid: one full occupancy of the device unless tuned
-    int per_cu = 0;
-    const void *f = c->dt == 0 ? reinterpret_cast<const void *>(&sweep_batch<0>)
-                  : c->dt == 1 ? reinterpret_cast<const void *>(&sweep_batch<1>)
-                               : reinterpret_cast<const void *>(&sweep_batch<2>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
-    c->grid = c->tile.grid > 0 ? c->tile.grid : c->cu_count * per_cu;
+    // persistent grid: one workgroup per CU unless tuned.  With items of a
+    // few MiB a second workgroup per CU adds no bandwidth, and when the items
+    // are about as many as the workgroups it leaves the CUs unevenly loaded.
+    c->grid = c->tile.grid > 0 ? c->tile.grid : c->cu_count;
     c->grid = std::max(1, std::min(c->grid, std::max(1, c->nitems)));
     c->dirty = false;
     return MODAP_OK;
