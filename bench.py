@@ -108,6 +108,42 @@ def counters_path(dt: str, n: int, m: int, tile: str) -> str:
     return os.path.join(ROOT, "profiles", f"sweep_wide_{dt}_n{n}_m{m}_tile{tile.replace(',', '-')}_counters.txt")
 
 
+BATCH_SOURCES = ["paper_2003_09956_amd/csrc/batch_kernels.hpp", "paper_2003_09956_amd/csrc/batch.hip",
+                 "paper_2003_09956_amd/csrc/modap_device.hpp", "paper_2003_09956_amd/csrc/sweep_wide.hpp"]
+
+
+def batch_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in BATCH_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def batch_tile_str(tile) -> str:
+    return ",".join(str(k) for k in tile["item_kib"]) + f",{tile['grid']}"
+
+
+def batch_counters_path(tile: str) -> str:
+    """Committed rocprofv3 counter summary of the batched sweep of the
+    512-system FP32 family at one tile (item_kib for the four buckets, grid)."""
+    return os.path.join(ROOT, "profiles", f"sweep_batch_f32_512sys_tile{tile.replace(',', '-')}_counters.txt")
+
+
+def measured_batch_traffic(tile):
+    """HBM bytes per batched sweep launch from the committed counter summary
+    taken on the current batch kernel source at this tile; else None."""
+    want = batch_tile_str(tile)
+    try:
+        with open(batch_counters_path(want)) as f:
+            kv = dict(l.split(" = ", 1) for l in f.read().splitlines() if " = " in l and not l.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("source_hash") != batch_source_hash() or kv.get("tile") != want:
+        return None
+    return int(float(kv["bytes_per_launch"]))
+
+
 def measured_traffic(dt, n, m, tile):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of known size), if
@@ -203,6 +239,9 @@ def main():
     ap.add_argument("--tile", type=str, default=None,
                     help="force the sweep shape block,lanes_per_row,chunks,rows_per_step,depth,interleave,grid "
                          "(skips the autotuner)")
+    ap.add_argument("--batch-tile", type=str, default=None,
+                    help="batched workload: force item_kib for the four row-length buckets and the grid, "
+                         "k1,k2,k3,k4,grid (skips the batch autotuner)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes five times (counter calibration)")
     args = ap.parse_args()
@@ -375,8 +414,14 @@ def bench_batch(args, P, W, torch):
         bytes_per_step += m * n * 4 + 24 * m
         del A, b
     torch.cuda.synchronize()
-    tile = B.autotune(3)
-    log("batch tile (autotuned)", tile)
+    if args.batch_tile:
+        *kib, grid = (int(v) for v in args.batch_tile.split(","))
+        B.set_tile(item_kib=kib, grid=grid)
+        tile = B.get_tile()
+        log("batch tile (forced)", tile)
+    else:
+        tile = B.autotune(5)
+        log("batch tile (autotuned)", tile)
     lam, eps = 1.0, 1e-6
     n_prof = (K + PROFILE_EVERY - 1) // PROFILE_EVERY
     B.iterate(WU, P.params(lam=lam, eps=eps, track=True, profile=max(1, WU // max(n_prof, 1))))
@@ -398,7 +443,8 @@ def bench_batch(args, P, W, torch):
                    "bytes_per_step": bytes_per_step, "tile": tile},
         "pct_of_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "sweep_batch<1>",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_batch_traffic(tile),
+                     "kernel": "sweep_batch<1>",
                      "avg_us": round(sweep_us, 3), "reduce_avg_us": round(reduce_us, 3)},
     }
     print(json.dumps(line), flush=True)

@@ -481,10 +481,13 @@ class Batch:
         return x, b, out
 
     def set_tile(self, item_kib=None, grid=0):
-        if item_kib is None and grid == 0:
+        if item_kib is None:
+            # the library's built-in item sizes, with the grid asked for
             self._check(lib().modap_batch_set_tile(self._h, None))
-            return
-        kib = list(item_kib) if item_kib is not None else [256] * 4
+            if grid == 0:
+                return
+            item_kib = self.get_tile()["item_kib"]
+        kib = list(item_kib)
         t = BatchTile((C.c_int32 * 4)(*[int(v) for v in kib]), int(grid))
         self._check(lib().modap_batch_set_tile(self._h, C.byref(t)))
 

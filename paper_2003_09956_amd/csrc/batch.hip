@@ -51,6 +51,11 @@ int bucket_of(int C) { return C == 1 ? 0 : C == 2 ? 1 : C == 4 ? 2 : 3; }
 
 }  // namespace
 
+// The untuned tile, near what the autotuner finds on FP32 families with rows
+// up to 2048 elements: items of up to 0.5 / 2 / 4 / 4 MiB for the four
+// row-length buckets, one workgroup per CU.
+constexpr modap_batch_tile kBuiltinTile{{512, 2048, 4096, 4096}, 0};
+
 struct modap_batch {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -60,7 +65,7 @@ struct modap_batch {
     size_t es = 4;
     std::vector<BSys> sys;
     int64_t jn = 0;
-    modap_batch_tile tile{{512, 2048, 4096, 4096}, 0};  // near what the autotuner finds for FP32 rows up to 2048
+    modap_batch_tile tile = kBuiltinTile;
 
     // tables of the current membership (rebuilt when dirty)
     bool dirty = true;
@@ -769,7 +774,7 @@ modap_status modap_batch_query(modap_batch *c, int64_t id, double *x, double *b,
 modap_status modap_batch_set_tile(modap_batch *c, const modap_batch_tile *t) {
     if (!c) return MODAP_E_INVAL;
     if (!t) {
-        c->tile = modap_batch_tile{{512, 2048, 4096, 4096}, 0};
+        c->tile = kBuiltinTile;
     } else {
         for (int q = 0; q < 4; ++q)
             if (t->item_kib[q] < 1) return fail(c, MODAP_E_INVAL, "item_kib must be >= 1");
@@ -821,23 +826,31 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
         *ms = t[t.size() / 2];
         return MODAP_OK;
     };
-    modap_batch_tile cur = c->tile;
-    cur.grid = 0;
+    // Starting from the built-in tile, each bucket's item size and then the
+    // grid: the incumbent is timed first and a challenger must beat it by
+    // kMargin, so that near-equal choices do not flip with timing noise.
+    constexpr float kMargin = 0.98f;
+    modap_batch_tile cur = kBuiltinTile;
+    auto time_tile = [&](const modap_batch_tile &t, float *ms) -> modap_status {
+        c->tile = t;
+        c->dirty = true;
+        return time_sweeps(ms);
+    };
     // a work item costs a few microseconds beyond its rows (queue, state,
     // staging, partial): large items pay it rarely, small ones balance better
     const int sizes[] = {64, 128, 256, 512, 1024, 2048, 4096};
     for (int q = 0; q < 4; ++q) {
         if (!present[q]) continue;
-        float win = 1e30f;
+        float win = 0.f;
+        if ((st = time_tile(cur, &win))) return st;
         int pick = cur.item_kib[q];
         for (int kib : sizes) {
+            if (kib == cur.item_kib[q]) continue;
             modap_batch_tile t = cur;
             t.item_kib[q] = kib;
-            c->tile = t;
-            c->dirty = true;
             float ms = 0.f;
-            if ((st = time_sweeps(&ms))) return st;
-            if (ms < win) {
+            if ((st = time_tile(t, &ms))) return st;
+            if (ms < win * kMargin) {
                 win = ms;
                 pick = kib;
             }
@@ -847,16 +860,15 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep_fn(c->dt), 256, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    float win = 1e30f;
-    int pick = 0;
-    for (int mult = 1; mult <= per_cu; ++mult) {
+    float win = 0.f;
+    if ((st = time_tile(cur, &win))) return st;   // grid 0: one workgroup per CU
+    int pick = cur.grid;
+    for (int mult = 2; mult <= per_cu; ++mult) {
         modap_batch_tile t = cur;
         t.grid = c->cu_count * mult;
-        c->tile = t;
-        c->dirty = true;
         float ms = 0.f;
-        if ((st = time_sweeps(&ms))) return st;
-        if (ms < win) {
+        if ((st = time_tile(t, &ms))) return st;
+        if (ms < win * kMargin) {
             win = ms;
             pick = t.grid;
         }

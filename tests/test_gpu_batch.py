@@ -214,7 +214,7 @@ def test_batch_autotune_keeps_results(P):
         ids = [B.add(s.A, s.b, x0=s.z + 0.3) for s in systems]
         say("batch autotune")
         best = B.autotune(2)
-        assert best["grid"] > 0 and all(k >= 32 for k in best["item_kib"])
+        assert best["grid"] >= 0 and all(k >= 32 for k in best["item_kib"])
         assert B.get_tile() == best
         B.iterate(1, P.params(lam=lam, eps=1e-9))
         for sid, sys_ in zip(ids, systems):
