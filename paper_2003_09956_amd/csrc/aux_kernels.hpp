@@ -49,6 +49,10 @@ __global__ void check_finite(const double *p, int64_t count, int *flag) {
     }
 }
 
+// Threads of a reduction workgroup.  Measured on the FP32 n = 8192 system
+// with 256 partials: 256 threads take 5.2 us, 1024 threads 6.9 us.
+constexpr int kReduceThreads = 256;
+
 // Column sums of the workgroup partials of y, in a fixed order, in FP64.
 // Workgroup b writes its share of ||y||^2 to ynp[b]; workgroup 0 also forms
 // the totals of h, dmax and binf.  The stop test and the step are taken from
@@ -56,12 +60,13 @@ __global__ void check_finite(const double *p, int64_t count, int *flag) {
 // iteration mode it first makes the previous step permanent in x and then
 // writes the working vectors of the next sweep.
 template <typename Acc>
-__global__ __launch_bounds__(1024) void reduce_y(const ReduceArgs a) {
+__global__ __launch_bounds__(kReduceThreads) void reduce_y(const ReduceArgs a) {
     constexpr int COLS = 64;                    // columns per workgroup
     constexpr int VW = 16 / (int)sizeof(Acc);   // columns per 16-byte load
     constexpr int LPRR = COLS / VW;             // lanes per partial row
     constexpr int RPW = 64 / LPRR;              // partial rows per wavefront load
-    constexpr int RG = 16 * RPW;                // row groups per workgroup
+    constexpr int NWR = kReduceThreads / 64;    // wavefronts per workgroup
+    constexpr int RG = NWR * RPW;               // row groups per workgroup
     constexpr int U = 8;                        // loads in flight per lane
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -155,7 +160,7 @@ __global__ __launch_bounds__(1024) void reduce_y(const ReduceArgs a) {
     }
     if (blockIdx.x != 0) return;
 
-    for (int g = tid + 1024; g < a.Gs; g += 1024) {
+    for (int g = tid + kReduceThreads; g < a.Gs; g += kReduceThreads) {
         h += a.h_part[g];
         dm = max_nan(dm, a.dmax_part[g]);
         bm = max_nan(bm, a.binf_part[g]);
@@ -166,8 +171,8 @@ __global__ __launch_bounds__(1024) void reduce_y(const ReduceArgs a) {
         dm = max_nan(dm, __shfl_xor(dm, o, 64));
         bm = max_nan(bm, __shfl_xor(bm, o, 64));
     }
-    __shared__ int64_t hw[16];
-    __shared__ double dw[16], bw[16];
+    __shared__ int64_t hw[NWR];
+    __shared__ double dw[NWR], bw[NWR];
     if (lane == 0) {
         hw[wv] = h;
         dw[wv] = dm;
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(1024) void reduce_y(const ReduceArgs a) {
     __syncthreads();
     if (tid != 0) return;
     Totals t{};
-    for (int w = 0; w < 16; ++w) {
+    for (int w = 0; w < NWR; ++w) {
         t.h += hw[w];
         t.dmax = max_nan(t.dmax, dw[w]);
         t.binf = max_nan(t.binf, bw[w]);

@@ -427,13 +427,13 @@ modap_status launch_reduce(modap_ctx *c, const ReduceArgs &r, hipEvent_t e0 = nu
         void *args[] = {&copy};
         const void *f = r.acc_f64 ? reinterpret_cast<const void *>(&reduce_y<double>)
                                   : reinterpret_cast<const void *>(&reduce_y<float>);
-        HIP_TRY(c, hipExtLaunchKernel(f, dim3(reduce_grid(c)), dim3(1024), args, 0, c->stream, e0, e1, 0));
+        HIP_TRY(c, hipExtLaunchKernel(f, dim3(reduce_grid(c)), dim3(kReduceThreads), args, 0, c->stream, e0, e1, 0));
         return MODAP_OK;
     }
     if (r.acc_f64)
-        hipLaunchKernelGGL(reduce_y<double>, dim3(reduce_grid(c)), dim3(1024), 0, c->stream, r);
+        hipLaunchKernelGGL(reduce_y<double>, dim3(reduce_grid(c)), dim3(kReduceThreads), 0, c->stream, r);
     else
-        hipLaunchKernelGGL(reduce_y<float>, dim3(reduce_grid(c)), dim3(1024), 0, c->stream, r);
+        hipLaunchKernelGGL(reduce_y<float>, dim3(reduce_grid(c)), dim3(kReduceThreads), 0, c->stream, r);
     LAUNCH_TRY(c, "reduce_y launch");
     return MODAP_OK;
 }
