@@ -80,11 +80,21 @@ MULTI = {
 DT_CODE = {"f64": 0, "f32": 1, "bf16": 2}
 
 
+def _code_only(path: str) -> bytes:
+    """A C++ source without its comments and with whitespace collapsed, so that
+    the hash below changes with the code and not with its commentary."""
+    import re
+    with open(os.path.join(ROOT, path)) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split()).encode()
+
+
 def kernel_source_hash(dt: str = "f32") -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES + [f"paper_2003_09956_amd/csrc/sweep_{dt}.hip"]:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        h.update(_code_only(p))
     return h.hexdigest()[:16]
 
 
@@ -115,8 +125,7 @@ BATCH_SOURCES = ["paper_2003_09956_amd/csrc/batch_kernels.hpp", "paper_2003_0995
 def batch_source_hash() -> str:
     h = hashlib.sha256()
     for p in BATCH_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        h.update(_code_only(p))
     return h.hexdigest()[:16]
 
 

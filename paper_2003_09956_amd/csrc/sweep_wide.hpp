@@ -23,9 +23,10 @@
 // workgroups do not all read the same part of the working vectors at once.
 // The lane's slices of x, v and of the partial y stay in registers for the
 // whole sweep; the next PD-1 steps' rows are loaded (non-temporally: A is read
-// once per sweep) while the current ones are reduced.  Dot products are reduced across the wavefront with a
-// butterfly (the same value in every lane) and across the wavefronts of a row
-// group through LDS, in a fixed order, so results do not depend on timing.
+// once per sweep) while the current ones are reduced.  Dot products are
+// reduced across the wavefront by DPP moves and lane reads (the same value in
+// every lane) and across the wavefronts of a row group through LDS, in a fixed
+// order, so results do not depend on timing.
 // Each workgroup owns a fixed set of rows (a contiguous band, or row blocks
 // taken in turn with the other workgroups) and writes one partial y; the
 // reduction kernel sums the partials in a fixed order.

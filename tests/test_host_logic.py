@@ -105,3 +105,14 @@ def test_drift_is_seeded_gaussian():
     V = W.drift(1000, 50, sigma=1e-2, seed=7)
     assert V.shape == (50, 1000) and np.array_equal(V, W.drift(1000, 50, sigma=1e-2, seed=7))
     assert abs(V.std() / 1e-2 - 1.0) < 0.02 and abs(V.mean()) < 1e-3
+
+
+def test_counter_hash_follows_code_not_comments(tmp_path, monkeypatch):
+    a = "// first\nint f(int x) { return x + 1; }  /* block\n comment */\n"
+    b = "// another comment\nint f(int x)   {\n  return x + 1;   // the same code\n}\n"
+    c = "int f(int x) { return x + 2; }\n"
+    for name, text in (("a.hpp", a), ("b.hpp", b), ("c.hpp", c)):
+        (tmp_path / name).write_text(text)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench._code_only("a.hpp") == bench._code_only("b.hpp")
+    assert bench._code_only("a.hpp") != bench._code_only("c.hpp")
