@@ -121,13 +121,13 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
     const int64_t row_bytes = a.ldA * (int64_t)sizeof(T);
 
     auto row_of = [&](int64_t t, int q) -> int64_t { return r0 + t * a.step_stride + grp * RS + q; };
-    // Loads are issued unconditionally (addresses clamped into the row band and
-    // the padded row) so that no branch separates them; rows past the band
-    // and columns past the padded row are discarded afterwards.  A step past
-    // the last one (the ring's look-ahead at the end of the band) reads row 0,
-    // which every workgroup shares from L2, instead of a row of its own:
-    // every pass of the row loop then issues the same loads, which lets the
-    // compiler count exactly which of them a row still waits for.
+    // Loads are issued unconditionally so that no branch separates them: a row
+    // index past the band is clamped to the band's last row, and the results
+    // of rows past the band are never used.  A step past the last one (the
+    // ring's look-ahead at the end of the band) reads row 0, which every
+    // workgroup shares from L2, instead of a row of its own: every pass of the
+    // row loop then issues the same loads, which lets the compiler count
+    // exactly which of them a row still waits for.
     //
     // Each row is read through a buffer resource whose range is the padded
     // row: the chunks of a lane that lie past it read as zeros, which is what
