@@ -12,7 +12,11 @@ y/||y||):
   b = A z + U(0,1); drift v ~ N(0, 1e-2^2)^n per iteration; x0 = 0; lambda = 1;
   eps = 1e-6 * ||b||_inf.
   --workload bf16-16384x65536: the same construction at n = 16384, m = 65536
-  with A stored BF16 (2 GiB), drift |v| = 1e-4 per iteration.
+  with A stored BF16 (2 GiB), drift |v| = 1e-4 per iteration; it also chases
+  the system from x0 = 0 at drift norms 1e-5, 1e-4 and 1e-3 per iteration,
+  with the BF16 rows and with the FP64 rows they were rounded from, and
+  reports both forms' time-to-feasible and the violation of the BF16 results
+  on the FP64 system.
 
 The timed loop runs in tracking mode (an eps-feasible check takes no step but
 the system keeps moving), so every timed step reads all of A.
@@ -47,6 +51,10 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_EVERY = 10      # one iteration in ten carries HIP events on its kernel dispatches
 DRIFT_SEEDS = 10        # drift sequences of the time-to-feasible chase on the default system
 DRIFT_STEPS = 3000      # iterations allowed per chase
+DRIFT_SPEEDS = (1e-5, 1e-4, 1e-3)   # drift norms |v| per iteration swept on the BF16 system
+SPEED_STEPS = 8000      # iterations allowed per chase of the BF16 system and of its FP64 original
+SPEED_SEEDS = 3         # drift sequences per speed
+SPEED_LAMBDA = 0.1      # ModAP step length of those chases
 METRIC = "pseudo-projection sweep HBM GB/s (% of peak); p50/p99 time-to-feasible"
 KERNEL_SOURCES = ["paper_2003_09956_amd/csrc/sweep_wide.hpp", "paper_2003_09956_amd/csrc/modap_device.hpp",
                   "paper_2003_09956_amd/csrc/sweep_inst.inc"]
@@ -182,6 +190,68 @@ def time_to_feasible(P, W, seeds):
             out.append(st.seconds * 1e3)
             iters.append(st.iters)
     return out, iters
+
+
+def drift_speed_sweep(P, W, torch, sys16, seed):
+    """The BF16-stored system chased from x0 = 0 under a drift of norm |v| =
+    1e-5, 1e-4 and 1e-3 per iteration, and the FP64 system its rows were
+    rounded from chased under the same drift sequences: time-to-feasible of
+    both forms on the same GPU, and the violation that each BF16 result leaves
+    on the FP64 system (the error of the storage precision in the final point;
+    the FP64 path itself matches the oracle to 1e-12 per sweep).  ModAP with
+    lambda = 0.1, the step length that reaches eps on these systems in the
+    fewest iterations."""
+    import numpy as np
+    n, m = sys16.n, sys16.m
+    log("generating the FP64 system the BF16 rows were rounded from ...")
+    s64 = W.gaussian(n, m, sys16.meta["seed"], "f64")
+    dev = torch.device("cuda")
+    A64, b64 = torch.from_numpy(s64.A).to(dev), torch.from_numpy(s64.b).to(dev)
+    del s64
+    A16 = torch.from_numpy(sys16.A.view(np.int16)).to(dev)
+    b16 = torch.from_numpy(sys16.b).to(dev)
+    prm = P.params(lam=SPEED_LAMBDA, eps=1e-6, max_iters=SPEED_STEPS)
+    fin = lambda v: round(v, 3) if math.isfinite(v) else None
+    out = []
+    with P.Solver(0) as q16, P.Solver(0) as q64:
+        for k, speed in enumerate(DRIFT_SPEEDS):
+            runs = {"bf16": [], "f64": []}
+            viol, vrows, eps_abs = 0.0, 0, 0.0
+            for sd in range(SPEED_SEEDS):
+                g = torch.Generator(device="cuda")
+                g.manual_seed(seed * 1000 + k * 10 + sd)
+                V = torch.randn((SPEED_STEPS, n), generator=g, device=dev, dtype=torch.float64)
+                V *= speed / math.sqrt(n)
+                for name, q, A, b in (("bf16", q16, A16, b16), ("f64", q64, A64, b64)):
+                    q.set_system(A, b, dtype=name)
+                    q.set_drift(V)
+                    st, code = q.solve(prm, raise_on_stop=False)
+                    runs[name].append((code == 0, st.seconds * 1e3, int(st.iters), st.seconds * 1e3 / max(st.sweeps, 1)))
+                    log("drift", speed, sd, name, code, runs[name][-1])
+                    if name == "bf16":
+                        eps_abs = max(eps_abs, st.eps_abs)
+                # the BF16 result on the FP64 data as they stand at its final
+                # check (the translations of the steps it took)
+                x16, _, _ = q16.query()
+                steps = runs["bf16"][-1][2]
+                q64.set_system(A64, b64, dtype="f64")
+                if steps:
+                    q64.update_coeffs(translate=V[:steps].sum(dim=0).contiguous())
+                ev = q64.eval_sweep(torch.from_numpy(x16).to(dev), want_r=False)
+                viol, vrows = max(viol, float(ev.max_viol)), max(vrows, int(ev.h))
+                del V
+            row = {"v_norm": speed, "seeds": SPEED_SEEDS, "max_steps": SPEED_STEPS}
+            for name, rr in runs.items():
+                ms = [r[1] if r[0] else math.inf for r in rr]
+                row[name] = {"caught": sum(r[0] for r in rr),
+                             "p50_ms": fin(float(np.percentile(ms, 50, method="higher"))),
+                             "steps": [r[2] for r in rr],
+                             "ms_per_step": round(float(np.mean([r[3] for r in rr])), 4)}
+            row["bf16_result_on_fp64_system"] = {"max_viol": viol, "violated_rows": vrows, "eps_abs": eps_abs}
+            p16, p64 = row["bf16"]["p50_ms"], row["f64"]["p50_ms"]
+            row["p50_speedup_bf16_over_f64"] = round(p64 / p16, 2) if p16 and p64 else None
+            out.append(row)
+    return out
 
 
 def cpu_baseline(sys_, V, seconds_budget):
@@ -389,6 +459,8 @@ def main():
         }
         if ttf_drift is not None:
             line["time_to_feasible"]["gaussian_f32_n8192_m16384_drift"] = ttf_drift
+        if dt == "bf16":
+            line["drift_speeds"] = drift_speed_sweep(P, W, torch, sys_, args.seed)
     if not args.no_cpu_baseline:
         steps, secs = cpu_baseline(sys_, V, args.cpu_seconds)
         line["cpu_baseline"] = {"value": round(bytes_per_step * steps / secs / 1e9, 4), "unit": "GB/s", "cores": 1,

@@ -141,7 +141,9 @@ modap_status modap_set_system(modap_ctx *ctx, int64_t m, int64_t n, modap_dtype 
                               int ptrs_on_device);
 
 /* Replace the current approximation by x ([n], NULL = zero) and reset the
- * iteration counters (checkpoint resume).  Errors: E_STATE, E_INVAL. */
+ * iteration counters (checkpoint resume).  A host x must be finite (E_INVAL);
+ * a device x is copied without inspection, and a non-finite entry in it stops
+ * the next iterate or solve with E_NUMERIC.  Errors: E_STATE, E_INVAL. */
 modap_status modap_set_x(modap_ctx *ctx, const double *x, int ptrs_on_device);
 
 /* Update the data between iterations (Step 6 of ModAP on lists, Step 9 of

@@ -442,6 +442,27 @@ def test_error_paths(P):
             s.set_tile(256, 64, 3)                      # no such compiled shape
 
 
+def test_numeric_stop(P):
+    """E_NUMERIC: a non-finite value reaching the check (eq. 10) or the step
+    length (eq. 12) stops the solve instead of stepping with it."""
+    import torch
+    with P.Solver() as s:
+        say("numeric stop")
+        # a device x is taken as is; a NaN in it reaches the residuals
+        s.set_system(np.eye(2), np.zeros(2), dtype="f64")
+        s.set_x(torch.tensor([np.nan, 0.0], dtype=torch.float64, device="cuda:0"))
+        st, code = s.solve(P.params(), raise_on_stop=False)
+        assert code == 8 and st.iters == 0 and st.state == 3
+        # finite data whose y overflows: y = (1e300, 1e300), ||y|| = inf
+        s.set_system(np.array([[1.0, 1.0]]), np.zeros(1), x0=np.array([1e300, 1e300]), dtype="f64")
+        st, code = s.solve(P.params(), raise_on_stop=False)
+        assert code == 8 and st.iters == 0 and st.state == 3
+        # the context stays usable: a finite restart solves
+        s.set_x(np.array([1.0, 1.0]))
+        st, code = s.solve(P.params(), raise_on_stop=False)
+        assert code == 0 and st.state == 1
+
+
 def test_device_pointers_and_profile(P):
     """The same calls with torch device tensors (ptrs_on_device = 1), and the
     per-kernel HIP-event timing used by the benchmark."""
