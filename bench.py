@@ -55,6 +55,7 @@ DRIFT_SPEEDS = (1e-5, 1e-4, 1e-3)   # drift norms |v| per iteration swept on the
 SPEED_STEPS = 8000      # iterations allowed per chase of the BF16 system and of its FP64 original
 SPEED_SEEDS = 3         # drift sequences per speed
 SPEED_LAMBDA = 0.1      # ModAP step length of those chases
+BATCH_TTF_STEPS = 4000  # iterations allowed per system in the chase of the batched family
 METRIC = "pseudo-projection sweep HBM GB/s (% of peak); p50/p99 time-to-feasible"
 KERNEL_SOURCES = ["paper_2003_09956_amd/csrc/sweep_wide.hpp", "paper_2003_09956_amd/csrc/modap_device.hpp",
                   "paper_2003_09956_amd/csrc/sweep_inst.inc"]
@@ -514,6 +515,7 @@ def bench_batch(args, P, W, torch):
     sweep_us = st.sweep_ms * 1e3 / st.profiled
     reduce_us = st.reduce_ms * 1e3 / st.profiled
     B.close()
+    del B
     value = bytes_per_step * K / wall / 1e9
     achieved = bytes_per_step / (sweep_us * 1e-6) / 1e9
     line = {
@@ -528,7 +530,63 @@ def bench_batch(args, P, W, torch):
                      "kernel": "sweep_batch<1>",
                      "avg_us": round(sweep_us, 3), "reduce_avg_us": round(reduce_us, 3)},
     }
+    if not args.no_ttf:
+        line["time_to_feasible"] = batch_time_to_feasible(args, P, W, torch, shapes, tile)
     print(json.dumps(line), flush=True)
+
+
+def batch_time_to_feasible(args, P, W, torch, shapes, tile):
+    """All systems of the batched family chased from x0 = 0 to eps-feasibility
+    under drifts of their own (N(0, 1e-3^2) per coordinate per iteration),
+    ModAP with lambda = 0.1: advanced together by the batch, and -- the plain
+    single-system form -- the FP64 rows they were rounded from solved one
+    system at a time under the same drifts."""
+    import numpy as np
+    prm = P.params(lam=SPEED_LAMBDA, eps=1e-6, max_iters=BATCH_TTF_STEPS)
+
+    def drift_of(i, n):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(args.seed * 7919 + i)
+        return torch.randn((BATCH_TTF_STEPS, n), generator=g, device="cuda", dtype=torch.float64) * 1e-3
+
+    seed_of = lambda i: args.seed * 100003 + i
+    B = P.Batch("f32")
+    ids = []
+    for i, (n, m) in enumerate(shapes):
+        A, b, _ = W.gaussian_device(n, m, seed=seed_of(i), dtype="f32")
+        ids.append(B.add(A, b))
+        B.set_drift(ids[-1], drift_of(i, n))
+        del A, b
+    B.set_tile(item_kib=tile["item_kib"], grid=tile["grid"])
+    torch.cuda.synchronize()
+    bst = B.solve(prm)
+    steps = [int(B.query(sid, want_x=False)[2].iters) for sid in ids]
+    caught = sum(int(B.query(sid, want_x=False)[2].state == 1) for sid in ids)
+    B.close()
+    del B
+    log(f"batch chase: {caught} of {len(ids)} caught in {bst.seconds:.2f} s")
+    # the FP64 single-system form, one system after another
+    done, secs, steps64 = 0, [], []
+    with P.Solver(0) as s:
+        for i, (n, m) in enumerate(shapes):
+            A, b, _ = W.gaussian_device(n, m, seed=seed_of(i), dtype="f64")
+            s.set_system(A, b, dtype="f64")
+            s.set_drift(drift_of(i, n))
+            st, code = s.solve(prm, raise_on_stop=False)
+            done += code == 0
+            secs.append(st.seconds)
+            steps64.append(int(st.iters))
+            del A, b
+    finish = np.cumsum(secs)
+    log(f"FP64 one at a time: {done} of {len(shapes)} caught in {finish[-1]:.2f} s")
+    pct = lambda v, q: float(np.percentile(np.asarray(v, dtype=float), q))
+    return {"systems": len(shapes), "lambda": SPEED_LAMBDA, "max_steps": BATCH_TTF_STEPS,
+            "batched_f32": {"caught": caught, "all_done_s": round(bst.seconds, 3),
+                            "steps_p50": pct(steps, 50), "steps_p99": pct(steps, 99)},
+            "f64_one_at_a_time": {"caught": done, "all_done_s": round(float(finish[-1]), 3),
+                                  "p50_done_s": round(pct(finish, 50), 3),
+                                  "steps_p50": pct(steps64, 50), "steps_p99": pct(steps64, 99)},
+            "speedup_all_done": round(float(finish[-1]) / bst.seconds, 2)}
 
 
 def _replace_rows_device(torch, n, m, k, z, gen, dtype):
