@@ -625,6 +625,24 @@ def catchup_trial(P, s, A, b, n, rate, lam, limit_s, chunk=4):
         last = now
 
 
+def paper_catchup_context(n):
+    """The paper's highest caught translation rates at this n (section 5),
+    with the hardware they were measured on: context, not a target."""
+    runs = []
+    with open(os.path.join(ROOT, "tests", "golden", "paper_catchup_rates.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            nn, nodes, r, total, _ = line.split()
+            if int(nn) == n:
+                runs.append({"nodes": int(nodes), "per_coord": int(r), "total": int(total)})
+    if not runs:
+        return None
+    return {"hardware": "cluster nodes of 2x Intel Xeon X5680 (6 cores, 3.33 GHz), 24 GB DDR3, "
+                        "InfiniBand QDR (section 5, Table 1)",
+            "lambda": "not stated", "eps": 1e-7, "runs": runs}
+
+
 def bench_catchup(args, P, W, torch):
     """Highest translation rate at which the iteration catches the moving
     polytope, found by bisection on measured runs."""
@@ -666,6 +684,7 @@ def bench_catchup(args, P, W, torch):
         "max_caught_rate": {"per_coord": round(lo, 4), "total": round(lo * math.sqrt(n), 2),
                             "first_missed_per_coord": round(hi, 4) if hi is not None else None,
                             "model_lambda_over_sqrt_n_t_iter": round(r_est, 4), "trials": trials},
+        "paper_context": paper_catchup_context(n),
     }
     print(json.dumps(line), flush=True)
 

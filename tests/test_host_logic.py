@@ -116,3 +116,11 @@ def test_counter_hash_follows_code_not_comments(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench._code_only("a.hpp") == bench._code_only("b.hpp")
     assert bench._code_only("a.hpp") != bench._code_only("c.hpp")
+
+
+def test_catchup_line_quotes_the_papers_rates_as_context():
+    ctx = bench.paper_catchup_context(32000)
+    assert [(r["nodes"], r["per_coord"], r["total"]) for r in ctx["runs"]] == [(50, 10, 1789), (75, 15, 2683),
+                                                                               (100, 18, 3220)]
+    assert [r["nodes"] for r in bench.paper_catchup_context(54000)["runs"]] == [75, 100, 150]
+    assert bench.paper_catchup_context(1000) is None          # no printed run at this size
