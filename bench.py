@@ -260,15 +260,22 @@ def cpu_baseline(sys_, V, seconds_budget):
     sweep + step, single thread, bounded to about `seconds_budget` seconds."""
     import oracle
     oracle.build(force=False)
-    t0 = time.perf_counter()
-    oracle.solve(sys_.A, sys_.dtype, sys_.b, sys_.x0, lam=1.0, eps=1e-300, eps_relative=False,
-                 rule=0, max_steps=1, V=V[:1])
-    one = time.perf_counter() - t0
-    steps = max(1, int(seconds_budget / max(one, 1e-3)))
-    t0 = time.perf_counter()
-    res = oracle.solve(sys_.A, sys_.dtype, sys_.b, sys_.x0, lam=1.0, eps=1e-300, eps_relative=False,
-                       rule=0, max_steps=steps, V=V[:steps])
-    dt = time.perf_counter() - t0
+
+    def run(k):
+        t0 = time.perf_counter()
+        res = oracle.solve(sys_.A, sys_.dtype, sys_.b, sys_.x0, lam=1.0, eps=1e-300, eps_relative=False,
+                           rule=0, max_steps=k, V=V[:k])
+        return time.perf_counter() - t0, res
+
+    # size the sample: a call costs a fixed part (the row norms) plus one
+    # part per iteration; the first call also touches A for the first time
+    run(1)
+    t1, _ = run(1)
+    t3, _ = run(3)
+    per = max((t3 - t1) / 2, 1e-4)
+    fixed = max(t1 - per, 0.0)
+    steps = max(1, min(len(V), round((seconds_budget - fixed) / per)))
+    dt, res = run(steps)
     assert res.iters == steps
     return steps, dt
 

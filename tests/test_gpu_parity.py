@@ -403,6 +403,30 @@ def test_feasible_start_is_a_fixed_point(P):
     assert np.array_equal(x, sys_.z)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_zero_iterations(P, dtype):
+    """k = 0 queues nothing and leaves x alone; a solve with max_iters = 0
+    still checks x0 (eq. 10) and stops there, with the oracle's violation."""
+    sys_ = W.gaussian(300, 700, seed=9, dtype=dtype)
+    o = oracle.sweep(sys_.A, dtype, sys_.b, sys_.x0)
+    assert o.h > 0
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype=dtype)
+        say("zero iterations", dtype)
+        st = s.iterate(0, P.params())
+        assert st.iters == 0 and st.sweeps == 0
+        st, code = s.solve(P.params(max_iters=0), raise_on_stop=False)
+        assert code == 6 and st.iters == 0 and st.sweeps == 1 and st.state == 4
+        scale = float(np.max(o.t / np.sqrt(o.nu)))
+        assert abs(st.max_viol - o.dmax) <= TOL[dtype] * scale and st.h == o.h
+        x, _, _ = s.query()
+        assert np.array_equal(x, sys_.x0)
+        # from the hidden (feasible) point, the same call reports success
+        s.set_x(sys_.z)
+        st, code = s.solve(P.params(max_iters=0), raise_on_stop=False)
+        assert code == 0 and st.iters == 0 and st.state == 1
+
+
 def test_error_paths(P):
     with P.Solver() as s:
         say("errors")
