@@ -98,6 +98,38 @@ def test_batch_alone_equals_in_mix(P):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+def test_batch_membership_changes_between_iterations(P):
+    """Systems leave and join a batch between iterations (as the server
+    does): the systems that stay, and the one that joins, take the same bits
+    as in batches that never held the others."""
+    keep = [W.gaussian(n, m, seed=n + 1, dtype="f32") for (n, m) in [(300, 800), (1500, 3100)]]
+    gone = W.gaussian(2048, 6000, seed=8, dtype="f32")
+    late = W.gaussian(640, 1700, seed=6, dtype="f32")
+    prm = P.params(lam=0.4, eps=1e-9)
+    with P.Batch("f32") as B:
+        say("membership: mixed batch")
+        ids = [B.add(s.A, s.b, x0=s.z + 0.4) for s in keep]
+        gid = B.add(gone.A, gone.b, x0=gone.z + 0.4)
+        B.iterate(6, prm)
+        B.remove(gid)
+        lid = B.add(late.A, late.b, x0=late.z + 0.4)
+        B.iterate(5, prm)
+        mixed = [B.query(i)[0] for i in ids] + [B.query(lid)[0]]
+        assert [B.query(i)[2].iters for i in ids] == [11, 11] and B.query(lid)[2].iters == 5
+    with P.Batch("f32") as B:
+        say("membership: reference batches")
+        ids = [B.add(s.A, s.b, x0=s.z + 0.4) for s in keep]
+        B.iterate(6, prm)                   # the same call boundaries as above
+        B.iterate(5, prm)
+        ref = [B.query(i)[0] for i in ids]
+    with P.Batch("f32") as B:
+        lid = B.add(late.A, late.b, x0=late.z + 0.4)
+        B.iterate(5, prm)
+        ref.append(B.query(lid)[0])
+    for a, b in zip(mixed, ref):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_batch_queued_equals_single_calls(P, dtype):
     """The in-sweep decision of queued iterations against one iteration per

@@ -322,20 +322,68 @@ def test_full_size_fp32_sweep_c2(P):
     assert fejer_gap(sys_.A, "f32", x, sys_.z + v, g.y, g.r) >= -1e-6 * np.abs(g.y).sum()
 
 
+# The one-pass shapes that cover an 8192-element FP32 row (block, lanes per
+# row, chunks, rows per step, depth): the shapes the autotuner chooses from
+# for the benchmark's system.
+C2_SHAPES = [(256, 256, 8, 1, 2), (512, 512, 4, 1, 2), (512, 512, 8, 1, 2), (512, 512, 4, 2, 2),
+             (1024, 1024, 2, 1, 2), (512, 256, 8, 1, 2), (512, 512, 4, 1, 3), (512, 512, 4, 1, 4),
+             (1024, 1024, 2, 1, 3)]
+
+
+def test_full_size_c2_every_tunable_shape(P):
+    """The benchmark's system under every launch shape the autotuner can pick
+    for it (one workgroup per CU, both row orders; two per CU for the
+    built-in shape), each sweep against the oracle element by element, with
+    a translation pending as in the timed iterations."""
+    sys_ = W.c2(0)
+    rng = np.random.default_rng(4)
+    x = rng.normal(scale=0.05, size=sys_.n)
+    v = rng.normal(scale=1e-2, size=sys_.n)
+    o = oracle.sweep(sys_.A, "f32", oracle.translate(sys_.A, "f32", sys_.b, v), x)
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype="f32")
+        s.update_coeffs(translate=v)
+        cases = [(shape, il, 0) for shape in C2_SHAPES for il in (0, 1)] + [(C2_SHAPES[0], 0, 512)]
+        for (blk, lpr, ch, rs, pd), il, grid in cases:
+            say(f"c2 shape {blk}/{lpr}/{ch}/{rs}/{pd} interleave={il} grid={grid}")
+            s.set_tile(blk, lpr, ch, grid, rs, depth=pd, interleave=il)
+            g = s.eval_sweep(x)
+            check_sweep(sys_.A, "f32", o, g.y, g.h, g.max_viol, g.r, label=f"c2 {blk}/{lpr}/{ch}/{rs}/{pd}/{il}/{grid}")
+
+
 @pytest.mark.timeout(900)
 def test_full_size_bf16_sweep_c3(P):
     """n=16384, m=65536 BF16 storage (2 GiB): full parity of one sweep against
-    the oracle on the same stored bytes, and against the FP64 system the BF16
-    rows were rounded from (quantisation, 5e-3)."""
+    the oracle on the same stored bytes, under the built-in launch shape and
+    every shape the autotuner can pick for this system; then the same sweep
+    against the FP64 system the BF16 rows were rounded from (quantisation,
+    5e-3)."""
     sys_ = W.c3(0)
     x = np.random.default_rng(1).normal(scale=0.03, size=sys_.n)
     say("c3 full-size sweep")
+    o = oracle.sweep(sys_.A, "bf16", sys_.b, x)
     with P.Solver() as s:
         s.set_system(sys_.A, sys_.b, dtype="bf16")
         g = s.eval_sweep(x)
-    o = oracle.sweep(sys_.A, "bf16", sys_.b, x)
-    err = check_sweep(sys_.A, "bf16", o, g.y, g.h, g.max_viol, g.r, label="c3")
-    say("  c3 errors", err)
+        err = check_sweep(sys_.A, "bf16", o, g.y, g.h, g.max_viol, g.r, label="c3")
+        say("  c3 errors", err, s.get_tile())
+        for depth in (2, 3):
+            for il in (0, 1):
+                say(f"c3 shape 512/512/4/1/{depth} interleave={il}")
+                s.set_tile(512, 512, 4, 0, 1, depth=depth, interleave=il)
+                g2 = s.eval_sweep(x)
+                check_sweep(sys_.A, "bf16", o, g2.y, g2.h, g2.max_viol, g2.r, label=f"c3 512/512/4/1/{depth}/{il}")
+        del o
+        # the FP64 rows of the same draw (the generator stream does not depend
+        # on the storage type), with their own b on both sides
+        s64 = W.gaussian(sys_.n, sys_.m, 0, "f64")
+        assert np.array_equal(W.encode(s64.A[:64], "bf16"), sys_.A[:64])
+        say("c3 against the FP64 original")
+        s.set_system(sys_.A, s64.b, dtype="bf16")
+        g3 = s.eval_sweep(x)
+    o64 = oracle.sweep(s64.A, "f64", s64.b, x)
+    err = check_sweep(s64.A, "f64", o64, g3.y, g3.h, g3.max_viol, g3.r, tol=TOL_BF16_VS_F64, label="c3 bf16-vs-f64")
+    say("  c3 quantisation error", err)
 
 
 def test_bf16_quantisation_against_fp64_original(P):
