@@ -252,7 +252,7 @@ typedef struct {
 /* Batch tuning: target bytes of A per work item for each row-length bucket
  * (rows of at most 64*VEC*C elements, C = 1, 2, 4, 8, VEC = 16 bytes / element
  * size), and the persistent grid (0 = one workgroup per CU).  A
- * system smaller than 16 items of that size is cut into 16 items of at least
+ * system smaller than 8 items of that size is cut into 8 items of at least
  * 32 KiB instead; the cut of a system never depends on the other systems. */
 typedef struct {
     int32_t item_kib[4];    /* largest KiB of A per work item, buckets C = 1, 2, 4, 8 (>= 1) */

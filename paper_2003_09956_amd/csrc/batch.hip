@@ -173,8 +173,10 @@ modap_status ensure_buf(modap_batch *c, P *&p, size_t &cap, size_t count) {
 // system is still cut into kMinItems items of at least kMinItemKib KiB, so
 // that a batch of few systems spreads over the device; a multiple of the
 // wavefronts of a workgroup.  The partition depends on the system and the
-// tile only, never on the other systems of the batch.
-constexpr int64_t kMinItems = 16;
+// tile only, never on the other systems of the batch.  Eight items per system
+// rather than sixteen: on a batch of many systems every item costs a few
+// microseconds of its own, and four to eight measured best.
+constexpr int64_t kMinItems = 8;
 constexpr int64_t kMinItemKib = 32;
 int64_t rows_per_item(const modap_batch *c, const BSys &s) {
     const int64_t sys_kib = s.m * s.ldA * (int64_t)c->es / 1024;
