@@ -19,7 +19,8 @@ y/||y||):
   on the FP64 system.
 
 The timed loop runs in tracking mode (an eps-feasible check takes no step but
-the system keeps moving), so every timed step reads all of A.
+the system keeps moving), so every timed step reads all of A.  The sweep runs
+in the library's built-in launch shape unless --autotune or --tile is given.
 
 Printed JSON line: `value` is the whole-job algorithmic HBM throughput of the
 timed steps, m*n*sizeof(A) + 24*m bytes per step (A, b read and written,
@@ -324,8 +325,10 @@ def main():
     ap.add_argument("--n", type=int, default=32000, help="translation experiment: number of variables")
     ap.add_argument("--lam", type=float, default=1.0, help="translation experiment: ModAP step length")
     ap.add_argument("--tile", type=str, default=None,
-                    help="force the sweep shape block,lanes_per_row,chunks,rows_per_step,depth,interleave,grid "
-                         "(skips the autotuner)")
+                    help="force the sweep shape block,lanes_per_row,chunks,rows_per_step,depth,interleave,grid")
+    ap.add_argument("--autotune", action="store_true",
+                    help="single-system workloads: run the sweep autotuner before timing (default: the library's "
+                         "built-in shape, so that a kernel trace of the same command names the same kernel)")
     ap.add_argument("--batch-tile", type=str, default=None,
                     help="batched workload: force item_kib for the four row-length buckets and the grid, "
                          "k1,k2,k3,k4,grid (skips the batch autotuner)")
@@ -386,9 +389,12 @@ def main():
             s.set_tile(blk, lpr, ch, grid, rs, depth=depth, interleave=il)
             tile = s.get_tile()
             log("tile (forced)", tile)
-        else:
+        elif args.autotune:
             tile = s.autotune(5)
             log("tile (autotuned)", tile)
+        else:
+            tile = s.get_tile()
+            log("tile (built-in)", tile)
         # the warm-up also profiles, as many iterations as the timed region
         # will, so that the profiling events exist before the clock starts
         n_prof = (K + PROFILE_EVERY - 1) // PROFILE_EVERY
