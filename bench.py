@@ -673,6 +673,8 @@ def bench_catchup(args, P, W, torch):
         st = s.iterate(20, P.params(lam=lam, eps=1e-6, eps_relative=False, max_iters=10 ** 9, profile=1,
                                     track=True))
         t_iter = (st.sweep_ms + st.reduce_ms) / st.profiled / 1e3
+        t_sweep = st.sweep_ms / st.profiled / 1e3
+        h_rest = int(st.h)
         r_est = lam / (math.sqrt(n) * t_iter)
         lo, hi = 0.0, None
         r = 0.5 * r_est
@@ -701,6 +703,19 @@ def bench_catchup(args, P, W, torch):
             "model_lambda_over_sqrt_n_t_iter": round(r_est, 4), "trials": trials},
         "paper_context": paper_catchup_context(n),
     }
+    # The sweep of these long rows is the split-row form (all its kernels
+    # between the same two events): algorithmic bytes are one pass over A; it
+    # moves (1 + h/m) A, re-reading the violated rows.
+    m = 2 * n + 1
+    alg = bytes_per_iter / t_sweep / 1e9
+    line["roofline"] = {"bound": "hbm", "achieved": round(alg, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(alg / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": f"sweep_split (tile {tile['block']},{tile['lanes_per_row']},{tile['chunks']})"
+                        if tile["kind"] == 1 else "sweep_wide",
+                        "avg_us": round(t_sweep * 1e6, 3),
+                        "moved_bytes_model": int(m * n * 8 * (1 + h_rest / m)) if tile["kind"] == 1 else None,
+                        "moved_GBs": round(m * n * 8 * (1 + h_rest / m) / t_sweep / 1e9, 2)
+                        if tile["kind"] == 1 else None}
     print(json.dumps(line), flush=True)
 
 
