@@ -91,22 +91,28 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_y(const ReduceArgs a) {
     issue(rg);
     const bool colw = a.work && tid < COLS && col < a.n;
     double xo = 0.0, yo = 0.0;
+    int64_t slen = 0;
     if (colw) {
-        xo = a.x[col];
-        yo = a.y[col];
+        xo = load_global(a.x + col);
+        yo = load_global(a.y + col);
+        if (a.V) slen = load_global(&a.ctl->sched_len);
     }
     int64_t h = 0;
     double dm = 0.0, bm = 0.0;
     if (blockIdx.x == 0 && tid < a.Gs) {
-        h = a.h_part[tid];
-        dm = a.dmax_part[tid];
-        bm = a.binf_part[tid];
+        h = load_global(a.h_part + tid);
+        dm = load_global(a.dmax_part + tid);
+        bm = load_global(a.binf_part + tid);
     }
     State S{};
     if (a.iterate) {
-        S = a.ctl->st[slot_of(a.j - 1)];
+        S = load_global(&a.ctl->st[slot_of(a.j - 1)]);
         if (S.status != ST_RUNNING) return;
     }
+    // The drift row due next depends on the state only: requested now, so
+    // that it arrives while the partial rows are summed.
+    const bool due = colw && a.V && S.sched_pos < slen;
+    const double vdue = due ? load_global(a.V + S.sched_pos * a.ldV + col) : 0.0;
 
     // Batches of U independent 16-byte loads (partial rows rg, rg+RG, ...),
     // each batch summed in order, batches in order: a fixed order for a given G.
@@ -146,10 +152,9 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_y(const ReduceArgs a) {
                     xo = step_point(xo, S.s, yo);
                     a.x[col] = xo;
                 }
-                const bool due = a.V && S.sched_pos < a.ctl->sched_len;
                 Acc *w = reinterpret_cast<Acc *>(a.work);
                 w[col] = (Acc)xo;
-                w[a.ldA + col] = due ? (Acc)a.V[S.sched_pos * a.ldV + col] : (Acc)0;
+                w[a.ldA + col] = (Acc)vdue;
                 w[2 * a.ldA + col] = (Acc)yv;
             }
             a.y[col] = yv;
