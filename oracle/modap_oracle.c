@@ -13,8 +13,9 @@
  *   - eq. (7): positive slice rho+_i(x) = max(<a_i,x> - b_i, 0)/||a_i||^2 * a_i;
  *   - eq. (8): phi(x) = (1/h) * sum_i rho+_i(x), h = number of non-zero terms;
  *   - eq. (10): x is eps-feasible iff for every i either <a_i,x> <= b_i or
- *     |<a_i,x> - b_i| / ||a_i|| < eps  (this oracle uses "<= eps_abs", see the
- *     readings list of the design notes);
+ *     |<a_i,x> - b_i| / ||a_i|| < eps.  This oracle compares with "<=": a row
+ *     whose distance equals eps_abs counts as satisfied, which changes nothing
+ *     but the case of exact equality;
  *   - eq. (12): psi(x) = lambda * phi(x)/||phi(x)||, which equals
  *     lambda * y/||y|| with y = sum_i rho+_i(x) (section 3, list form);
  *   - section 3, ModAP on lists: Map computes the list of positive slices,
