@@ -129,7 +129,7 @@ modap_status modap_create(int device, void *hip_stream, modap_ctx **out);
 void modap_destroy(modap_ctx *ctx);
 
 /* Load the system A x <= b (section 2, eq. 1) and the starting point x0
- * (NULL = the zero vector, Step 2 of ModAP on lists).  A is m x n in `storage`
+ * (NULL = the zero vector, the start of ModAP on lists, section 3).  A is m x n in `storage`
  * with leading dimension lda; b is [m]; x0 is [n].  The library copies the data
  * into its own row-padded layout, computes ||a_i||^2 in FP64 and synchronises.
  * Resets iteration counters, the drift schedule and any pending update.
@@ -146,8 +146,8 @@ modap_status modap_set_system(modap_ctx *ctx, int64_t m, int64_t n, modap_dtype 
  * the next iterate or solve with E_NUMERIC.  Errors: E_STATE, E_INVAL. */
 modap_status modap_set_x(modap_ctx *ctx, const double *x, int ptrs_on_device);
 
-/* Update the data between iterations (Step 6 of ModAP on lists, Step 9 of
- * ModAPL): first, k >= 0 rows are replaced in place -- row rows[q] becomes
+/* Update the data between iterations (the data update of ModAP on lists and of
+ * ModAPL, section 3): first, k >= 0 rows are replaced in place -- row rows[q] becomes
  * new_rows[q*n .. q*n+n) (storage type, [k x n] row-major) and b[rows[q]]
  * becomes new_b[q], with ||a_i||^2 refreshed; then, when translate_v != NULL,
  * the feasible set is translated by +v: b <- b + A v.  The translation is not
@@ -169,7 +169,7 @@ modap_status modap_update_coeffs(modap_ctx *ctx, int64_t k, const int64_t *rows,
 modap_status modap_set_drift(modap_ctx *ctx, int64_t T, const double *V, int64_t ldv,
                              int ptrs_on_device);
 
-/* Queue k >= 0 iterations (ModAP on lists, Steps 3-8, each a sweep at the
+/* Queue k >= 0 iterations (the loop of ModAP on lists, section 3, each a sweep at the
  * current x and data followed by a step, unless that sweep finds x
  * eps-feasible, after which the remaining queued iterations do nothing).
  * With out == NULL the call returns without waiting; with out != NULL it

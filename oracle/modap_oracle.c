@@ -187,8 +187,9 @@ int oracle_step(int64_t n, const double *y, int64_t h, int rule, double lambda,
  * Order of one iteration (readings of the listing, which is an image in the
  * text): check x_k against the current data (eq. (10)); if eps-feasible, stop
  * and output x_k; otherwise Map/Reduce at x_k to y, step to x_{k+1}, then
- * update the data.  The paper's Step 7 check of x_{k+1} on the updated data
- * is the next iteration's check; the only addition is the check of x_0.
+ * update the data.  The paper's check of x_{k+1} on the updated data, which
+ * follows the data update, is the next iteration's check here; the only
+ * addition is the check of x_0.
  *
  * eps_abs = eps * max_i |b_i| (current b) when eps_relative != 0, else eps.
  * Returns 0 converged, 1 step limit reached, 2 no direction (||y|| = 0 while
