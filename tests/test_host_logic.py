@@ -124,3 +124,10 @@ def test_catchup_line_quotes_the_papers_rates_as_context():
                                                                                (100, 18, 3220)]
     assert [r["nodes"] for r in bench.paper_catchup_context(54000)["runs"]] == [75, 100, 150]
     assert bench.paper_catchup_context(1000) is None          # no printed run at this size
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
