@@ -305,6 +305,9 @@ def test_batch_errors(P):
         sys_ = W.gaussian(3000, 10, seed=1, dtype="f32")
         with pytest.raises(P.ModapError, match="E_INVAL"):
             B.add(sys_.A, sys_.b)                       # rows longer than the batched sweep covers
+        for shape in ((0, 4), (4, 0)):                     # empty systems
+            with pytest.raises(P.ModapError, match="E_INVAL"):
+                B.add(np.zeros(shape, dtype=np.float32), np.zeros(shape[0]))
         small = W.gaussian(50, 80, seed=2, dtype="f32")
         sid = B.add(small.A, small.b)
         with pytest.raises(P.ModapError, match="E_INVAL"):

@@ -481,6 +481,10 @@ def test_error_paths(P):
         with pytest.raises(P.ModapError) as e:
             s.iterate(1, P.params())
         assert e.value.status == 5                      # before set_system
+        for shape in ((0, 3), (3, 0)):                   # empty systems
+            with pytest.raises(P.ModapError) as e:
+                s.set_system(np.zeros(shape), np.zeros(shape[0]), dtype="f64")
+            assert e.value.status == 1
         A = np.array([[1.0, 0.0], [0.0, 0.0]])
         with pytest.raises(P.ModapError) as e:
             s.set_system(A, np.zeros(2), dtype="f64")
