@@ -85,7 +85,7 @@ MULTI = {
                           "10 ms of wall clock each live system translated (random walk, |v|=1e-4 per tick) and 1% "
                           "of its rows replaced (ticks elapsed during a round applied together after it), "
                           "admission by HBM footprint, ModAP lambda=0.1, eps=1e-6*||b||inf; the same arrivals and "
-                          "updates served in FP64 one request at a time for comparison",
+                          "updates also served one request at a time, in BF16 and in FP64, for comparison",
 }
 DT_CODE = {"f64": 0, "f32": 1, "bf16": 2}
 
@@ -732,6 +732,8 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8):
     S = P.Server(storage, budget_bytes=args.budget_gb * 1e9, prm=prm, iters_per_round=ipr)
     if max_live:
         S.set_max_live(max_live)
+    # the generators run on torch's stream; waiting for that stream alone
+    # leaves the server's iterations in flight
     gen = torch.Generator(device="cuda")
     gen.manual_seed(args.seed + 17)
     reqs = {}
@@ -745,7 +747,7 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8):
         while i < len(arrivals) and arrivals[i][0] <= now:
             t_arr, n, m, sd = arrivals[i]
             A, b, z = W.gaussian_device(n, m, seed=sd, dtype=storage)
-            torch.cuda.synchronize()
+            torch.cuda.current_stream().synchronize()
             tk = S.submit(A, b, now=t_arr)
             reqs[tk] = {"n": n, "m": m, "z": z}
             i += 1
@@ -764,7 +766,7 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8):
                 nrep = min(r["m"], k * max(1, math.ceil(frac * r["m"])))
                 idx, rows, nb = _replace_rows_device(torch, r["n"], r["m"], nrep, r["z"], gen, storage)
                 r["upd"] = (idx, rows, nb, v)
-            torch.cuda.synchronize()
+            torch.cuda.current_stream().synchronize()
             for tk in live:
                 idx, rows, nb, v = reqs[tk].pop("upd")
                 S.update(tk, rows=idx, new_rows=rows, new_b=nb, translate=v)
@@ -794,14 +796,17 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8):
 
 
 def bench_serve(args, P, W, torch):
-    """Served BF16 (continuous batching) against the plain FP64 form served one
-    request at a time, on the same arrival process and update schedule."""
+    """Served BF16 (continuous batching) against the same BF16 requests served
+    one at a time (a queue alone) and the plain FP64 form served one at a
+    time, on the same arrival process and update schedule."""
     arrivals = W.serving_arrivals(args.rate, args.horizon, seed=args.seed)
     log(f"{len(arrivals)} arrivals over {args.horizon} s at {args.rate}/s")
     cap = max(60.0, 6.0 * args.horizon)
     ipr = args.iters_per_round
     served, bytes_, wall, rounds = serve_pass(args, P, W, torch, arrivals, "bf16", 0, cap, ipr=ipr)
     log("served", served)
+    queue, _, _, _ = serve_pass(args, P, W, torch, arrivals, "bf16", 1, cap, ipr=ipr)
+    log("bf16 one at a time", queue)
     plain, _, _, _ = serve_pass(args, P, W, torch, arrivals, "f64", 1, cap, ipr=ipr)
     log("fp64 one at a time", plain)
     value = bytes_ / wall / 1e9
@@ -817,7 +822,8 @@ def bench_serve(args, P, W, torch):
         "roofline": {"bound": "hbm", "achieved": round(value, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(value / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "sweep_batch and sweep_wide of all live requests (aggregate over the pass)"},
-        "time_to_feasible": {"served_bf16_continuous_batching": served, "fp64_single_system_one_at_a_time": plain},
+        "time_to_feasible": {"served_bf16_continuous_batching": served, "bf16_queue_one_at_a_time": queue,
+                             "fp64_single_system_one_at_a_time": plain},
     }
     print(json.dumps(line), flush=True)
 

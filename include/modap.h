@@ -380,8 +380,11 @@ modap_status modap_server_submit(modap_server *server, int64_t m, int64_t n, con
                                  int64_t ldv, int ptrs_on_device, double now, int64_t *ticket);
 
 /* Data update of a live request (see modap_update_coeffs), applied before
- * its next iteration.  Errors: E_INVAL (unknown ticket), E_STATE (not live),
- * E_ZERO_ROW. */
+ * its next iteration.  Device buffers are copied before the call returns
+ * (their producer must have finished writing them), host buffers are read
+ * during the call: either may be reused at once.  Errors: E_INVAL (unknown
+ * ticket, k out of range), E_STATE (not live), E_ZERO_ROW, E_NOMEM,
+ * E_DEVICE. */
 modap_status modap_server_update(modap_server *server, int64_t ticket, int64_t k, const int64_t *rows,
                                  const void *new_rows, const double *new_b, const double *translate_v,
                                  int ptrs_on_device);

@@ -53,6 +53,15 @@ struct Req {
     std::vector<double> x;
 };
 
+// Device memory for the inputs of one update, reusable once the update that
+// read it has run (its event has completed).
+struct Stage {
+    void *p = nullptr;
+    size_t size = 0;
+    hipEvent_t used = nullptr;
+    bool busy = false;
+};
+
 }  // namespace
 
 struct modap_server {
@@ -67,6 +76,8 @@ struct modap_server {
     int64_t max_sweeps = 0;
     modap_batch *batch = nullptr;
     hipStream_t batch_stream = nullptr;
+    hipStream_t copy_stream = nullptr;    // staging of device-side update inputs
+    std::vector<Stage> stages;
     int batch_live = 0;
     std::vector<Req> reqs;
     std::deque<int64_t> pending;
@@ -94,6 +105,40 @@ double footprint(int dt, int64_t m, int64_t n, int64_t T) {
     const double acc = (double)acc_size(dt);
     return (double)m * ldA * (double)elem_size(dt) + 24.0 * (double)m + 5.0 * 8.0 * ldA + 6.0 * acc * ldA +
            acc * ldA * (double)((m + 63) / 64) + 8.0 * ldA * (double)T + 65536.0;
+}
+
+// A staging buffer of at least `bytes` whose last update has run, from the
+// server's pool (grown when none is free).
+modap_status take_stage(modap_server *s, size_t bytes, Stage **out) {
+    for (Stage &t : s->stages) {
+        if (t.busy) {
+            const hipError_t e = hipEventQuery(t.used);
+            if (e == hipSuccess) {
+                t.busy = false;
+            } else if (e != hipErrorNotReady) {
+                s->err = std::string("hipEventQuery: ") + hipGetErrorString(e);
+                return MODAP_E_DEVICE;
+            }
+        }
+        if (!t.busy && t.size >= bytes) {
+            *out = &t;
+            return MODAP_OK;
+        }
+    }
+    Stage t;
+    t.size = (bytes + (1u << 20) - 1) / (1u << 20) * (1u << 20);
+    if (hipMalloc(&t.p, t.size) != hipSuccess) {
+        s->err = "no device memory to stage an update";
+        return MODAP_E_NOMEM;
+    }
+    if (hipEventCreateWithFlags(&t.used, hipEventDisableTiming) != hipSuccess) {
+        (void)hipFree(t.p);
+        s->err = "hipEventCreateWithFlags failed";
+        return MODAP_E_DEVICE;
+    }
+    s->stages.push_back(t);
+    *out = &s->stages.back();
+    return MODAP_OK;
 }
 
 double elapsed_since(std::chrono::steady_clock::time_point t0) {
@@ -197,8 +242,14 @@ modap_status modap_server_create(int device, modap_dtype storage, double hbm_bud
         delete s;
         return MODAP_E_DEVICE;
     }
+    if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(s->batch_stream);
+        delete s;
+        return MODAP_E_DEVICE;
+    }
     modap_status st = modap_batch_create(device, s->batch_stream, storage, &s->batch);
     if (st) {
+        (void)hipStreamDestroy(s->copy_stream);
         (void)hipStreamDestroy(s->batch_stream);
         delete s;
         return st;
@@ -213,6 +264,12 @@ void modap_server_destroy(modap_server *s) {
     for (Req &r : s->reqs)
         if (r.state == RQ_LIVE) drop(s, r);
     modap_batch_destroy(s->batch);
+    for (Stage &t : s->stages) {
+        (void)hipEventSynchronize(t.used);
+        (void)hipFree(t.p);
+        (void)hipEventDestroy(t.used);
+    }
+    if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
     if (s->batch_stream) (void)hipStreamDestroy(s->batch_stream);
     delete s;
 }
@@ -251,13 +308,48 @@ modap_status modap_server_update(modap_server *s, int64_t ticket, int64_t k, con
     if (ticket < 0 || ticket >= (int64_t)s->reqs.size()) return fail(s, MODAP_E_INVAL, "unknown ticket");
     Req &r = s->reqs[(size_t)ticket];
     if (r.state != RQ_LIVE) return fail(s, MODAP_E_STATE, "the request is not live");
-    modap_status st;
-    if (r.in_batch) {
-        if ((st = modap_batch_update(s->batch, r.bid, k, rows, new_rows, new_b, translate_v, ptrs_on_device)))
-            return fail(s, st, modap_batch_last_error(s->batch));
-    } else if ((st = modap_update_coeffs(r.ctx, k, rows, new_rows, new_b, translate_v, ptrs_on_device))) {
-        return fail(s, st, modap_last_error(r.ctx));
+    if (k < 0 || k > r.m) return fail(s, MODAP_E_INVAL, "k out of range");
+    if (k > 0 && (!rows || !new_rows || !new_b)) return fail(s, MODAP_E_INVAL, "rows, new_rows and new_b are required");
+    DeviceGuard g(s->device);
+    // Device inputs are copied into memory of the server's own before the
+    // call returns, so that the caller may release or reuse its buffers at
+    // once although the update runs later on the request's stream.  The copy
+    // is reused only once the update that reads it has run.
+    const hipStream_t gs = r.in_batch ? s->batch_stream : r.stream;
+    const int64_t *rp = rows;
+    const void *np = new_rows;
+    const double *bp = new_b, *vp = translate_v;
+    Stage *stage = nullptr;
+    if (ptrs_on_device && (k > 0 || translate_v)) {
+        const size_t rb = (size_t)k * (size_t)r.n * s->es;
+        const size_t o2 = (size_t)k * 8, o3 = (o2 + rb + 15) / 16 * 16, o4 = o3 + (size_t)k * 8;
+        const size_t total = o4 + (translate_v ? (size_t)r.n * 8 : 0);
+        modap_status sst = take_stage(s, total, &stage);
+        if (sst) return sst;
+        char *p = reinterpret_cast<char *>(stage->p);
+        hipError_t e = hipSuccess;
+        if (k > 0) {
+            if (e == hipSuccess) e = hipMemcpyAsync(p, rows, (size_t)k * 8, hipMemcpyDeviceToDevice, s->copy_stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(p + o2, new_rows, rb, hipMemcpyDeviceToDevice, s->copy_stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(p + o3, new_b, (size_t)k * 8, hipMemcpyDeviceToDevice, s->copy_stream);
+        }
+        if (e == hipSuccess && translate_v)
+            e = hipMemcpyAsync(p + o4, translate_v, (size_t)r.n * 8, hipMemcpyDeviceToDevice, s->copy_stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->copy_stream);
+        if (e != hipSuccess) return fail(s, MODAP_E_DEVICE, std::string("staging the update: ") + hipGetErrorString(e));
+        rp = k > 0 ? reinterpret_cast<const int64_t *>(p) : nullptr;
+        np = k > 0 ? p + o2 : nullptr;
+        bp = k > 0 ? reinterpret_cast<const double *>(p + o3) : nullptr;
+        vp = translate_v ? reinterpret_cast<const double *>(p + o4) : nullptr;
     }
+    modap_status st = r.in_batch ? modap_batch_update(s->batch, r.bid, k, rp, np, bp, vp, ptrs_on_device)
+                                 : modap_update_coeffs(r.ctx, k, rp, np, bp, vp, ptrs_on_device);
+    if (stage) {
+        // reusable once whatever the update queued on the request's stream has run
+        HIP_TRY(s, hipEventRecord(stage->used, gs));
+        stage->busy = true;
+    }
+    if (st) return fail(s, st, r.in_batch ? modap_batch_last_error(s->batch) : modap_last_error(r.ctx));
     return MODAP_OK;
 }
 
