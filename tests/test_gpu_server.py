@@ -145,6 +145,41 @@ def test_server_updates_and_feasibility(P):
         assert o.dmax <= 1e-6 * o.binf + TOL["bf16"] * np.max(o.t / np.sqrt(o.nu))
 
 
+def test_server_update_inputs_may_be_reused_at_once(P):
+    """Device-side update inputs are copied before modap_server_update
+    returns: overwriting them right after the call (with NaN and zeros) does
+    not reach the requests, which finish eps-feasible for the data the update
+    described, on both the batched path and a context of its own."""
+    import torch
+    dev = torch.device("cuda:0")
+    systems = [W.gaussian(n, 4 * n, seed=70 + n, dtype="bf16") for n in (400, 4500)]
+    prm = P.params(lam=0.1, eps=1e-6, max_iters=5000)
+    with P.Server("bf16", budget_bytes=40e9, prm=prm, iters_per_round=8) as S:
+        tickets = [S.submit(s.A, s.b) for s in systems]
+        S.round()
+        say("server update inputs")
+        data = {}
+        for t, s in zip(tickets, systems):
+            assert S.info(t)["state"] == 1
+            idx, rows, nb = W.replacement_rows(s, max(1, s.m // 100), seed=t)
+            v = np.random.default_rng(t).normal(scale=1e-5, size=s.n)
+            d = [torch.from_numpy(a).to(dev) for a in (idx, rows.view(np.int16), nb, v)]
+            S.update(t, rows=d[0], new_rows=d[1], new_b=d[2], translate=d[3])
+            d[1].zero_()
+            d[2].fill_(float("nan"))
+            d[3].fill_(float("nan"))
+            torch.cuda.synchronize()
+            A2, b2 = oracle.replace_rows(s.A, "bf16", s.b, idx, rows, nb)
+            data[t] = (A2, oracle.translate(A2, "bf16", b2, v))
+        infos = run_until_done(S, tickets)
+        xs = [S.result(t) for t in tickets]
+    assert all(i["state"] == 2 and i["status"] == 1 for i in infos), infos
+    for t, x in zip(tickets, xs):
+        A, b = data[t]
+        o = oracle.sweep(A, "bf16", b, x)
+        assert o.dmax <= 1e-6 * o.binf + TOL["bf16"] * np.max(o.t / np.sqrt(o.nu))
+
+
 def test_server_errors(P):
     prm = P.params(lam=0.1, eps=1e-6, max_iters=100)
     with P.Server("bf16", budget_bytes=1e6, prm=prm) as S:
