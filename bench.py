@@ -68,6 +68,9 @@ WORKLOADS = {
     "bf16-16384x65536": ("bf16", 16384, 65536, 1e-4 / 128,
                          "BF16-stored Gaussian system n=16384 m=65536 (FP32 accumulation, FP64 scalars), "
                          "drift |v|=1e-4 per iteration, lambda=1, eps=1e-6*||b||inf, ModAP fixed-length step"),
+    "f64-4096x32768": ("f64", 4096, 32768, 1e-4 / 64,
+                       "FP64-stored Gaussian system n=4096 m=32768 (1 GiB, FP64 throughout), drift |v|=1e-4 per "
+                       "iteration, lambda=1, eps=1e-6*||b||inf, ModAP fixed-length step"),
 }
 ELEM_BYTES = {"f64": 8, "f32": 4, "bf16": 2}
 # Workloads of many systems: the batched family (512 FP32 systems, n ~ U{64..2048},
