@@ -740,7 +740,6 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8):
     gen = torch.Generator(device="cuda")
     gen.manual_seed(args.seed + 17)
     reqs = {}
-    waiting = set()
     i = 0
     t0 = time.perf_counter()
     next_tick = tick
@@ -752,11 +751,8 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8):
             t_arr, n, m, sd = arrivals[i]
             A, b, z = W.gaussian_device(n, m, seed=sd, dtype=storage)
             torch.cuda.current_stream().synchronize()
-            tk = S.submit(A, b, now=t_arr)
-            # the server reads A and b when it admits the request: keep them
-            # until then
-            reqs[tk] = {"n": n, "m": m, "z": z, "data": (A, b)}
-            waiting.add(tk)
+            tk = S.submit(A, b, now=t_arr)      # the binding holds A and b until admission
+            reqs[tk] = {"n": n, "m": m, "z": z}
             i += 1
         if now >= next_tick:
             # every tick that has elapsed since the last update counts: k ticks
@@ -780,9 +776,6 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8):
             next_tick += k * tick
         left = S.round(now)
         rounds += 1
-        for tk in [t for t in waiting if S.info(t)["state"] != 0]:
-            waiting.discard(tk)
-            reqs[tk].pop("data")
         if now - last_log > 5.0:
             log(f"{storage} max_live={max_live}: t={now:.1f}s arrivals {i}/{len(arrivals)} outstanding {left}")
             last_log = now

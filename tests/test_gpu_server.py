@@ -48,20 +48,21 @@ def final_b(sys_, V, steps):
     return b
 
 
-def test_server_result_same_alone_and_in_mix(P):
+@pytest.mark.parametrize("dtype", ["bf16", "f64"])
+def test_server_result_same_alone_and_in_mix(P, dtype):
     """Two requests (one batched, one with a context of its own because its
     rows exceed the batched sweep) with drift schedules, served alone and
     then among other requests arriving in between: identical x and step
     counts."""
-    short = W.gaussian(600, 2400, seed=11, dtype="bf16")
-    long = W.gaussian(5000, 6000, seed=12, dtype="bf16")
-    fillers = [W.gaussian(n, 4 * n, seed=n, dtype="bf16") for n in (128, 300, 4200, 900)]
+    short = W.gaussian(600, 2400, seed=11, dtype=dtype)
+    long = W.gaussian(5000, 6000, seed=12, dtype=dtype)
+    fillers = [W.gaussian(n, 4 * n, seed=n, dtype=dtype) for n in (128, 300, 4200, 900)]
     Vs = W.drift(600, 400, sigma=1e-5, seed=11)
     Vl = W.drift(5000, 400, sigma=1e-5, seed=12)
     prm = P.params(lam=0.1, eps=1e-6, max_iters=5000)
     out = {}
     for mix in (False, True):
-        with P.Server("bf16", budget_bytes=40e9, prm=prm, iters_per_round=8) as S:
+        with P.Server(dtype, budget_bytes=40e9, prm=prm, iters_per_round=8) as S:
             tickets = []
             if mix:
                 tickets.append(S.submit(fillers[0].A, fillers[0].b))
@@ -73,7 +74,7 @@ def test_server_result_same_alone_and_in_mix(P):
             tl = S.submit(long.A, long.b, V=Vl)
             if mix:
                 tickets.append(S.submit(fillers[3].A, fillers[3].b))
-            say(f"server mix={mix}")
+            say(f"server dtype={dtype} mix={mix}")
             infos = run_until_done(S, tickets + [ts, tl])
             assert all(i["state"] == 2 and i["status"] == 1 for i in infos), infos
             i_s, i_l = S.info(ts), S.info(tl)
@@ -83,8 +84,8 @@ def test_server_result_same_alone_and_in_mix(P):
     assert np.array_equal(out[False][0], out[True][0]) and np.array_equal(out[False][1], out[True][1])
     # and each result is eps-feasible for its own final (translated) data
     for sys_, V, x, it in ((short, Vs, out[True][0], out[True][2]), (long, Vl, out[True][1], out[True][3])):
-        o = oracle.sweep(sys_.A, "bf16", final_b(sys_, V, it), x)
-        assert o.dmax <= 1e-6 * o.binf + TOL["bf16"] * np.max(o.t / np.sqrt(o.nu))
+        o = oracle.sweep(sys_.A, dtype, final_b(sys_, V, it), x)
+        assert o.dmax <= 1e-6 * o.binf + TOL[dtype] * np.max(o.t / np.sqrt(o.nu))
 
 
 def test_server_admission_respects_budget(P):
