@@ -315,7 +315,7 @@ modap_status modap_batch_set_tile(modap_batch *batch, const modap_batch_tile *ti
 modap_status modap_batch_get_tile(modap_batch *batch, modap_batch_tile *tile);
 
 /* Autotuner of the batch: for each row-length bucket present, the item size
- * (KiB of A per work item, from 64 to 4096) and then the grid are chosen by
+ * (KiB of A per work item, from 64 to 16384) and then the grid are chosen by
  * timing `reps` stateless batch sweeps of the current systems (their state
  * is not changed); the result is kept and returned in *best (may be NULL).
  * Synchronises.  Errors: E_STATE (empty batch), E_INVAL, E_DEVICE. */

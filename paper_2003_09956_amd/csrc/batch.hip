@@ -52,9 +52,12 @@ int bucket_of(int C) { return C == 1 ? 0 : C == 2 ? 1 : C == 4 ? 2 : 3; }
 }  // namespace
 
 // The untuned tile, near what the autotuner finds on FP32 families with rows
-// up to 2048 elements: items of up to 0.5 / 2 / 4 / 4 MiB for the four
-// row-length buckets, one workgroup per CU.
-constexpr modap_batch_tile kBuiltinTile{{512, 2048, 4096, 4096}, 0};
+// up to 2048 elements: items of up to 0.5 / 2 / 4 / 8 MiB for the four
+// row-length buckets, one workgroup per CU.  On the 512-system family, 8 MiB
+// items for the longest rows took the sweep from 2.51 to 2.48 ms (fewer items,
+// each with a cost of its own; the largest are handed out first, so they do
+// not end the sweep late).
+constexpr modap_batch_tile kBuiltinTile{{512, 2048, 4096, 8192}, 0};
 
 struct modap_batch {
     int device = 0;
@@ -840,7 +843,7 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
     };
     // a work item costs a few microseconds beyond its rows (queue, state,
     // staging, partial): large items pay it rarely, small ones balance better
-    const int sizes[] = {64, 128, 256, 512, 1024, 2048, 4096};
+    const int sizes[] = {64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384};
     for (int q = 0; q < 4; ++q) {
         if (!present[q]) continue;
         float win = 0.f;
