@@ -35,7 +35,12 @@
  *    the upper 16 bits of an IEEE binary32 (uint16 bit patterns).
  *  - Precision: rows are stored as given; ||a_i||^2, b, x, y, the stop test
  *    and the step are FP64.  Dot products accumulate in FP64 for MODAP_F64
- *    storage and in FP32 for MODAP_F32 / MODAP_BF16 storage.
+ *    storage and in FP32 for MODAP_F32 / MODAP_BF16 storage; the optional
+ *    certificate of a stop (modap_params.certify) accumulates in FP64.
+ *  - Exact data: the library keeps the right-hand side as bref + A w, with w
+ *    the FP64 sum of every translation applied; the sweep carries a working
+ *    copy of b translated in its own precision, which the certificate rebases
+ *    onto the exact value.
  *  - Threading: a context is used by one host thread at a time; several
  *    contexts may share a device.
  */
@@ -81,13 +86,26 @@ typedef struct {
     int32_t track;          /* iterate only: != 0 keeps following a changing system -- an
                                eps-feasible check takes no step but does not stop the queued
                                iterations, so drift keeps being applied and re-checked */
+    int32_t certify;        /* != 0: every stop at eps-feasibility is confirmed by an FP64
+                               certificate before it is accepted (eq. 10 on the exact data):
+                               one more pass over the same stored rows with x and the
+                               translations in FP64, FP64 accumulation, and a rigorous bound of
+                               its own rounding added to every distance.  If the bound exceeds
+                               eps_abs, the certificate's y decides a step instead and the
+                               iteration goes on.  The certificate also rebases the working
+                               right-hand side onto the exact data (see modap_query).  It runs
+                               in modap_solve and at the end of modap_iterate, of
+                               modap_batch_solve and of a synchronising modap_batch_iterate, and
+                               in each round of the server. */
+    int32_t pad;
 } modap_params;
 
 typedef struct {
     int64_t iters;          /* steps taken since modap_set_system / modap_set_x */
     int64_t sweeps;         /* sweeps (feasibility checks) since then */
     int32_t converged;      /* 1 if the last check found x eps-feasible */
-    int32_t state;          /* 0 running, 1 converged, 2 no direction, 3 numeric, 4 step limit, 5 bad row */
+    int32_t state;          /* 0 running, 1 converged, 2 no direction, 3 numeric, 4 step limit, 5 bad row,
+                               6 not certifiable (eps_abs below the FP64 certificate's rounding bound) */
     double max_viol;        /* last check: max_i max(r_i, 0)/||a_i|| */
     int64_t h;              /* last check: number of violated rows */
     double y_norm;          /* last check: ||y|| */
@@ -101,6 +119,11 @@ typedef struct {
                                the previous step permanent in x); the stop decision and the
                                step length are taken at the start of the next sweep */
     int64_t profiled;       /* profile: number of sweeps timed in this call */
+    int32_t certified;      /* 1 if the last stop was confirmed by the FP64 certificate (max_viol
+                               is then its upper bound of the largest distance) */
+    int32_t pad;
+    double b_drift;         /* last certificate: largest |b_i - exact b_i| of the working
+                               right-hand side, which the certificate then corrected */
 } modap_stats;
 
 /* Kernel shape of the sweep (see modap_set_tile).  kind 0 = one pass with a
@@ -152,10 +175,14 @@ modap_status modap_set_x(modap_ctx *ctx, const double *x, int ptrs_on_device);
  * becomes new_b[q], with ||a_i||^2 refreshed; then, when translate_v != NULL,
  * the feasible set is translated by +v: b <- b + A v.  The translation is not
  * applied by a separate pass over A: it is carried into the next sweep, which
- * reads A anyway.  Updates take effect at the next sweep in call order.  rows
- * must be distinct and in [0, m).  A zero or non-finite replacement row is
- * reported as E_ZERO_ROW by this call for host inputs, and by the next
- * synchronising call for device inputs.  Errors: E_STATE, E_INVAL, E_ZERO_ROW. */
+ * reads A anyway.  Updates take effect at the next sweep in call order.  A
+ * translation still pending from an earlier call or from the drift schedule
+ * has already happened to the data: it does not move the new rows.  rows
+ * must be distinct and in [0, m).  For host inputs a repeated or
+ * out-of-range index is E_INVAL and a zero or non-finite row E_ZERO_ROW from
+ * this call; for device inputs each is detected on the device before any
+ * row is written, and reported as E_ZERO_ROW by the next synchronising call
+ * (the context must then be loaded again).  Errors: E_STATE, E_INVAL, E_ZERO_ROW. */
 modap_status modap_update_coeffs(modap_ctx *ctx, int64_t k, const int64_t *rows,
                                  const void *new_rows, const double *new_b,
                                  const double *translate_v, int ptrs_on_device);
@@ -194,9 +221,12 @@ modap_status modap_solve(modap_ctx *ctx, const modap_params *params, modap_stats
 modap_status modap_eval_sweep(modap_ctx *ctx, const double *x, double *r, double *y,
                               int64_t *h, double *max_viol, int ptrs_on_device);
 
-/* Read the current approximation x ([n]) and right-hand side b ([m], with
- * pending translations applied) and the statistics; any of x, b, out may be
- * NULL.  Synchronises.  Errors: E_STATE, E_DEVICE. */
+/* Read the current approximation x ([n]) and right-hand side b ([m]) and
+ * the statistics; any of x, b, out may be NULL.  b is the data as the caller
+ * sees them -- every translation given so far applied, pending ones included
+ * -- computed in FP64 as bref + A w (see "Exact data" above) without
+ * committing anything, so reading b never changes the iteration.
+ * Synchronises.  Errors: E_STATE, E_DEVICE. */
 modap_status modap_query(modap_ctx *ctx, double *x, double *b, modap_stats *out,
                          int ptrs_on_device);
 
@@ -289,8 +319,9 @@ modap_status modap_batch_update(modap_batch *batch, int64_t id, int64_t k, const
                                 int ptrs_on_device);
 
 /* Queue k iterations of every running system (see modap_iterate); out may be
- * NULL (then the call does not wait).  Errors: E_STATE (empty batch), E_INVAL,
- * E_DEVICE. */
+ * NULL (then the call does not wait, and a stop is left for the certificate
+ * of the next synchronising call, when params.certify asks for one).
+ * Errors: E_STATE (empty batch), E_INVAL, E_DEVICE. */
 modap_status modap_batch_iterate(modap_batch *batch, const modap_params *params, int64_t k,
                                  modap_batch_stats *out);
 
@@ -368,13 +399,14 @@ modap_status modap_server_create(int device, modap_dtype storage, double hbm_bud
 void modap_server_destroy(modap_server *server);
 
 /* Queue a request: A [m x n] (lda = n), b [m], x0 [n] or NULL, and a drift
- * schedule V [T x ldv] (T = 0: none).  Unlike the other calls, the caller's
- * buffers are READ LATER, when the request is admitted by a round; they must
- * stay valid and unchanged until modap_server_info reports it live, done or
- * failed.  Device buffers are read on the server's own streams: their
- * producer must have finished writing them before that round.  *ticket
- * identifies the request.  Errors: E_INVAL, E_NOMEM (the request alone
- * exceeds the budget). */
+ * schedule V [T x ldv] (T = 0: none).  The inputs are copied before the call
+ * returns -- host inputs into host memory, device inputs into device memory
+ * of the server (their producer must have finished writing them) -- so the
+ * caller may release or reuse them at once.  The copy is held while the
+ * request waits and released at admission; it is not counted against the
+ * budget, which governs live requests.  *ticket identifies the request.
+ * Errors: E_INVAL, E_NOMEM (the request alone exceeds the budget, or no
+ * memory for the copy), E_DEVICE. */
 modap_status modap_server_submit(modap_server *server, int64_t m, int64_t n, const void *A,
                                  const double *b, const double *x0, int64_t T, const double *V,
                                  int64_t ldv, int ptrs_on_device, double now, int64_t *ticket);

@@ -26,7 +26,8 @@ STEP_FIXED, STEP_AVG = 0, 1
 OK = 0
 STATUS_NAMES = {0: "OK", 1: "E_INVAL", 2: "E_ZERO_ROW", 3: "E_NOMEM", 4: "E_DEVICE", 5: "E_STATE",
                 6: "E_NOT_CONVERGED", 7: "E_INFEASIBLE", 8: "E_NUMERIC"}
-STATE_NAMES = {0: "running", 1: "converged", 2: "no_direction", 3: "numeric", 4: "step_limit", 5: "bad_row"}
+STATE_NAMES = {0: "running", 1: "converged", 2: "no_direction", 3: "numeric", 4: "step_limit", 5: "bad_row",
+               6: "uncertified"}
 
 # every symbol declared in include/modap.h
 EXPORTS = ["modap_create", "modap_destroy", "modap_set_system", "modap_set_x", "modap_update_coeffs",
@@ -43,7 +44,7 @@ EXPORTS = ["modap_create", "modap_destroy", "modap_set_system", "modap_set_x", "
 class Params(C.Structure):
     _fields_ = [("lambda_", C.c_double), ("eps", C.c_double), ("eps_relative", C.c_int32),
                 ("step", C.c_int32), ("max_iters", C.c_int64), ("profile", C.c_int32),
-                ("track", C.c_int32)]
+                ("track", C.c_int32), ("certify", C.c_int32), ("pad", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -51,10 +52,11 @@ class Stats(C.Structure):
                 ("state", C.c_int32), ("max_viol", C.c_double), ("h", C.c_int64),
                 ("y_norm", C.c_double), ("b_inf", C.c_double), ("eps_abs", C.c_double),
                 ("seconds", C.c_double), ("hbm_bytes", C.c_double), ("sweep_ms", C.c_double),
-                ("reduce_ms", C.c_double), ("profiled", C.c_int64)]
+                ("reduce_ms", C.c_double), ("profiled", C.c_int64), ("certified", C.c_int32),
+                ("pad", C.c_int32), ("b_drift", C.c_double)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
         d["state_name"] = STATE_NAMES.get(self.state, "?")
         return d
 
@@ -169,10 +171,11 @@ def lib():
 
 
 def params(lam=1.0, eps=1e-6, eps_relative=True, step=STEP_FIXED, max_iters=100000, profile=0,
-           track=False):
-    """profile: 0 = no timing, k = time every k-th iteration (True = every iteration)."""
+           track=False, certify=True):
+    """profile: 0 = no timing, k = time every k-th iteration (True = every iteration).
+    certify: confirm every stop at eps-feasibility with the library's FP64 certificate."""
     return Params(float(lam), float(eps), int(bool(eps_relative)), int(step), int(max_iters),
-                  int(profile), int(bool(track)))
+                  int(profile), int(bool(track)), int(bool(certify)), 0)
 
 
 def _is_torch(a):
@@ -504,8 +507,8 @@ class Batch:
 
 class Server:
     """Continuous-batching solve server (modap_server_* of the C ABI).  The
-    caller drives it with round(now); arrays of a submitted request are kept
-    referenced here until the request has been admitted."""
+    caller drives it with round(now); the library copies a request's inputs
+    when it is submitted."""
 
     def __init__(self, dtype="bf16", budget_bytes=64e9, prm=None, iters_per_round=8, device: int = 0):
         L = lib()
@@ -518,14 +521,12 @@ class Server:
         if st != OK:
             raise ModapError(st, L.modap_strerror(st).decode())
         self._h = h
-        self._held = {}
         self.shapes = {}
 
     def close(self):
         if getattr(self, "_h", None):
             lib().modap_server_destroy(self._h)
             self._h = None
-            self._held.clear()
 
     def __del__(self):
         try:
@@ -554,7 +555,6 @@ class Server:
         t = C.c_int64()
         self._check(lib().modap_server_submit(self._h, m, n, pa, pb, px, T, pv, n, g.on_dev, float(now),
                                               C.byref(t)))
-        self._held[t.value] = g.keep       # read by the library when the request is admitted
         self.shapes[t.value] = (m, n)
         return t.value
 
@@ -571,8 +571,6 @@ class Server:
     def round(self, now=0.0):
         out = C.c_int64()
         self._check(lib().modap_server_round(self._h, float(now), C.byref(out)))
-        for t in [t for t in self._held if self.info(t)["state"] != 0]:
-            del self._held[t]
         return out.value
 
     def info(self, ticket):

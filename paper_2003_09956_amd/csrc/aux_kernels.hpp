@@ -1,7 +1,7 @@
 // Kernels around the sweep: row norms, the fixed-order reduction of the
 // partial y, the stage kernel that settles each iteration, control-block
-// updates made between calls, in-place row replacement and the flush of a
-// pending translation.
+// updates made between calls, in-place row replacement and the exact
+// right-hand side read back by a query.
 #pragma once
 
 #include "modap_device.hpp"
@@ -90,11 +90,12 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_y(const ReduceArgs a) {
     };
     issue(rg);
     const bool colw = a.work && tid < COLS && col < a.n;
-    double xo = 0.0, yo = 0.0;
+    double xo = 0.0, yo = 0.0, wso = 0.0;
     int64_t slen = 0;
     if (colw) {
         xo = load_global(a.x + col);
         yo = load_global(a.y + col);
+        if (a.wsum) wso = load_global(a.wsum + col);
         if (a.V) slen = load_global(&a.ctl->sched_len);
     }
     int64_t h = 0;
@@ -110,9 +111,14 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_y(const ReduceArgs a) {
         if (S.status != ST_RUNNING) return;
     }
     // The drift row due next depends on the state only: requested now, so
-    // that it arrives while the partial rows are summed.
+    // that it arrives while the partial rows are summed.  So is the
+    // translation this sweep applied (one-shot part and drift row), which is
+    // added to the running sum of translations in FP64.
     const bool due = colw && a.V && S.sched_pos < slen;
     const double vdue = due ? load_global(a.V + S.sched_pos * a.ldV + col) : 0.0;
+    const bool ap = colw && a.wsum && a.has_v && S.vpend_valid;
+    const bool ar = colw && a.wsum && a.has_v && a.V && S.v_idx >= 0;
+    const double vap = (ap ? load_global(a.vpend + col) : 0.0) + (ar ? load_global(a.V + S.v_idx * a.ldV + col) : 0.0);
 
     // Batches of U independent 16-byte loads (partial rows rg, rg+RG, ...),
     // each batch summed in order, batches in order: a fixed order for a given G.
@@ -156,6 +162,7 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_y(const ReduceArgs a) {
                 w[col] = (Acc)xo;
                 w[a.ldA + col] = (Acc)vdue;
                 w[2 * a.ldA + col] = (Acc)yv;
+                if (ap || ar) a.wsum[col] = wso + vap;
             }
             a.y[col] = yv;
             sq = yv * yv;
@@ -322,65 +329,103 @@ __global__ void ctl_set_drift(Ctrl *c, int sl, int64_t T) {
 }
 
 // Row replacement in place (one workgroup per replaced row): copy the new
-// coefficients, refresh ||a_i||^2, and store b_i so that a translation still
-// pending for the next sweep leaves the new row's right-hand side as given.
+// coefficients, refresh ||a_i||^2, and store the right-hand sides.  A
+// translation still pending for the next sweep (the one-shot part and the
+// drift row due) has already happened to the data the caller sees, so it must
+// not move the new row: b_i is stored as new_b - <a_new, pending>, which the
+// next sweep's translation brings back to new_b.  The exact data are
+// bref + A wsum, so bref_i = new_b - <a_new, wsum + pending>.  Nothing is
+// written once the state holds ST_BAD_ROW (for instance after a duplicate
+// device-side row index).
 template <int DT>
 __global__ __launch_bounds__(256) void scatter_rows(void *A, int64_t ldA, int64_t m, int64_t n,
                                                     const int64_t *rows, const void *new_rows,
-                                                    const double *new_b, double *b, double *nu,
-                                                    Ctrl *ctl, int sl, const double *vpend) {
+                                                    const double *new_b, double *b, double *bref, double *nu,
+                                                    Ctrl *ctl, int sl, const double *vpend, const double *V,
+                                                    int64_t ldV, const double *wsum) {
     using T = typename Store<DT>::T;
     const int64_t q = blockIdx.x;
+    const State st = load_global(&ctl->st[sl]);
+    if (st.status == ST_BAD_ROW) return;
     const int64_t i = rows[q];
     if (i < 0 || i >= m) {
         if (threadIdx.x == 0) ctl->st[sl].status = ST_BAD_ROW;
         return;
     }
-    const int valid = ctl->st[sl].vpend_valid;
+    const bool valid = st.vpend_valid != 0;
+    const double *vrow = (V && st.v_idx >= 0) ? V + st.v_idx * ldV : nullptr;
     T *dst = reinterpret_cast<T *>(A) + i * ldA;
     const T *src = reinterpret_cast<const T *>(new_rows) + q * n;
-    double s2 = 0.0, sv = 0.0;
+    double s2 = 0.0, sv = 0.0, sw = 0.0;
     for (int64_t j = threadIdx.x; j < n; j += 256) {
         const T raw = src[j];
         dst[j] = raw;
         const double v = load_elem<DT>(src, j);
         s2 = __fma_rn(v, v, s2);
-        if (valid) sv = __fma_rn(v, vpend[j], sv);
+        const double pj = (valid ? vpend[j] : 0.0) + (vrow ? vrow[j] : 0.0);
+        sv = __fma_rn(v, pj, sv);
+        sw = __fma_rn(v, wsum[j], sw);
     }
     s2 = wave_sum(s2);
     sv = wave_sum(sv);
-    __shared__ double p2[4], pv[4];
+    sw = wave_sum(sw);
+    __shared__ double p2[4], pv[4], pw[4];
     if ((threadIdx.x & 63) == 0) {
         p2[threadIdx.x >> 6] = s2;
         pv[threadIdx.x >> 6] = sv;
+        pw[threadIdx.x >> 6] = sw;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         const double t2 = ((p2[0] + p2[1]) + p2[2]) + p2[3];
         const double tv = ((pv[0] + pv[1]) + pv[2]) + pv[3];
+        const double tw = ((pw[0] + pw[1]) + pw[2]) + pw[3];
         nu[i] = t2;
-        b[i] = valid ? new_b[q] - tv : new_b[q];
+        b[i] = new_b[q] - tv;
+        bref[i] = new_b[q] - (tw + tv);
         if (!(t2 > 0.0) || !isfinite(t2) || !isfinite(new_b[q])) ctl->st[sl].status = ST_BAD_ROW;
     }
 }
 
-// Apply a pending one-shot translation to b with a pass of its own (used when
-// b is read back): b_i += <a_i, vpend>, FP64, one wavefront per row.
+// Device-side row indices of a replacement: one thread per index claims its
+// row in `claim` (zero outside this pair of kernels); an index out of range or
+// claimed twice puts the state in ST_BAD_ROW before any row is written.
+__global__ void claim_rows(const int64_t *rows, int64_t k, int64_t m, int *claim, Ctrl *ctl, int sl) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < k; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = rows[q];
+        if (i < 0 || i >= m || atomicAdd(claim + i, 1) != 0) ctl->st[sl].status = ST_BAD_ROW;
+    }
+}
+
+// Releases the claims of claim_rows (after the replacement).
+__global__ void release_rows(const int64_t *rows, int64_t k, int64_t m, int *claim) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < k; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = rows[q];
+        if (i >= 0 && i < m) claim[i] = 0;
+    }
+}
+
+// The right-hand side of the data as the caller sees them, in FP64 and
+// without changing any state: out_i = bref_i + <a_i, wsum + pending>, with
+// the pending translation (one-shot part and due drift row) of slot sl.  One
+// wavefront per row, a fixed summation order.
 template <int DT>
-__global__ __launch_bounds__(256) void flush_translation(const void *A, int64_t ldA, int64_t m, int64_t n,
-                                                         const Ctrl *ctl, int sl, const double *vpend, double *b) {
-    if (!ctl->st[sl].vpend_valid) return;
+__global__ __launch_bounds__(256) void rhs_exact(const void *A, int64_t ldA, int64_t m, int64_t n, const Ctrl *ctl,
+                                                 int sl, const double *bref, const double *wsum,
+                                                 const double *vpend, const double *V, int64_t ldV, double *out) {
+    const State st = load_global(&ctl->st[sl]);
+    const bool valid = st.vpend_valid != 0;
+    const double *vrow = (V && st.v_idx >= 0) ? V + st.v_idx * ldV : nullptr;
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= m) return;
     double s = 0.0;
-    for (int64_t j = lane; j < n; j += 64) s = __fma_rn(load_elem<DT>(A, row * ldA + j), vpend[j], s);
+    for (int64_t j = lane; j < n; j += 64) {
+        const double t = wsum[j] + ((valid ? vpend[j] : 0.0) + (vrow ? vrow[j] : 0.0));
+        s = __fma_rn(load_elem<DT>(A, row * ldA + j), t, s);
+    }
     s = wave_sum(s);
-    if (lane == 0) b[row] += s;
-}
-
-__global__ void ctl_clear_vpend(Ctrl *c, int sl) {
-    if (threadIdx.x == 0) c->st[sl].vpend_valid = 0;
+    if (lane == 0) out[row] = bref[row] + s;
 }
 
 }  // namespace modap

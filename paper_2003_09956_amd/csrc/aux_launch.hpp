@@ -19,16 +19,24 @@ hipError_t aux_check_finite(const double *p, int64_t count, int *flag, hipStream
 hipError_t aux_ctl_init(Ctrl *c, hipStream_t s);
 // Replace k rows in place (see scatter_rows).
 hipError_t aux_scatter_rows(int dt, void *A, int64_t ldA, int64_t m, int64_t n, int64_t k, const int64_t *rows,
-                            const void *new_rows, const double *new_b, double *b, double *nu, Ctrl *ctl, int sl,
-                            const double *vpend, hipStream_t s);
+                            const void *new_rows, const double *new_b, double *b, double *bref, double *nu, Ctrl *ctl,
+                            int sl, const double *vpend, const double *V, int64_t ldV, const double *wsum,
+                            hipStream_t s);
+// Claim the rows of a device-side replacement before it (ST_BAD_ROW on an
+// index out of range or repeated), and release the claims after it.
+hipError_t aux_claim_rows(const int64_t *rows, int64_t k, int64_t m, int *claim, Ctrl *ctl, int sl, hipStream_t s);
+hipError_t aux_release_rows(const int64_t *rows, int64_t k, int64_t m, int *claim, hipStream_t s);
 // Add v to the one-shot translation of the state in slot sl.
 hipError_t aux_vpend_add(Ctrl *c, int sl, double *vpend, const double *v, int64_t n, hipStream_t s);
 // Move a scheduled translation that is due into the one-shot slot.
 hipError_t aux_sched_to_vpend(Ctrl *c, int sl, double *vpend, const double *V, int64_t ldV, int64_t n, hipStream_t s);
 // Install a drift schedule of T rows (the state restarts at its first row).
 hipError_t aux_ctl_set_drift(Ctrl *c, int sl, int64_t T, hipStream_t s);
-// Apply every translation still pending in slot sl to b with a pass of its own.
-hipError_t aux_flush(int dt, const void *A, int64_t ldA, int64_t m, int64_t n, Ctrl *ctl, int sl, double *vpend,
-                     const double *V, double *b, hipStream_t s);
+// out <- bref + A (wsum + pending translation of slot sl), FP64; changes no state.
+hipError_t aux_rhs_exact(int dt, const void *A, int64_t ldA, int64_t m, int64_t n, const Ctrl *ctl, int sl,
+                         const double *bref, const double *wsum, const double *vpend, const double *V, int64_t ldV,
+                         double *out, hipStream_t s);
+// Queue the FP64 certificate of the stop in slot a.sl (see certify.hpp); R and Gs are filled in.
+hipError_t aux_certify(int dt, CertArgs a, hipStream_t s);
 
 }  // namespace modap

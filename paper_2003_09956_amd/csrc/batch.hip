@@ -24,6 +24,7 @@
 #include "aux_launch.hpp"
 #include "batch_kernels.hpp"
 #include "host_common.hpp"
+#include "internal.hpp"
 #include "modap.h"
 
 using namespace modap;
@@ -36,6 +37,7 @@ struct BSys {
     int64_t m = 0, n = 0, ldA = 0;
     void *A = nullptr;
     double *b = nullptr, *nu = nullptr, *x = nullptr, *y = nullptr, *vpend = nullptr, *V = nullptr;
+    double *bref = nullptr, *wsum = nullptr;   // the data are bref + A wsum (see certify.hpp)
     int64_t T = 0;
     void *work = nullptr;
     Ctrl *ctl = nullptr;
@@ -95,6 +97,19 @@ struct modap_batch {
 
     int32_t *queue = nullptr;
     int *d_count = nullptr;
+    // shared by the systems (their calls are ordered on the batch's stream)
+    int *claim = nullptr;                  // row claims of a device-side replacement (zero between calls)
+    size_t claim_cap = 0;
+    double *rhs = nullptr;                 // exact right-hand side read by modap_batch_query
+    size_t rhs_cap = 0;
+    int2 *d_states = nullptr;              // statuses gathered for the certificate
+    size_t states_cap = 0;
+    // FP64 certificate scratch, sized for the largest system certified so far
+    double *cert_wt = nullptr, *cert_part = nullptr, *cert_y = nullptr, *cert_ynp = nullptr;
+    int64_t *cert_h = nullptr;
+    double *cert_dmax = nullptr, *cert_binf = nullptr, *cert_drift = nullptr;
+    Totals *cert_tot = nullptr;
+    size_t cert_m = 0, cert_part_cap = 0, cert_n = 0;
     int *h_count = nullptr;               // pinned [2]
     unsigned long long *bad = nullptr;
     int *flag = nullptr;
@@ -125,6 +140,8 @@ void release_sys(BSys &s) {
     free_dev(s.x);
     free_dev(s.y);
     free_dev(s.vpend);
+    free_dev(s.bref);
+    free_dev(s.wsum);
     free_dev(s.V);
     free_dev(s.work);
     free_dev(s.ctl);
@@ -213,6 +230,7 @@ modap_status rebuild(modap_batch *c) {
         d.x = s.x;
         d.y = s.y;
         d.vpend = s.vpend;
+        d.wsum = s.wsum;
         d.V = s.T > 0 ? s.V : nullptr;
         d.work = s.work;
         d.ctl = s.ctl;
@@ -427,7 +445,128 @@ modap_status count_running_now(modap_batch *c, int slot_index, int *out) {
 
 int last_slot(const modap_batch *c) { return (int)((c->jn - 1) & 1); }
 
+// Scratch of the FP64 certificate for a system of m rows and padded length
+// ldA (row bands of at least 256 rows, at most 128 bands).
+modap_status ensure_cert(modap_batch *c, int64_t m, int64_t ldA, int64_t *rpb, int *bands) {
+    *rpb = std::max<int64_t>(256, (m + 127) / 128);
+    *bands = (int)((m + *rpb - 1) / *rpb);
+    const size_t gs = (size_t)((m + 3) / 4);
+    if ((size_t)m > c->cert_m) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        free_dev(c->cert_wt);
+        free_dev(c->cert_h);
+        free_dev(c->cert_dmax);
+        free_dev(c->cert_binf);
+        free_dev(c->cert_drift);
+        c->cert_m = 0;
+        HIP_TRY(c, hipMalloc(&c->cert_wt, sizeof(double) * (size_t)m));
+        HIP_TRY(c, hipMalloc(&c->cert_h, sizeof(int64_t) * gs));
+        HIP_TRY(c, hipMalloc(&c->cert_dmax, sizeof(double) * gs));
+        HIP_TRY(c, hipMalloc(&c->cert_binf, sizeof(double) * gs));
+        HIP_TRY(c, hipMalloc(&c->cert_drift, sizeof(double) * gs));
+        c->cert_m = (size_t)m;
+    }
+    if ((size_t)ldA > c->cert_n) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        free_dev(c->cert_y);
+        free_dev(c->cert_ynp);
+        c->cert_n = 0;
+        HIP_TRY(c, hipMalloc(&c->cert_y, sizeof(double) * (size_t)ldA));
+        HIP_TRY(c, hipMalloc(&c->cert_ynp, sizeof(double) * (size_t)((ldA + 63) / 64)));
+        c->cert_n = (size_t)ldA;
+    }
+    const size_t pc = (size_t)*bands * (size_t)ldA;
+    if (pc > c->cert_part_cap) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        free_dev(c->cert_part);
+        c->cert_part_cap = 0;
+        HIP_TRY(c, hipMalloc(&c->cert_part, sizeof(double) * pc));
+        c->cert_part_cap = pc;
+    }
+    if (!c->cert_tot) HIP_TRY(c, hipMalloc(&c->cert_tot, sizeof(Totals)));
+    return MODAP_OK;
+}
+
+// Queue the FP64 certificate of system s (a no-op on the device unless its
+// committed state is an uncertified stop).
+modap_status certify_sys(modap_batch *c, BSys &s, const modap_params *p) {
+    int64_t rpb = 0;
+    int bands = 0;
+    modap_status st;
+    if ((st = ensure_cert(c, s.m, s.ldA, &rpb, &bands))) return st;
+    CertArgs v{};
+    v.A = s.A;
+    v.ldA = s.ldA;
+    v.m = s.m;
+    v.n = s.n;
+    v.b = s.b;
+    v.bref = s.bref;
+    v.nu = s.nu;
+    v.x = s.x;
+    v.wsum = s.wsum;
+    v.V = s.T > 0 ? s.V : nullptr;
+    v.ldV = s.ldA;
+    v.work = s.work;
+    v.ctl = s.ctl;
+    v.sl = last_slot(c);
+    v.wt = c->cert_wt;
+    v.h_part = c->cert_h;
+    v.dmax_part = c->cert_dmax;
+    v.binf_part = c->cert_binf;
+    v.drift_part = c->cert_drift;
+    v.bands = bands;
+    v.rows_per_band = rpb;
+    v.part = c->cert_part;
+    v.y = c->cert_y;
+    v.ynp = c->cert_ynp;
+    v.tot = c->cert_tot;
+    v.dp = decide_of(p, 0);
+    HIP_TRY(c, aux_certify(c->dt, v, c->stream));
+    return MODAP_OK;
+}
+
+// The certificate of every system whose committed state is an uncertified
+// stop (the states are read first, so only those systems are queued).
+// Synchronises.  *count (may be NULL) receives the number certified.
+modap_status certify_stopped(modap_batch *c, const modap_params *p, int *count) {
+    if (count) *count = 0;
+    const int nsys = (int)c->h_sys.size();
+    if (nsys == 0) return MODAP_OK;
+    modap_status st;
+    if ((st = ensure_buf(c, c->d_states, c->states_cap, (size_t)nsys))) return st;
+    BatchArgs a = batch_args(c);
+    hipLaunchKernelGGL(gather_states, dim3((nsys + 255) / 256), dim3(256), 0, c->stream, a, last_slot(c), c->d_states);
+    LAUNCH_TRY(c, "gather_states launch");
+    std::vector<int2> hs((size_t)nsys);
+    HIP_TRY(c, hipMemcpyAsync(hs.data(), c->d_states, sizeof(int2) * (size_t)nsys, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int cnt = 0;
+    for (int i = 0; i < nsys; ++i) {
+        if (hs[(size_t)i].x != ST_CONVERGED || hs[(size_t)i].y != 0) continue;
+        if ((st = certify_sys(c, c->sys[(size_t)c->order[(size_t)i]], p))) return st;
+        ++cnt;
+    }
+    if (cnt) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (count) *count = cnt;
+    return MODAP_OK;
+}
+
 }  // namespace
+
+// Certificate of the stops of the given systems (used by the server, which
+// reads each request's state after a round).  Synchronises.
+modap_status modap_batch_certify_ids(modap_batch *c, const modap_params *p, const int64_t *ids, int64_t count) {
+    if (!c) return MODAP_E_INVAL;
+    DeviceGuard g(c->device);
+    modap_status st;
+    for (int64_t q = 0; q < count; ++q) {
+        BSys *s = find_sys(c, ids[q]);
+        if (!s) return fail(c, MODAP_E_INVAL, "unknown system id");
+        if ((st = certify_sys(c, *s, p))) return st;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MODAP_OK;
+}
 
 extern "C" {
 
@@ -475,6 +614,18 @@ void modap_batch_destroy(modap_batch *c) {
     free_dev(c->binf_part);
     free_dev(c->queue);
     free_dev(c->d_count);
+    free_dev(c->claim);
+    free_dev(c->rhs);
+    free_dev(c->d_states);
+    free_dev(c->cert_wt);
+    free_dev(c->cert_part);
+    free_dev(c->cert_y);
+    free_dev(c->cert_ynp);
+    free_dev(c->cert_h);
+    free_dev(c->cert_dmax);
+    free_dev(c->cert_binf);
+    free_dev(c->cert_drift);
+    free_dev(c->cert_tot);
     free_dev(c->bad);
     free_dev(c->flag);
     free_dev(c->stage);
@@ -516,6 +667,7 @@ modap_status modap_batch_add(modap_batch *c, int64_t m, int64_t n, const void *A
     if ((e = hipMalloc(&s.A, abytes)) != hipSuccess || (e = hipMalloc(&s.b, sizeof(double) * m)) != hipSuccess ||
         (e = hipMalloc(&s.nu, sizeof(double) * m)) != hipSuccess || (e = hipMalloc(&s.x, vbytes)) != hipSuccess ||
         (e = hipMalloc(&s.y, vbytes)) != hipSuccess || (e = hipMalloc(&s.vpend, vbytes)) != hipSuccess ||
+        (e = hipMalloc(&s.wsum, vbytes)) != hipSuccess || (e = hipMalloc(&s.bref, sizeof(double) * m)) != hipSuccess ||
         (e = hipMalloc(&s.work, wbytes)) != hipSuccess || (e = hipMalloc(&s.ctl, sizeof(Ctrl))) != hipSuccess ||
         (e = hipMalloc(&s.tot, sizeof(Totals))) != hipSuccess ||
         (e = hipMalloc(&s.ynp, sizeof(double) * (size_t)((n + 63) / 64))) != hipSuccess)
@@ -537,6 +689,8 @@ modap_status modap_batch_add(modap_batch *c, int64_t m, int64_t n, const void *A
           "copy x0");
     q(hipMemsetAsync(s.y, 0, vbytes, c->stream), "hipMemsetAsync");
     q(hipMemsetAsync(s.vpend, 0, vbytes, c->stream), "hipMemsetAsync");
+    q(hipMemsetAsync(s.wsum, 0, vbytes, c->stream), "hipMemsetAsync");
+    q(hipMemcpyAsync(s.bref, s.b, sizeof(double) * m, hipMemcpyDeviceToDevice, c->stream), "copy b");
     q(hipMemsetAsync(s.work, 0, wbytes, c->stream), "hipMemsetAsync");
     const unsigned long long none = ULLONG_MAX;
     q(hipMemcpyAsync(c->bad, &none, sizeof none, hipMemcpyHostToDevice, c->stream), "copy");
@@ -654,9 +808,21 @@ modap_status modap_batch_update(modap_batch *c, int64_t id, int64_t k, const int
         d_v = v ? reinterpret_cast<const double *>(p + o4) : nullptr;
     }
     const int sl = last_slot(c);
+    if (k > 0 && on_dev) {
+        if (c->claim_cap < (size_t)s->m) {
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            free_dev(c->claim);
+            c->claim_cap = 0;
+            HIP_TRY(c, hipMalloc(&c->claim, sizeof(int) * (size_t)s->m));
+            HIP_TRY(c, hipMemsetAsync(c->claim, 0, sizeof(int) * (size_t)s->m, c->stream));
+            c->claim_cap = (size_t)s->m;
+        }
+        HIP_TRY(c, aux_claim_rows(d_rows, k, s->m, c->claim, s->ctl, sl, c->stream));
+    }
     if (k > 0)
-        HIP_TRY(c, aux_scatter_rows(c->dt, s->A, s->ldA, s->m, s->n, k, d_rows, d_new, d_b, s->b, s->nu, s->ctl, sl,
-                                    s->vpend, c->stream));
+        HIP_TRY(c, aux_scatter_rows(c->dt, s->A, s->ldA, s->m, s->n, k, d_rows, d_new, d_b, s->b, s->bref, s->nu,
+                                    s->ctl, sl, s->vpend, s->T > 0 ? s->V : nullptr, s->ldA, s->wsum, c->stream));
+    if (k > 0 && on_dev) HIP_TRY(c, aux_release_rows(d_rows, k, s->m, c->claim, c->stream));
     if (d_v) {
         HIP_TRY(c, aux_vpend_add(s->ctl, sl, s->vpend, d_v, s->n, c->stream));
         s->vpend_maybe = true;
@@ -685,6 +851,7 @@ modap_status modap_batch_iterate(modap_batch *c, const modap_params *p, int64_t 
         if ((st = enqueue_iteration(c, p, track, i, &ev, &bytes))) return st;
     if (k > 0 && (st = enqueue_settle(c, p, track))) return st;
     if (!out) return MODAP_OK;
+    if (k > 0 && p->certify && (st = certify_stopped(c, p, nullptr))) return st;
     if ((st = count_running_now(c, last_slot(c), &c->h_count[0]))) return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     *out = modap_batch_stats{};
@@ -709,33 +876,47 @@ modap_status modap_batch_solve(modap_batch *c, const modap_params *p, modap_batc
     const int64_t total = p->max_iters + 1;
     if (p->profile > 0 && !event_at(c, (size_t)(4 * ((std::min<int64_t>(total, 4096) + p->profile - 1) / p->profile)) - 1))
         return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
-    int64_t queued = 0, chunk = 1;
-    int slot = 0, pending = -1;
     size_t ev = 0;
     double bytes = 0.0;
-    bool done = false;
-    while (queued < total && !done) {
-        const int64_t cnt = std::min(chunk, total - queued);
-        for (int64_t i = 0; i < cnt; ++i)
-            if ((st = enqueue_iteration(c, p, 0, queued + i, &ev, &bytes))) return st;
-        queued += cnt;
-        // the newest settled states: the checks before the last queued sweep
-        if ((st = count_running_now(c, (int)((c->jn - 2) & 1), &c->h_count[slot]))) return st;
-        HIP_TRY(c, hipEventRecord(c->sync_ev[slot], c->stream));
-        if (pending >= 0) {
-            HIP_TRY(c, hipEventSynchronize(c->sync_ev[pending]));
-            if (c->h_count[pending] == 0) done = true;
+    int64_t queued_all = 0;
+    // Passes of queued iterations until no system runs; stops that the FP64
+    // certificate does not confirm have taken a step instead, and the next
+    // pass goes on from there (the step limits are the devices').
+    for (;;) {
+        int64_t queued = 0, chunk = 1;
+        int slot = 0, pending = -1;
+        bool done = false;
+        while (queued < total && !done) {
+            const int64_t cnt = std::min(chunk, total - queued);
+            for (int64_t i = 0; i < cnt; ++i)
+                if ((st = enqueue_iteration(c, p, 0, queued + i, &ev, &bytes))) return st;
+            queued += cnt;
+            // the newest settled states: the checks before the last queued sweep
+            if ((st = count_running_now(c, (int)((c->jn - 2) & 1), &c->h_count[slot]))) return st;
+            HIP_TRY(c, hipEventRecord(c->sync_ev[slot], c->stream));
+            if (pending >= 0) {
+                HIP_TRY(c, hipEventSynchronize(c->sync_ev[pending]));
+                if (c->h_count[pending] == 0) done = true;
+            }
+            pending = slot;
+            slot ^= 1;
+            chunk = std::min<int64_t>(chunk * 2, 64);
         }
-        pending = slot;
-        slot ^= 1;
-        chunk = std::min<int64_t>(chunk * 2, 64);
+        queued_all += queued;
+        if ((st = enqueue_settle(c, p, 0))) return st;
+        if (!p->certify) break;
+        int certified = 0;
+        if ((st = certify_stopped(c, p, &certified))) return st;
+        if (certified == 0) break;
+        if ((st = count_running_now(c, last_slot(c), &c->h_count[0]))) return st;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (c->h_count[0] == 0) break;
     }
-    if ((st = enqueue_settle(c, p, 0))) return st;
     if ((st = count_running_now(c, last_slot(c), &c->h_count[0]))) return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (out) {
         *out = modap_batch_stats{};
-        out->iters = queued;
+        out->iters = queued_all;
         out->running = c->h_count[0];
         out->systems = (int64_t)c->h_sys.size();
         out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -754,9 +935,11 @@ modap_status modap_batch_query(modap_batch *c, int64_t id, double *x, double *b,
     const int sl = last_slot(c);
     if (x && (st = b_from_device(c, x, s->x, sizeof(double) * s->n, on_dev))) return st;
     if (b) {
-        HIP_TRY(c, aux_flush(c->dt, s->A, s->ldA, s->m, s->n, s->ctl, sl, s->vpend, s->T > 0 ? s->V : nullptr, s->b,
-                             c->stream));
-        if ((st = b_from_device(c, b, s->b, sizeof(double) * s->m, on_dev))) return st;
+        // the data as the caller sees them, in FP64, without committing anything
+        if ((st = ensure_buf(c, c->rhs, c->rhs_cap, (size_t)s->m))) return st;
+        HIP_TRY(c, aux_rhs_exact(c->dt, s->A, s->ldA, s->m, s->n, s->ctl, sl, s->bref, s->wsum, s->vpend,
+                                 s->T > 0 ? s->V : nullptr, s->ldA, c->rhs, c->stream));
+        if ((st = b_from_device(c, b, c->rhs, sizeof(double) * s->m, on_dev))) return st;
     }
     State k;
     HIP_TRY(c, hipMemcpyAsync(&k, &s->ctl->st[sl], sizeof(State), hipMemcpyDeviceToHost, c->stream));
@@ -772,6 +955,8 @@ modap_status modap_batch_query(modap_batch *c, int64_t id, double *x, double *b,
         out->y_norm = k.ynorm;
         out->b_inf = k.binf;
         out->eps_abs = k.eps_abs;
+        out->certified = k.certified;
+        out->b_drift = k.bdrift;
     }
     return MODAP_OK;
 }

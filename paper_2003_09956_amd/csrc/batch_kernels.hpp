@@ -39,6 +39,7 @@ struct BatchSys {
     const double *nu;       // [m] ||a_i||^2
     double *x, *y;          // [ldA] FP64, zero-padded
     const double *vpend;    // [ldA] one-shot translation
+    double *wsum;           // [ldA] FP64 sum of the translations applied since the last rebase
     const double *V;        // drift schedule [T x ldA] or null
     void *work;             // [3 x ldA] Acc: x, v and y of the next sweep
     Ctrl *ctl;
@@ -403,6 +404,10 @@ __global__ __launch_bounds__(256) void reduce_batch(const BatchArgs a, const Bat
             xo = step_point(xo, P.s, S.y[col]);
             S.x[col] = xo;
         }
+        // the translation the sweep applied joins the FP64 sum of translations
+        const bool ap = P.vpend_valid != 0, ar = S.V && P.v_idx >= 0;
+        if (ap || ar)
+            S.wsum[col] += (ap ? S.vpend[col] : 0.0) + (ar ? S.V[P.v_idx * S.ldA + col] : 0.0);
         const bool due = S.V && P.sched_pos < S.ctl->sched_len;
         Acc *w = reinterpret_cast<Acc *>(S.work);
         w[col] = (Acc)xo;
@@ -474,6 +479,14 @@ __global__ __launch_bounds__(256) void settle_batch(const BatchArgs a) {
     const double s = sst.s;
     if (s == 0.0) return;
     for (int64_t col = threadIdx.x; col < S.n; col += blockDim.x) S.x[col] = step_point(S.x[col], s, S.y[col]);
+}
+
+// Status and certificate flag of every system in slot sl (one thread each).
+__global__ void gather_states(const BatchArgs a, int sl, int2 *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.nsys) return;
+    const State &s = a.sys[i].ctl->st[sl];
+    out[i] = make_int2(s.status, s.certified);
 }
 
 // Number of systems whose state in slot sl is ST_RUNNING (one workgroup).

@@ -25,6 +25,8 @@
 #include <vector>
 
 #include "aux_kernels.hpp"
+#include "aux_launch.hpp"
+#include "certify.hpp"
 #include "host_common.hpp"
 #include "modap.h"
 #include "sweep_split.hpp"
@@ -46,6 +48,9 @@ struct modap_ctx {
     size_t es = 0;
     void *A = nullptr;
     double *b = nullptr, *nu = nullptr, *x = nullptr, *y = nullptr, *vpend = nullptr;
+    double *bref = nullptr;      // [m] right-hand side at zero translation: the data are bref + A wsum
+    double *wsum = nullptr;      // [ldA] FP64 sum of the translations applied since the last rebase
+    int *claim = nullptr;        // [m] row claims of a device-side replacement (zero between calls)
     double *V = nullptr;
     int64_t T = 0;
     bool vpend_maybe = false;   // a translation may be pending on the device
@@ -86,6 +91,14 @@ struct modap_ctx {
     // staging for host-side update inputs
     void *stage = nullptr;
     size_t stage_bytes = 0;
+
+    // FP64 certificate scratch (allocated at the first certificate of a system)
+    double *cert_wt = nullptr, *cert_part = nullptr, *cert_y = nullptr, *cert_ynp = nullptr;
+    int64_t *cert_h = nullptr;
+    double *cert_dmax = nullptr, *cert_binf = nullptr, *cert_drift = nullptr;
+    Totals *cert_tot = nullptr;
+    int cert_bands = 0;
+    int64_t cert_rows_per_band = 0;
 
     std::vector<hipEvent_t> events;
     hipEvent_t sync_ev[2] = {nullptr, nullptr};
@@ -418,6 +431,7 @@ ReduceArgs reduce_args(modap_ctx *c) {
     r.binf_part = c->binf_part;
     r.tot = c->tot;
     r.ynp = c->ynp;
+    r.vpend = c->vpend;
     return r;
 }
 
@@ -530,6 +544,8 @@ modap_status enqueue_iteration(modap_ctx *c, const modap_params *p, int track, i
     r.iterate = 1;
     r.apply_step = i > 0;
     r.work = c->work;
+    r.wsum = hv ? c->wsum : nullptr;   // no translation: nothing to add to the sum
+    r.has_v = hv;
     if ((st = launch_reduce(c, r, ev[2], ev[3]))) return st;
     c->jn = j + 1;
     *bytes += sweep_bytes(c, hv);
@@ -564,6 +580,8 @@ void fill_stats(modap_stats *o, const State &k) {
     o->y_norm = k.ynorm;
     o->b_inf = k.binf;
     o->eps_abs = k.eps_abs;
+    o->certified = k.certified;
+    o->b_drift = k.bdrift;
 }
 
 modap_status profile_totals(modap_ctx *c, size_t ev_used, modap_stats *o) {
@@ -590,12 +608,32 @@ modap_status status_of(modap_ctx *c, const State &k, bool solve) {
         case ST_LIMIT: return solve ? fail(c, MODAP_E_NOT_CONVERGED, "step limit reached before eps-feasibility") : MODAP_OK;
         case ST_NO_DIRECTION: return fail(c, MODAP_E_INFEASIBLE, "a row is violated but y = 0: no step direction");
         case ST_NUMERIC: return fail(c, MODAP_E_NUMERIC, "NaN or infinity in the iteration");
-        case ST_BAD_ROW: return fail(c, MODAP_E_ZERO_ROW, "a replaced row is zero, not finite, or out of range");
+        case ST_BAD_ROW: return fail(c, MODAP_E_ZERO_ROW, "a replaced row is zero, not finite, out of range or repeated");
+        case ST_UNCERTIFIED:
+            return fail(c, MODAP_E_NOT_CONVERGED, "the FP64 certificate cannot confirm the stop: eps_abs lies below "
+                                                  "its rounding bound");
         default: return fail(c, MODAP_E_DEVICE, "unknown device state");
     }
 }
 
+void release_cert(modap_ctx *c) {
+    free_dev(c->cert_wt);
+    free_dev(c->cert_part);
+    free_dev(c->cert_y);
+    free_dev(c->cert_ynp);
+    free_dev(c->cert_h);
+    free_dev(c->cert_dmax);
+    free_dev(c->cert_binf);
+    free_dev(c->cert_drift);
+    free_dev(c->cert_tot);
+    c->cert_bands = 0;
+}
+
 void release_system(modap_ctx *c) {
+    release_cert(c);
+    free_dev(c->bref);
+    free_dev(c->wsum);
+    free_dev(c->claim);
     free_dev(c->A);
     free_dev(c->wrow);
     free_dev(c->b);
@@ -615,31 +653,67 @@ void release_system(modap_ctx *c) {
 }
 
 modap_status launch_scatter(modap_ctx *c, int64_t k, const int64_t *rows, const void *new_rows, const double *nb) {
-    const int sl = last_slot(c);
-    switch (c->dt) {
-        case 0: hipLaunchKernelGGL(scatter_rows<0>, dim3(k), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, rows, new_rows, nb, c->b, c->nu, c->ctl, sl, (const double *)c->vpend); break;
-        case 1: hipLaunchKernelGGL(scatter_rows<1>, dim3(k), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, rows, new_rows, nb, c->b, c->nu, c->ctl, sl, (const double *)c->vpend); break;
-        default: hipLaunchKernelGGL(scatter_rows<2>, dim3(k), dim3(256), 0, c->stream, c->A, c->ldA, c->m, c->n, rows, new_rows, nb, c->b, c->nu, c->ctl, sl, (const double *)c->vpend); break;
-    }
-    LAUNCH_TRY(c, "scatter_rows launch");
+    HIP_TRY(c, aux_scatter_rows(c->dt, c->A, c->ldA, c->m, c->n, k, rows, new_rows, nb, c->b, c->bref, c->nu,
+                                c->ctl, last_slot(c), c->vpend, c->V, c->ldA, c->wsum, c->stream));
     return MODAP_OK;
 }
 
-modap_status launch_flush(modap_ctx *c) {
-    const int sl = last_slot(c);
-    const int nb = (int)((c->m + 3) / 4);
-    hipLaunchKernelGGL(sched_to_vpend, dim3(1), dim3(1024), 0, c->stream, c->ctl, sl, c->vpend, (const double *)c->V,
-                       c->ldA, c->n);
-    switch (c->dt) {
-        case 0: hipLaunchKernelGGL(flush_translation<0>, dim3(nb), dim3(256), 0, c->stream, (const void *)c->A, c->ldA, c->m, c->n, (const Ctrl *)c->ctl, sl, (const double *)c->vpend, c->b); break;
-        case 1: hipLaunchKernelGGL(flush_translation<1>, dim3(nb), dim3(256), 0, c->stream, (const void *)c->A, c->ldA, c->m, c->n, (const Ctrl *)c->ctl, sl, (const double *)c->vpend, c->b); break;
-        default: hipLaunchKernelGGL(flush_translation<2>, dim3(nb), dim3(256), 0, c->stream, (const void *)c->A, c->ldA, c->m, c->n, (const Ctrl *)c->ctl, sl, (const double *)c->vpend, c->b); break;
-    }
-    hipLaunchKernelGGL(ctl_clear_vpend, dim3(1), dim3(64), 0, c->stream, c->ctl, sl);
-    LAUNCH_TRY(c, "flush_translation launch");
+// Scratch of the FP64 certificate: row bands of at least 256 rows, at most
+// 128 bands (the band partials of y are FP64 rows of ldA).
+modap_status ensure_cert(modap_ctx *c) {
+    if (c->cert_bands > 0) return MODAP_OK;
+    const int64_t rpb = std::max<int64_t>(256, (c->m + 127) / 128);
+    const int bands = (int)((c->m + rpb - 1) / rpb);
+    const int64_t gs = (c->m + 3) / 4;
+    HIP_TRY(c, hipMalloc(&c->cert_wt, sizeof(double) * (size_t)c->m));
+    HIP_TRY(c, hipMalloc(&c->cert_part, sizeof(double) * (size_t)bands * (size_t)c->ldA));
+    HIP_TRY(c, hipMalloc(&c->cert_y, sizeof(double) * (size_t)c->ldA));
+    HIP_TRY(c, hipMalloc(&c->cert_ynp, sizeof(double) * (size_t)reduce_grid(c)));
+    HIP_TRY(c, hipMalloc(&c->cert_h, sizeof(int64_t) * (size_t)gs));
+    HIP_TRY(c, hipMalloc(&c->cert_dmax, sizeof(double) * (size_t)gs));
+    HIP_TRY(c, hipMalloc(&c->cert_binf, sizeof(double) * (size_t)gs));
+    HIP_TRY(c, hipMalloc(&c->cert_drift, sizeof(double) * (size_t)gs));
+    HIP_TRY(c, hipMalloc(&c->cert_tot, sizeof(Totals)));
+    c->cert_rows_per_band = rpb;
+    c->cert_bands = bands;
     return MODAP_OK;
 }
 
+// Queue the FP64 certificate of the committed state (a no-op on the device
+// unless that state is an uncertified stop).
+modap_status enqueue_certify(modap_ctx *c, const modap_params *p) {
+    modap_status st;
+    if ((st = ensure_cert(c))) return st;
+    CertArgs v{};
+    v.A = c->A;
+    v.ldA = c->ldA;
+    v.m = c->m;
+    v.n = c->n;
+    v.b = c->b;
+    v.bref = c->bref;
+    v.nu = c->nu;
+    v.x = c->x;
+    v.wsum = c->wsum;
+    v.V = c->V;
+    v.ldV = c->ldA;
+    v.work = c->work;
+    v.ctl = c->ctl;
+    v.sl = last_slot(c);
+    v.wt = c->cert_wt;
+    v.h_part = c->cert_h;
+    v.dmax_part = c->cert_dmax;
+    v.binf_part = c->cert_binf;
+    v.drift_part = c->cert_drift;
+    v.bands = c->cert_bands;
+    v.rows_per_band = c->cert_rows_per_band;
+    v.part = c->cert_part;
+    v.y = c->cert_y;
+    v.ynp = c->cert_ynp;
+    v.tot = c->cert_tot;
+    v.dp = decide_params(p, 0);
+    HIP_TRY(c, aux_certify(c->dt, v, c->stream));
+    return MODAP_OK;
+}
 
 // Tuning cache: lines "dt ldA m block lanes_per_row chunks rows_per_step depth interleave grid".
 const char *tune_cache_path() {
@@ -794,6 +868,8 @@ modap_status modap_set_system(modap_ctx *c, int64_t m, int64_t n, modap_dtype st
     const size_t abytes = (size_t)m * (size_t)c->ldA * c->es;
     HIP_TRY(c, hipMalloc(&c->A, abytes));
     HIP_TRY(c, hipMalloc(&c->b, sizeof(double) * m));
+    HIP_TRY(c, hipMalloc(&c->bref, sizeof(double) * m));
+    HIP_TRY(c, hipMalloc(&c->claim, sizeof(int) * m));
     HIP_TRY(c, hipMalloc(&c->nu, sizeof(double) * m));
     // x, y, the one-shot translation and the evaluation point are padded with
     // zeros to ldA so that the sweep reads whole 16-byte vectors of them.
@@ -801,6 +877,7 @@ modap_status modap_set_system(modap_ctx *c, int64_t m, int64_t n, modap_dtype st
     HIP_TRY(c, hipMalloc(&c->x, vbytes));
     HIP_TRY(c, hipMalloc(&c->y, vbytes));
     HIP_TRY(c, hipMalloc(&c->vpend, vbytes));
+    HIP_TRY(c, hipMalloc(&c->wsum, vbytes));
     HIP_TRY(c, hipMalloc(&c->x_eval, vbytes));
     HIP_TRY(c, hipMalloc(&c->y_eval, vbytes));
     const size_t wbytes = 3 * acc_size(c->dt) * (size_t)c->ldA;
@@ -820,6 +897,9 @@ modap_status modap_set_system(modap_ctx *c, int64_t m, int64_t n, modap_dtype st
     if (x0 && (st = to_device(c, c->x, x0, sizeof(double) * n, on_dev))) return st;
     HIP_TRY(c, hipMemsetAsync(c->y, 0, vbytes, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->vpend, 0, vbytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->wsum, 0, vbytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->claim, 0, sizeof(int) * m, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->bref, c->b, sizeof(double) * m, hipMemcpyDeviceToDevice, c->stream));
     const unsigned long long none = ULLONG_MAX;
     HIP_TRY(c, hipMemcpyAsync(c->bad, &none, sizeof none, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
@@ -946,7 +1026,9 @@ modap_status modap_update_coeffs(modap_ctx *c, int64_t k, const int64_t *rows, c
         d_b = reinterpret_cast<const double *>(s + o3);
         d_v = v ? reinterpret_cast<const double *>(s + o4) : nullptr;
     }
+    if (k > 0 && on_dev) HIP_TRY(c, aux_claim_rows(d_rows, k, c->m, c->claim, c->ctl, last_slot(c), c->stream));
     if (k > 0 && (st = launch_scatter(c, k, d_rows, d_new, d_b))) return st;
+    if (k > 0 && on_dev) HIP_TRY(c, aux_release_rows(d_rows, k, c->m, c->claim, c->stream));
     if (d_v) {
         hipLaunchKernelGGL(vpend_add, dim3(1), dim3(1024), 0, c->stream, c->ctl, last_slot(c), c->vpend, d_v, c->n);
         LAUNCH_TRY(c, "vpend_add launch");
@@ -1019,6 +1101,7 @@ modap_status modap_iterate(modap_ctx *c, const modap_params *p, int64_t k, modap
     for (int64_t i = 0; i < k; ++i)
         if ((st = enqueue_iteration(c, p, track, i, &ev, &bytes))) return st;
     if (k > 0 && (st = enqueue_settle(c, p, track))) return st;
+    if (k > 0 && p->certify && (st = enqueue_certify(c, p))) return st;
     if (!out) return MODAP_OK;
     State kc;
     if ((st = read_state(c, &kc))) return st;
@@ -1042,39 +1125,45 @@ modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) 
     if ((st = enqueue_prime(c, c->work, c->x))) return st;
     const int64_t total = p->max_iters + 1;  // the last sweep checks the last step
     if ((st = reserve_events(c, std::min<int64_t>(total, 4096), p->profile))) return st;
-    int64_t queued = 0, chunk = 1;
-    int slot = 0, pending = -1;
     size_t ev = 0;
     double bytes = 0.0;
-    bool done = false;
     auto observed = t0;
-    while (queued < total && !done) {
-        const int64_t cnt = std::min(chunk, total - queued);
-        for (int64_t i = 0; i < cnt; ++i)
-            if ((st = enqueue_iteration(c, p, 0, queued + i, &ev, &bytes))) return st;
-        queued += cnt;
-        // the newest settled state: the check before the last queued sweep
-        HIP_TRY(c, hipMemcpyAsync(&c->hst[slot], &c->ctl->st[slot_of(c->jn - 2)], sizeof(State),
-                                  hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(c, hipEventRecord(c->sync_ev[slot], c->stream));
-        if (pending >= 0) {
-            HIP_TRY(c, hipEventSynchronize(c->sync_ev[pending]));
-            if (c->hst[pending].status != ST_RUNNING) {
-                done = true;
-                observed = std::chrono::steady_clock::now();
-            }
-        }
-        pending = slot;
-        slot ^= 1;
-        chunk = std::min<int64_t>(chunk * 2, 64);
-    }
-    if ((st = enqueue_settle(c, p, 0))) return st;
-    if (!done) {
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        observed = std::chrono::steady_clock::now();
-    }
     State kc;
-    if ((st = read_state(c, &kc))) return st;
+    // Passes of queued iterations until the device stops; a stop at
+    // eps-feasibility that the FP64 certificate does not confirm has taken a
+    // step instead, and the next pass goes on from there.  The step limit is
+    // the device's, so a pass may queue more iterations than remain.
+    for (;;) {
+        int64_t queued = 0, chunk = 1;
+        int slot = 0, pending = -1;
+        bool done = false;
+        while (queued < total && !done) {
+            const int64_t cnt = std::min(chunk, total - queued);
+            for (int64_t i = 0; i < cnt; ++i)
+                if ((st = enqueue_iteration(c, p, 0, queued + i, &ev, &bytes))) return st;
+            queued += cnt;
+            // the newest settled state: the check before the last queued sweep
+            HIP_TRY(c, hipMemcpyAsync(&c->hst[slot], &c->ctl->st[slot_of(c->jn - 2)], sizeof(State),
+                                      hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipEventRecord(c->sync_ev[slot], c->stream));
+            if (pending >= 0) {
+                HIP_TRY(c, hipEventSynchronize(c->sync_ev[pending]));
+                if (c->hst[pending].status != ST_RUNNING) done = true;
+            }
+            pending = slot;
+            slot ^= 1;
+            chunk = std::min<int64_t>(chunk * 2, 64);
+        }
+        if ((st = enqueue_settle(c, p, 0))) return st;
+        if ((st = read_state(c, &kc))) return st;
+        observed = std::chrono::steady_clock::now();
+        if (!(p->certify && kc.status == ST_CONVERGED && !kc.certified)) break;
+        if ((st = enqueue_certify(c, p))) return st;
+        if ((st = read_state(c, &kc))) return st;
+        bytes += sweep_bytes(c, false);
+        observed = std::chrono::steady_clock::now();
+        if (kc.status != ST_RUNNING) break;
+    }
     if (out) {
         *out = modap_stats{};
         fill_stats(out, kc);
@@ -1121,18 +1210,16 @@ modap_status modap_query(modap_ctx *c, double *x, double *b, modap_stats *out, i
     modap_status st = check_ctx(c, true);
     if (st) return st;
     DeviceGuard g(c->device);
-    const int sl = last_slot(c);
-    (void)sl;
     if (x && (st = from_device(c, x, c->x, sizeof(double) * c->n, on_dev))) return st;
     if (b) {
-        if (c->vpend_maybe || c->V) {
-            if ((st = launch_flush(c))) return st;
-        }
-        if ((st = from_device(c, b, c->b, sizeof(double) * c->m, on_dev))) return st;
+        // the data as the caller sees them, every translation applied, in FP64;
+        // nothing is committed, so reading b does not change the iteration
+        HIP_TRY(c, aux_rhs_exact(c->dt, c->A, c->ldA, c->m, c->n, c->ctl, last_slot(c), c->bref, c->wsum, c->vpend,
+                                 c->V, c->ldA, c->r_eval, c->stream));
+        if ((st = from_device(c, b, c->r_eval, sizeof(double) * c->m, on_dev))) return st;
     }
     State kc;
     if ((st = read_state(c, &kc))) return st;
-    if (b) c->vpend_maybe = false;
     if (out) {
         *out = modap_stats{};
         fill_stats(out, kc);
@@ -1273,13 +1360,26 @@ hipError_t aux_ctl_init(Ctrl *c, hipStream_t s) {
 }
 
 hipError_t aux_scatter_rows(int dt, void *A, int64_t ldA, int64_t m, int64_t n, int64_t k, const int64_t *rows,
-                            const void *new_rows, const double *new_b, double *b, double *nu, Ctrl *ctl, int sl,
-                            const double *vpend, hipStream_t s) {
+                            const void *new_rows, const double *new_b, double *b, double *bref, double *nu, Ctrl *ctl,
+                            int sl, const double *vpend, const double *V, int64_t ldV, const double *wsum,
+                            hipStream_t s) {
     switch (dt) {
-        case 0: hipLaunchKernelGGL(scatter_rows<0>, dim3(k), dim3(256), 0, s, A, ldA, m, n, rows, new_rows, new_b, b, nu, ctl, sl, vpend); break;
-        case 1: hipLaunchKernelGGL(scatter_rows<1>, dim3(k), dim3(256), 0, s, A, ldA, m, n, rows, new_rows, new_b, b, nu, ctl, sl, vpend); break;
-        default: hipLaunchKernelGGL(scatter_rows<2>, dim3(k), dim3(256), 0, s, A, ldA, m, n, rows, new_rows, new_b, b, nu, ctl, sl, vpend); break;
+        case 0: hipLaunchKernelGGL(scatter_rows<0>, dim3(k), dim3(256), 0, s, A, ldA, m, n, rows, new_rows, new_b, b, bref, nu, ctl, sl, vpend, V, ldV, wsum); break;
+        case 1: hipLaunchKernelGGL(scatter_rows<1>, dim3(k), dim3(256), 0, s, A, ldA, m, n, rows, new_rows, new_b, b, bref, nu, ctl, sl, vpend, V, ldV, wsum); break;
+        default: hipLaunchKernelGGL(scatter_rows<2>, dim3(k), dim3(256), 0, s, A, ldA, m, n, rows, new_rows, new_b, b, bref, nu, ctl, sl, vpend, V, ldV, wsum); break;
     }
+    return hipPeekAtLastError();
+}
+
+hipError_t aux_claim_rows(const int64_t *rows, int64_t k, int64_t m, int *claim, Ctrl *ctl, int sl, hipStream_t s) {
+    const int grid = (int)std::min<int64_t>(1024, (k + 255) / 256);
+    hipLaunchKernelGGL(claim_rows, dim3(grid), dim3(256), 0, s, rows, k, m, claim, ctl, sl);
+    return hipPeekAtLastError();
+}
+
+hipError_t aux_release_rows(const int64_t *rows, int64_t k, int64_t m, int *claim, hipStream_t s) {
+    const int grid = (int)std::min<int64_t>(1024, (k + 255) / 256);
+    hipLaunchKernelGGL(release_rows, dim3(grid), dim3(256), 0, s, rows, k, m, claim);
     return hipPeekAtLastError();
 }
 
@@ -1298,16 +1398,37 @@ hipError_t aux_ctl_set_drift(Ctrl *c, int sl, int64_t T, hipStream_t s) {
     return hipPeekAtLastError();
 }
 
-hipError_t aux_flush(int dt, const void *A, int64_t ldA, int64_t m, int64_t n, Ctrl *ctl, int sl, double *vpend,
-                     const double *V, double *b, hipStream_t s) {
+hipError_t aux_rhs_exact(int dt, const void *A, int64_t ldA, int64_t m, int64_t n, const Ctrl *ctl, int sl,
+                         const double *bref, const double *wsum, const double *vpend, const double *V, int64_t ldV,
+                         double *out, hipStream_t s) {
     const int nb = (int)((m + 3) / 4);
-    hipLaunchKernelGGL(sched_to_vpend, dim3(1), dim3(1024), 0, s, ctl, sl, vpend, V, ldA, n);
     switch (dt) {
-        case 0: hipLaunchKernelGGL(flush_translation<0>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, (const Ctrl *)ctl, sl, (const double *)vpend, b); break;
-        case 1: hipLaunchKernelGGL(flush_translation<1>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, (const Ctrl *)ctl, sl, (const double *)vpend, b); break;
-        default: hipLaunchKernelGGL(flush_translation<2>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, (const Ctrl *)ctl, sl, (const double *)vpend, b); break;
+        case 0: hipLaunchKernelGGL(rhs_exact<0>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, ctl, sl, bref, wsum, vpend, V, ldV, out); break;
+        case 1: hipLaunchKernelGGL(rhs_exact<1>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, ctl, sl, bref, wsum, vpend, V, ldV, out); break;
+        default: hipLaunchKernelGGL(rhs_exact<2>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, ctl, sl, bref, wsum, vpend, V, ldV, out); break;
     }
-    hipLaunchKernelGGL(ctl_clear_vpend, dim3(1), dim3(64), 0, s, ctl, sl);
+    return hipPeekAtLastError();
+}
+
+template <int DT>
+static void launch_cert(CertArgs a, hipStream_t s) {
+    using Acc = typename Store<DT>::Acc;
+    constexpr int VEC = Store<DT>::VEC;
+    const int tiles = (int)((a.ldA + 256 * VEC - 1) / (256 * VEC));
+    hipLaunchKernelGGL(cert_dot<DT>, dim3(a.Gs), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(cert_axpy<DT>, dim3(a.bands, tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(cert_reduce, dim3(a.R), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(cert_decide<Acc>, dim3(1), dim3(1024), 0, s, a);
+}
+
+hipError_t aux_certify(int dt, CertArgs a, hipStream_t s) {
+    a.R = (int32_t)((a.n + 63) / 64);
+    a.Gs = (int32_t)((a.m + 3) / 4);
+    switch (dt) {
+        case 0: launch_cert<0>(a, s); break;
+        case 1: launch_cert<1>(a, s); break;
+        default: launch_cert<2>(a, s); break;
+    }
     return hipPeekAtLastError();
 }
 

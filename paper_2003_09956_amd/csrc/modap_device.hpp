@@ -14,6 +14,7 @@ enum : int32_t {
     ST_NUMERIC = 3,
     ST_LIMIT = 4,
     ST_BAD_ROW = 5,
+    ST_UNCERTIFIED = 6,   // the FP64 certificate cannot confirm eps: eps_abs lies below its rounding bound
 };
 
 // The iteration state after one feasibility check and its decision.
@@ -31,7 +32,9 @@ struct alignas(16) State {
     int32_t status;       // ST_*
     int32_t feasible;     // last check found x eps-feasible
     int32_t vpend_valid;  // a one-shot translation waits for the next sweep
-    int32_t pad;
+    int32_t certified;    // the stop was confirmed by the FP64 certificate
+    double bdrift;        // last certificate: max_i |b_i - exact b_i| it corrected
+    double pad;
 };
 
 // Device-resident control block of one context.  The state after the check
@@ -51,7 +54,7 @@ struct alignas(32) Totals {
     int64_t h;
     double dmax;
     double binf;
-    double pad;
+    double bdrift;      // certificate only: max_i |b_i - exact b_i| before the rebase
 };
 
 // Parameters of the decision taken after every check.
@@ -144,6 +147,11 @@ struct ReduceArgs {
     void *work;             // iteration mode: out [3 x ldA] Acc x, drift row due next, y
     const double *V;        // drift schedule [T x ldV] or null
     int64_t ldV;
+    double *wsum;           // iteration mode: [ldA] FP64 sum of the translations applied since the
+                            // last rebase of b (the exact data are bref + A wsum)
+    const double *vpend;    // [ldA] one-shot translation
+    int32_t has_v;          // the sweep was compiled with the translation (it applied the state's)
+    int32_t pad2;
 };
 
 struct StageArgs {
@@ -161,6 +169,36 @@ struct StageArgs {
     int64_t ldV;
     int64_t n, ldA;
     void *work;             // out [2 x ldA] Acc
+};
+
+// One system as the FP64 certificate of a stop sees it (certify.hpp).
+struct CertArgs {
+    const void *A;          // [m x ldA] storage type
+    int64_t ldA, m, n;
+    double *b;              // [m] working right-hand side (rebased)
+    double *bref;           // [m] right-hand side at zero translation (rebased)
+    const double *nu;       // [m] ||a_i||^2
+    double *x;              // [ldA] FP64 approximation
+    double *wsum;           // [ldA] translations applied since the last rebase (cleared)
+    const double *V;        // drift schedule [T x ldV] or null (working vectors after a step)
+    int64_t ldV;
+    void *work;             // [3 x ldA] working vectors of the next sweep
+    Ctrl *ctl;
+    int32_t sl;             // the committed state slot, read and rewritten in place
+    int32_t R;              // ceil(n / 64): parts of ||y||^2
+    double *wt;             // [m] r_i/||a_i||^2 for violated rows, else 0
+    int64_t *h_part;        // [dot workgroups]
+    double *dmax_part;      // [dot workgroups]
+    double *binf_part;      // [dot workgroups]
+    double *drift_part;     // [dot workgroups]
+    int32_t Gs;             // dot workgroups: ceil(m / 4)
+    int32_t bands;          // row bands of cert_axpy
+    int64_t rows_per_band;
+    double *part;           // [bands x ldA] FP64 partial y
+    double *y;              // [ldA] FP64 y of the certificate
+    double *ynp;            // [R]
+    Totals *tot;
+    Decide dp;
 };
 
 __host__ __device__ __forceinline__ int slot_of(int64_t j) { return (int)(j & 1); }
@@ -271,6 +309,7 @@ __device__ __forceinline__ State decide(const State &p, const Totals &t, double 
     if (p.status != ST_RUNNING) return s;
     s.sweeps = p.sweeps + 1;
     s.vpend_valid = 0;
+    s.certified = 0;
     s.dmax = t.dmax;
     s.binf = t.binf;
     s.h = t.h;

@@ -13,13 +13,16 @@
 // other requests it was served with.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <deque>
+#include <new>
 #include <string>
 #include <vector>
 
 #include "host_common.hpp"
+#include "internal.hpp"
 #include "modap.h"
 
 using namespace modap_host;
@@ -32,10 +35,15 @@ struct Req {
     int state = RQ_QUEUED;
     int64_t m = 0, n = 0, ldA = 0;
     double footprint = 0.0;
-    // submission (caller memory, read at admission)
-    const void *A = nullptr;
-    const double *b = nullptr, *x0 = nullptr, *V = nullptr;
-    int64_t T = 0, ldv = 0;
+    // submission: copies of the caller's inputs, made by modap_server_submit
+    // and released at admission -- host inputs in host memory, device inputs
+    // in device memory of the server (A row-major with lda = n, V with ldv = n)
+    std::vector<char> hA;
+    std::vector<double> hb, hx0, hV;
+    void *dA = nullptr;
+    double *db = nullptr, *dx0 = nullptr, *dV = nullptr;
+    bool has_x0 = false;
+    int64_t T = 0;
     int on_dev = 0;
     // live
     bool in_batch = false;
@@ -145,6 +153,18 @@ double elapsed_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// Release a request's copy of its submitted inputs.
+void release_inputs(Req &r) {
+    std::vector<char>().swap(r.hA);
+    std::vector<double>().swap(r.hb);
+    std::vector<double>().swap(r.hx0);
+    std::vector<double>().swap(r.hV);
+    free_dev(r.dA);
+    free_dev(r.db);
+    free_dev(r.dx0);
+    free_dev(r.dV);
+}
+
 void drop(modap_server *s, Req &r) {
     if (r.in_batch && r.bid >= 0) {
         (void)modap_batch_remove(s->batch, r.bid);
@@ -155,8 +175,6 @@ void drop(modap_server *s, Req &r) {
     r.ctx = nullptr;
     r.stream = nullptr;
     r.bid = -1;
-    r.A = nullptr;
-    r.b = r.x0 = r.V = nullptr;
     s->used -= r.footprint;
     --s->live;
 }
@@ -165,13 +183,18 @@ void drop(modap_server *s, Req &r) {
 // failure everything created here is released again.
 modap_status admit(modap_server *s, Req &r, double now) {
     modap_status st;
+    const int od = r.on_dev;
+    const void *A = od ? (const void *)r.dA : (const void *)r.hA.data();
+    const double *b = od ? r.db : r.hb.data();
+    const double *x0 = !r.has_x0 ? nullptr : od ? r.dx0 : r.hx0.data();
+    const double *V = r.T == 0 ? nullptr : od ? r.dV : r.hV.data();
     if (r.ldA <= batch_row_limit(s->dt)) {
         int64_t id = -1;
-        if ((st = modap_batch_add(s->batch, r.m, r.n, r.A, r.n, r.b, r.x0, r.on_dev, &id))) {
+        if ((st = modap_batch_add(s->batch, r.m, r.n, A, r.n, b, x0, od, &id))) {
             r.error = modap_batch_last_error(s->batch);
             return st;
         }
-        if (r.T > 0 && (st = modap_batch_set_drift(s->batch, id, r.T, r.V, r.ldv, r.on_dev))) {
+        if (r.T > 0 && (st = modap_batch_set_drift(s->batch, id, r.T, V, r.n, od))) {
             r.error = modap_batch_last_error(s->batch);
             (void)modap_batch_remove(s->batch, id);
             return st;
@@ -186,8 +209,8 @@ modap_status admit(modap_server *s, Req &r, double now) {
             return MODAP_E_DEVICE;
         }
         st = modap_create(s->device, r.stream, &r.ctx);
-        if (!st) st = modap_set_system(r.ctx, r.m, r.n, (modap_dtype)s->dt, r.A, r.n, r.b, r.x0, r.on_dev);
-        if (!st && r.T > 0) st = modap_set_drift(r.ctx, r.T, r.V, r.ldv, r.on_dev);
+        if (!st) st = modap_set_system(r.ctx, r.m, r.n, (modap_dtype)s->dt, A, r.n, b, x0, od);
+        if (!st && r.T > 0) st = modap_set_drift(r.ctx, r.T, V, r.n, od);
         if (st) {
             r.error = r.ctx ? modap_last_error(r.ctx) : "context creation failed";
             if (r.ctx) modap_destroy(r.ctx);
@@ -261,8 +284,10 @@ modap_status modap_server_create(int device, modap_dtype storage, double hbm_bud
 void modap_server_destroy(modap_server *s) {
     if (!s) return;
     DeviceGuard g(s->device);
-    for (Req &r : s->reqs)
+    for (Req &r : s->reqs) {
         if (r.state == RQ_LIVE) drop(s, r);
+        release_inputs(r);
+    }
     modap_batch_destroy(s->batch);
     for (Stage &t : s->stages) {
         (void)hipEventSynchronize(t.used);
@@ -287,13 +312,47 @@ modap_status modap_server_submit(modap_server *s, int64_t m, int64_t n, const vo
     r.ldA = padded(s->dt, n);
     r.footprint = footprint(s->dt, m, n, T);
     if (r.footprint > s->budget) return fail(s, MODAP_E_NOMEM, "the request alone exceeds the HBM budget");
-    r.A = A;
-    r.b = b;
-    r.x0 = x0;
+    // Copy the inputs now, so that the caller may release them when this call
+    // returns: host inputs into host memory, device inputs into device memory
+    // of the server (after the caller's writes to them, which must be done).
     r.T = T;
-    r.V = V;
-    r.ldv = ldv;
     r.on_dev = ptrs_on_device;
+    r.has_x0 = x0 != nullptr;
+    const size_t ab = (size_t)m * (size_t)n * s->es;
+    if (!ptrs_on_device) {
+        try {
+            r.hA.assign(reinterpret_cast<const char *>(A), reinterpret_cast<const char *>(A) + ab);
+            r.hb.assign(b, b + m);
+            if (x0) r.hx0.assign(x0, x0 + n);
+            if (T > 0) {
+                r.hV.resize((size_t)T * (size_t)n);
+                for (int64_t q = 0; q < T; ++q)
+                    std::copy(V + q * ldv, V + q * ldv + n, r.hV.begin() + (ptrdiff_t)(q * n));
+            }
+        } catch (const std::bad_alloc &) {
+            release_inputs(r);
+            return fail(s, MODAP_E_NOMEM, "no host memory to copy the request's inputs");
+        }
+    } else {
+        DeviceGuard g(s->device);
+        hipError_t e = hipMalloc(&r.dA, ab);
+        if (e == hipSuccess) e = hipMalloc(&r.db, sizeof(double) * (size_t)m);
+        if (e == hipSuccess && x0) e = hipMalloc(&r.dx0, sizeof(double) * (size_t)n);
+        if (e == hipSuccess && T > 0) e = hipMalloc(&r.dV, sizeof(double) * (size_t)T * (size_t)n);
+        if (e == hipSuccess) e = hipMemcpyAsync(r.dA, A, ab, hipMemcpyDeviceToDevice, s->copy_stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(r.db, b, sizeof(double) * (size_t)m, hipMemcpyDeviceToDevice, s->copy_stream);
+        if (e == hipSuccess && x0)
+            e = hipMemcpyAsync(r.dx0, x0, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s->copy_stream);
+        if (e == hipSuccess && T > 0)
+            e = hipMemcpy2DAsync(r.dV, sizeof(double) * (size_t)n, V, sizeof(double) * (size_t)ldv,
+                                 sizeof(double) * (size_t)n, (size_t)T, hipMemcpyDeviceToDevice, s->copy_stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->copy_stream);
+        if (e != hipSuccess) {
+            release_inputs(r);
+            return fail(s, e == hipErrorOutOfMemory ? MODAP_E_NOMEM : MODAP_E_DEVICE,
+                        std::string("copying the request's inputs: ") + hipGetErrorString(e));
+        }
+    }
     r.t_submit = now;
     *ticket = (int64_t)s->reqs.size();
     s->reqs.push_back(std::move(r));
@@ -365,8 +424,7 @@ modap_status modap_server_round(modap_server *s, double now, int64_t *outstandin
         if (s->max_live > 0 && s->live >= s->max_live) break;
         s->pending.pop_front();
         st = admit(s, r, now + elapsed_since(t0));
-        r.A = nullptr;  // the caller's memory is no longer read
-        r.b = r.x0 = r.V = nullptr;
+        release_inputs(r);  // the request's data now live in the batch or its context
         if (st) {
             r.state = RQ_FAILED;
             r.status = -(int32_t)st;
@@ -384,6 +442,20 @@ modap_status modap_server_round(modap_server *s, double now, int64_t *outstandin
     HIP_TRY(s, hipStreamSynchronize(s->batch_stream));
     for (Req &r : s->reqs)
         if (r.state == RQ_LIVE && !r.in_batch) HIP_TRY(s, hipStreamSynchronize(r.stream));
+    // Stops of batched requests get their FP64 certificate here (a request
+    // with a context of its own had it queued after its iterations).
+    if (s->params.certify && s->batch_live > 0) {
+        std::vector<int64_t> ids;
+        for (Req &r : s->reqs) {
+            if (r.state != RQ_LIVE || !r.in_batch) continue;
+            modap_stats q{};
+            if ((st = modap_batch_query(s->batch, r.bid, nullptr, nullptr, &q, 0)))
+                return fail(s, st, "query of a live request failed");
+            if (q.state == 1 && !q.certified) ids.push_back(r.bid);
+        }
+        if (!ids.empty() && (st = modap_batch_certify_ids(s->batch, &s->params, ids.data(), (int64_t)ids.size())))
+            return fail(s, st, modap_batch_last_error(s->batch));
+    }
     const double t_end = now + elapsed_since(t0);
     for (Req &r : s->reqs) {
         if (r.state != RQ_LIVE) continue;
