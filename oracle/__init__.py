@@ -39,11 +39,17 @@ _lib = None
 
 
 def lib():
+    """The compiled oracle.  MODAP_ORACLE_LIB may name another build of the same
+    source (the sanitizer test runs the pins against an ASan/UBSan build)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_LIB)
+        alt = os.environ.get("MODAP_ORACLE_LIB")
+        if alt:
+            L = C.CDLL(alt)
+        else:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            L = C.CDLL(_LIB)
         i64, dp, vp, ip = C.c_int64, C.POINTER(C.c_double), C.c_void_p, C.POINTER(C.c_int64)
         L.oracle_norms.argtypes = [i64, i64, C.c_int, vp, i64, dp]
         L.oracle_norms.restype = i64

@@ -12,6 +12,10 @@ Independent of the oracle's C code: used to pin it.
 * ``exact_sweep`` -- one sweep in exact rational arithmetic (fractions), for
   integer or dyadic inputs: residuals, h and y exactly; the distances squared
   exactly (the distances themselves need a square root).
+* ``exact_scale`` -- the rounding-error scale of each residual,
+  t_i = sum_j |a_ij x_j| + |b_i| (the quantity a forward error bound of the
+  dot product <a_i, x> - b_i is proportional to; Higham, Accuracy and
+  Stability of Numerical Algorithms, sect. 3.1), in exact rationals.
 """
 from __future__ import annotations
 
@@ -82,3 +86,11 @@ def exact_sweep(A, b, x):
             h += 1
             d2.append(ri * ri / nu)
     return r, h, y, d2
+
+
+def exact_scale(A, b, x):
+    """Exact t_i = sum_j |a_ij x_j| + |b_i| for every row (list of Fractions)."""
+    A = [[Fraction(v) for v in row] for row in np.asarray(A, dtype=np.float64).tolist()]
+    b = [Fraction(v) for v in np.asarray(b, dtype=np.float64).tolist()]
+    x = [Fraction(v) for v in np.asarray(x, dtype=np.float64).tolist()]
+    return [sum(abs(A[i][j] * x[j]) for j in range(len(x))) + abs(b[i]) for i in range(len(A))]

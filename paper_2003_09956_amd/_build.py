@@ -11,7 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libmodap.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["host.hip", "batch.hip", "server.hip", "sweep_f64.hip", "sweep_f32.hip", "sweep_bf16.hip"]
+SOURCES = ["host.hip", "batch.hip", "server.hip", "sweep_f64.hip", "sweep_f32.hip", "sweep_bf16.hip",
+           "validate.cpp"]
 ARCH = "gfx950"
 
 CFLAGS = [

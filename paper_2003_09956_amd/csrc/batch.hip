@@ -333,13 +333,9 @@ Decide decide_of(const modap_params *p, int track) {
 }
 
 modap_status check_params(modap_batch *c, const modap_params *p) {
-    if (!p) return fail(c, MODAP_E_INVAL, "params is NULL");
-    if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return fail(c, MODAP_E_INVAL, "lambda must be finite and > 0");
-    if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(c, MODAP_E_INVAL, "eps must be finite and > 0");
-    if (p->step != MODAP_STEP_FIXED && p->step != MODAP_STEP_AVG) return fail(c, MODAP_E_INVAL, "unknown step rule");
-    if (p->max_iters < 0) return fail(c, MODAP_E_INVAL, "max_iters must be >= 0");
-    if (p->profile < 0) return fail(c, MODAP_E_INVAL, "profile must be >= 0");
-    return MODAP_OK;
+    const char *msg = nullptr;
+    const modap_status st = modap_host::check_params(p, &msg);
+    return st ? fail(c, st, msg) : MODAP_OK;
 }
 
 hipEvent_t event_at(modap_batch *c, size_t i) {
@@ -640,7 +636,8 @@ modap_status modap_batch_add(modap_batch *c, int64_t m, int64_t n, const void *A
                              const double *x0, int on_dev, int64_t *id) {
     if (!c) return MODAP_E_INVAL;
     if (!id) return fail(c, MODAP_E_INVAL, "id is NULL");
-    if (m < 1 || n < 1 || lda < n || !A || !b) return fail(c, MODAP_E_INVAL, "bad sizes or NULL data");
+    const char *msg = nullptr;
+    if (check_system(m, n, lda, A, b, c->dt, &msg)) return fail(c, MODAP_E_INVAL, msg);
     const int64_t v = vec_elems(c->dt);
     const int64_t ldA = (n + v - 1) / v * v;
     if (ldA > max_row(c->dt))
@@ -741,11 +738,8 @@ modap_status modap_batch_set_drift(modap_batch *c, int64_t id, int64_t T, const 
     if (!c) return MODAP_E_INVAL;
     BSys *s = find_sys(c, id);
     if (!s) return fail(c, MODAP_E_INVAL, "unknown system id");
-    if (T < 0) return fail(c, MODAP_E_INVAL, "T < 0");
-    if (T > 0 && V && ldv < s->n) return fail(c, MODAP_E_INVAL, "ldv < n");
-    if (T > 0 && V && !on_dev)
-        for (int64_t r = 0; r < T; ++r)
-            if (!all_finite(V + r * ldv, s->n)) return fail(c, MODAP_E_INVAL, "drift has a non-finite entry");
+    const char *msg = nullptr;
+    if (modap_status cs = check_drift(T, V, ldv, s->n, !on_dev, &msg)) return fail(c, cs, msg);
     DeviceGuard g(c->device);
     const int sl = last_slot(c);
     if (s->V) {
@@ -773,16 +767,13 @@ modap_status modap_batch_update(modap_batch *c, int64_t id, int64_t k, const int
     if (!c) return MODAP_E_INVAL;
     BSys *s = find_sys(c, id);
     if (!s) return fail(c, MODAP_E_INVAL, "unknown system id");
+    const char *msg = nullptr;
     if (k < 0 || k > s->m) return fail(c, MODAP_E_INVAL, "k out of range");
     if (k > 0 && (!rows || !new_rows || !new_b)) return fail(c, MODAP_E_INVAL, "rows, new_rows and new_b are required");
     const size_t rbytes = (size_t)k * (size_t)s->n * c->es;
     if (k > 0 && !on_dev) {
-        std::unordered_set<int64_t> seen;
-        for (int64_t q = 0; q < k; ++q) {
-            if (rows[q] < 0 || rows[q] >= s->m) return fail(c, MODAP_E_INVAL, "row index out of range");
-            if (!seen.insert(rows[q]).second) return fail(c, MODAP_E_INVAL, "row indices must be distinct");
-            if (!std::isfinite(new_b[q])) return fail(c, MODAP_E_INVAL, "new_b has a non-finite entry");
-        }
+        if (modap_status cs = check_rows(k, rows, new_rows, new_b, s->m, &msg)) return fail(c, cs, msg);
+        if (modap_status cs = check_new_rows(c->dt, new_rows, k, s->n, &msg)) return fail(c, cs, msg);
     }
     if (v && !on_dev && !all_finite(v, s->n)) return fail(c, MODAP_E_INVAL, "translation has a non-finite entry");
     DeviceGuard g(c->device);

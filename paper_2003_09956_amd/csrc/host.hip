@@ -301,13 +301,9 @@ modap_status check_ctx(modap_ctx *c, bool need_system) {
 }
 
 modap_status check_params(modap_ctx *c, const modap_params *p) {
-    if (!p) return fail(c, MODAP_E_INVAL, "params is NULL");
-    if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return fail(c, MODAP_E_INVAL, "lambda must be finite and > 0");
-    if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(c, MODAP_E_INVAL, "eps must be finite and > 0");
-    if (p->step != MODAP_STEP_FIXED && p->step != MODAP_STEP_AVG) return fail(c, MODAP_E_INVAL, "unknown step rule");
-    if (p->max_iters < 0) return fail(c, MODAP_E_INVAL, "max_iters must be >= 0");
-    if (p->profile < 0) return fail(c, MODAP_E_INVAL, "profile must be >= 0");
-    return MODAP_OK;
+    const char *msg = nullptr;
+    const modap_status st = modap_host::check_params(p, &msg);
+    return st ? fail(c, st, msg) : MODAP_OK;
 }
 
 
@@ -845,11 +841,8 @@ modap_status modap_set_system(modap_ctx *c, int64_t m, int64_t n, modap_dtype st
                               const double *b, const double *x0, int on_dev) {
     modap_status st = check_ctx(c, false);
     if (st) return st;
-    if (m < 1 || n < 1) return fail(c, MODAP_E_INVAL, "m and n must be >= 1");
-    if (lda < n) return fail(c, MODAP_E_INVAL, "lda < n");
-    if (!A || !b) return fail(c, MODAP_E_INVAL, "A and b are required");
-    if (storage != MODAP_F64 && storage != MODAP_F32 && storage != MODAP_BF16)
-        return fail(c, MODAP_E_INVAL, "unknown storage type");
+    const char *msg = nullptr;
+    if ((st = check_system(m, n, lda, A, b, (int)storage, &msg))) return fail(c, st, msg);
     if (!on_dev) {
         if (!all_finite(b, m)) return fail(c, MODAP_E_INVAL, "b has a non-finite entry");
         if (x0 && !all_finite(x0, n)) return fail(c, MODAP_E_INVAL, "x0 has a non-finite entry");
@@ -973,37 +966,14 @@ modap_status modap_update_coeffs(modap_ctx *c, int64_t k, const int64_t *rows, c
                                  const double *new_b, const double *v, int on_dev) {
     modap_status st = check_ctx(c, true);
     if (st) return st;
+    const char *msg = nullptr;
     if (k < 0 || k > c->m) return fail(c, MODAP_E_INVAL, "k out of range");
     if (k > 0 && (!rows || !new_rows || !new_b)) return fail(c, MODAP_E_INVAL, "rows, new_rows and new_b are required");
     DeviceGuard g(c->device);
     const size_t rbytes = (size_t)k * (size_t)c->n * c->es;
     if (k > 0 && !on_dev) {
-        std::unordered_set<int64_t> seen;
-        for (int64_t q = 0; q < k; ++q) {
-            if (rows[q] < 0 || rows[q] >= c->m) return fail(c, MODAP_E_INVAL, "row index out of range");
-            if (!seen.insert(rows[q]).second) return fail(c, MODAP_E_INVAL, "row indices must be distinct");
-            if (!std::isfinite(new_b[q])) return fail(c, MODAP_E_INVAL, "new_b has a non-finite entry");
-        }
-        for (int64_t q = 0; q < k; ++q) {
-            double s2 = 0.0;
-            for (int64_t j = 0; j < c->n; ++j) {
-                const size_t idx = (size_t)(q * c->n + j);
-                double val;
-                if (c->dt == 0) {
-                    val = reinterpret_cast<const double *>(new_rows)[idx];
-                } else if (c->dt == 1) {
-                    val = reinterpret_cast<const float *>(new_rows)[idx];
-                } else {
-                    uint32_t u = ((uint32_t)reinterpret_cast<const uint16_t *>(new_rows)[idx]) << 16;
-                    float f;
-                    std::memcpy(&f, &u, sizeof f);
-                    val = f;
-                }
-                if (!std::isfinite(val)) return fail(c, MODAP_E_ZERO_ROW, "replacement row has a non-finite entry");
-                s2 += val * val;
-            }
-            if (!(s2 > 0.0)) return fail(c, MODAP_E_ZERO_ROW, "replacement row is zero");
-        }
+        if ((st = check_rows(k, rows, new_rows, new_b, c->m, &msg))) return fail(c, st, msg);
+        if ((st = check_new_rows(c->dt, new_rows, k, c->n, &msg))) return fail(c, st, msg);
     }
     if (v && !on_dev && !all_finite(v, c->n)) return fail(c, MODAP_E_INVAL, "translation has a non-finite entry");
     const int64_t *d_rows = rows;
@@ -1040,12 +1010,8 @@ modap_status modap_update_coeffs(modap_ctx *c, int64_t k, const int64_t *rows, c
 modap_status modap_set_drift(modap_ctx *c, int64_t T, const double *V, int64_t ldv, int on_dev) {
     modap_status st = check_ctx(c, true);
     if (st) return st;
-    if (T < 0) return fail(c, MODAP_E_INVAL, "T < 0");
-    if (T > 0 && V && ldv < c->n) return fail(c, MODAP_E_INVAL, "ldv < n");
-    if (T > 0 && V && !on_dev) {
-        for (int64_t s = 0; s < T; ++s)
-            if (!all_finite(V + s * ldv, c->n)) return fail(c, MODAP_E_INVAL, "drift has a non-finite entry");
-    }
+    const char *msg = nullptr;
+    if ((st = check_drift(T, V, ldv, c->n, !on_dev, &msg))) return fail(c, st, msg);
     DeviceGuard g(c->device);
     const int sl = last_slot(c);
     if (c->V) {

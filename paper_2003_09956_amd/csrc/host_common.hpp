@@ -9,6 +9,7 @@
 #include <string>
 
 #include "modap.h"
+#include "validate.hpp"
 
 namespace modap_host {
 
@@ -47,12 +48,6 @@ template <typename P>
 void free_dev(P *&p) {
     if (p) (void)hipFree((void *)p);
     p = nullptr;
-}
-
-inline bool all_finite(const double *p, int64_t count) {
-    for (int64_t i = 0; i < count; ++i)
-        if (!std::isfinite(p[i])) return false;
-    return true;
 }
 
 }  // namespace modap_host

@@ -104,17 +104,6 @@ int64_t padded(int dt, int64_t n) {
 // Rows the batched sweep covers (64 lanes x 16-byte vectors x 8 chunks).
 int64_t batch_row_limit(int dt) { return 64 * (int64_t)vec_elems(dt) * 8; }
 
-// Device bytes a request holds while live: A, b, ||a||^2, r, the FP64
-// vectors (x, y, translation, two evaluation vectors), the working vectors,
-// the y partials of one sweep (about one row of Acc per row band) and the
-// drift schedule.
-double footprint(int dt, int64_t m, int64_t n, int64_t T) {
-    const double ldA = (double)padded(dt, n);
-    const double acc = (double)acc_size(dt);
-    return (double)m * ldA * (double)elem_size(dt) + 24.0 * (double)m + 5.0 * 8.0 * ldA + 6.0 * acc * ldA +
-           acc * ldA * (double)((m + 63) / 64) + 8.0 * ldA * (double)T + 65536.0;
-}
-
 // A staging buffer of at least `bytes` whose last update has run, from the
 // server's pool (grown when none is free).
 modap_status take_stage(modap_server *s, size_t bytes, Stage **out) {
@@ -246,9 +235,8 @@ modap_status modap_server_create(int device, modap_dtype storage, double hbm_bud
     if (!out) return MODAP_E_INVAL;
     *out = nullptr;
     if (!p || !(hbm_budget_bytes > 0.0) || iters_per_round < 1) return MODAP_E_INVAL;
-    if (!(p->lambda > 0.0) || !std::isfinite(p->lambda) || !(p->eps > 0.0) || !std::isfinite(p->eps) ||
-        (p->step != MODAP_STEP_FIXED && p->step != MODAP_STEP_AVG) || p->max_iters < 1)
-        return MODAP_E_INVAL;
+    const char *msg = nullptr;
+    if (check_params(p, &msg) || p->max_iters < 1) return MODAP_E_INVAL;
     modap_server *s = new (std::nothrow) modap_server();
     if (!s) return MODAP_E_NOMEM;
     s->device = device;
@@ -304,13 +292,13 @@ modap_status modap_server_submit(modap_server *s, int64_t m, int64_t n, const vo
                                  double now, int64_t *ticket) {
     if (!s) return MODAP_E_INVAL;
     if (!ticket) return fail(s, MODAP_E_INVAL, "ticket is NULL");
-    if (m < 1 || n < 1 || !A || !b) return fail(s, MODAP_E_INVAL, "bad sizes or NULL data");
-    if (T < 0 || (T > 0 && (!V || ldv < n))) return fail(s, MODAP_E_INVAL, "bad drift schedule");
+    const char *msg = nullptr;
+    if (modap_status cs = check_request(m, n, A, b, T, V, ldv, &msg)) return fail(s, cs, msg);
     Req r;
     r.m = m;
     r.n = n;
     r.ldA = padded(s->dt, n);
-    r.footprint = footprint(s->dt, m, n, T);
+    r.footprint = request_footprint(s->dt, m, n, T);
     if (r.footprint > s->budget) return fail(s, MODAP_E_NOMEM, "the request alone exceeds the HBM budget");
     // Copy the inputs now, so that the caller may release them when this call
     // returns: host inputs into host memory, device inputs into device memory
@@ -420,8 +408,7 @@ modap_status modap_server_round(modap_server *s, double now, int64_t *outstandin
     // admission in arrival order while the footprint fits
     while (!s->pending.empty()) {
         Req &r = s->reqs[(size_t)s->pending.front()];
-        if (s->used + r.footprint > s->budget) break;
-        if (s->max_live > 0 && s->live >= s->max_live) break;
+        if (!admissible(s->used, r.footprint, s->budget, s->live, s->max_live)) break;
         s->pending.pop_front();
         st = admit(s, r, now + elapsed_since(t0));
         release_inputs(r);  // the request's data now live in the batch or its context

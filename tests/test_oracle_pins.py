@@ -126,6 +126,43 @@ def test_sweep_equals_exact_rational_sweep(oracle_lib, seed):
     assert s.dmax == pytest.approx(dref, rel=4.5e-16)
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_rounding_scale_equals_exact_rational_scale(oracle_lib, seed):
+    """The rounding-error scale t_i = sum_j |a_ij x_j| + |b_i| that every GPU
+    tolerance is measured on, against its definition in exact rationals.
+    Dyadic inputs of mixed signs (k/8, b_i of both signs) make every term and
+    partial sum exact in FP64, so t must match exactly: a dropped |b_i|, a
+    signed instead of an absolute product or a missing term would not."""
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(1, 7))
+    m = int(rng.integers(2, 12))
+    A = rng.integers(-16, 17, size=(m, n)) / 8.0
+    A[np.all(A == 0, axis=1), 0] = -1.0
+    x = rng.integers(-40, 41, size=n) / 8.0
+    b = rng.integers(-30, 31, size=m) / 8.0
+    b[0] = -abs(b[0]) - 0.5                 # at least one negative right-hand side
+    s = oracle_lib.sweep(A, "f64", b, x)
+    t = brute.exact_scale(A, b, x)
+    np.testing.assert_array_equal(s.t, np.array([float(v) for v in t]))
+    # t bounds the residual (triangle inequality), with equality only when all
+    # terms of row i have one sign
+    assert np.all(np.abs(s.r) <= s.t)
+
+
+def test_rounding_scale_of_stored_rows(oracle_lib):
+    """t is taken on the stored (widened) rows: for BF16 storage the scale of
+    a row whose entries were rounded is that of the rounded entries."""
+    A64 = np.array([[1.0 + 2.0 ** -9, -3.0], [0.5, 0.25]])   # 1 + 2^-9 is not a BF16 value
+    Ab = W.encode(A64, "bf16")
+    x = np.array([2.0, -1.0])
+    b = np.array([-1.0, 0.75])
+    s = oracle_lib.sweep(Ab, "bf16", b, x)
+    Aw = W.stored_to_f64(Ab, "bf16")
+    assert Aw[0, 0] != A64[0, 0]
+    t = brute.exact_scale(Aw, b, x)
+    np.testing.assert_array_equal(s.t, np.array([float(v) for v in t]))
+
+
 def test_storage_widening_is_exact(oracle_lib):
     """BF16 is the top half of a binary32: the oracle's widening agrees with an
     independent bit-level widening, so the same stored bytes give the same sweep."""
