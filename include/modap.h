@@ -445,6 +445,26 @@ modap_status modap_server_totals(modap_server *server, double *hbm_bytes, int64_
 /* Message describing the last failing call on the server. */
 const char *modap_server_last_error(modap_server *server);
 
+/* One sweep with no allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid it): the pure sweep of modap_eval_sweep on a system given in
+ * device memory, with no context.  A is [m x lda] device memory in `storage`
+ * with lda >= n and lda a multiple of 16 bytes, columns [n, lda) zero; b [m],
+ * x [n] and the outputs y [n] (required), r [m], *h and *max_viol (each may
+ * be NULL) are device memory of `device`.  The work is queued on hip_stream
+ * (NULL: the device's default stream) and nothing waits for it.  Every
+ * intermediate lives in a 32 MiB device array of the library, one per GPU,
+ * held until the process ends: calls on one GPU share it, so calls that
+ * overlap on one GPU (on different streams) race.  Rows must be non-zero
+ * (a zero row gives NaN, not an error).  It calls no allocator.
+ * Errors: E_INVAL (sizes, NULL, lda, storage, rows too long for the one-pass
+ * sweep, or a system whose norms, working vectors and partial sums exceed
+ * the 32 MiB -- e.g. above about 3.5 million rows, or FP32 rows above
+ * 16384 elements), E_DEVICE. */
+modap_status modap_eval_sweep_static(int device, void *hip_stream, int64_t m, int64_t n, modap_dtype storage,
+                                     const void *A, int64_t lda, const double *b, const double *x, double *r,
+                                     double *y, int64_t *h, double *max_viol);
+
 /* Message for a status code (static storage). */
 const char *modap_strerror(modap_status status);
 

@@ -38,7 +38,8 @@ EXPORTS = ["modap_create", "modap_destroy", "modap_set_system", "modap_set_x", "
            "modap_batch_query", "modap_batch_set_tile", "modap_batch_get_tile", "modap_batch_autotune",
            "modap_batch_last_error", "modap_server_create", "modap_server_destroy", "modap_server_submit",
            "modap_server_update", "modap_server_round", "modap_server_info", "modap_server_result",
-           "modap_server_totals", "modap_server_last_error", "modap_server_set_max_live"]
+           "modap_server_totals", "modap_server_last_error", "modap_server_set_max_live",
+           "modap_eval_sweep_static"]
 
 
 class Params(C.Structure):
@@ -162,6 +163,7 @@ def lib():
         L.modap_server_last_error.argtypes = [vp]
         L.modap_server_last_error.restype = C.c_char_p
         L.modap_server_set_max_live.argtypes = [vp, i64]
+        L.modap_eval_sweep_static.argtypes = [i32, vp, i64, i64, i32, vp, i64, dp, dp, dp, dp, dp, dp]
         for name in EXPORTS:
             if name not in ("modap_destroy", "modap_strerror", "modap_last_error", "modap_batch_destroy",
                             "modap_batch_last_error", "modap_server_destroy", "modap_server_last_error"):
@@ -176,6 +178,34 @@ def params(lam=1.0, eps=1e-6, eps_relative=True, step=STEP_FIXED, max_iters=1000
     certify: confirm every stop at eps-feasibility with the library's FP64 certificate."""
     return Params(float(lam), float(eps), int(bool(eps_relative)), int(step), int(max_iters),
                   int(profile), int(bool(track)), int(bool(certify)), 0)
+
+
+def eval_sweep_static(A, b, x, y, dtype="f32", r=None, h=None, max_viol=None, lda=None, device=0, stream=None):
+    """modap_eval_sweep_static: one sweep with no allocation.  Every array is a
+    torch tensor on `device` (A [m x lda] zero-padded, b [m], x [n], outputs y [n]
+    and optionally r [m], h (int64 [1]) and max_viol (float64 [1])); the work is
+    queued on `stream` (default: torch's current stream) and not waited for."""
+    code = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    m = int(A.shape[0])
+    n = int(x.shape[0])
+    lda = int(A.shape[1]) if lda is None else int(lda)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream(device).cuda_stream
+    g = _Args(device)
+    pa = g.ptr(A, _NP_STORE[code], m * lda)
+    pb = g.ptr(b, np.float64, m)
+    px = g.ptr(x, np.float64, n)
+    py = g.ptr(y, np.float64, n)
+    pr = g.ptr(r, np.float64, m)
+    ph = g.ptr(h, np.int64, 1)
+    pd = g.ptr(max_viol, np.float64, 1)
+    if g.on_dev != 1:
+        raise ValueError("eval_sweep_static takes device tensors only")
+    st = lib().modap_eval_sweep_static(int(device), C.c_void_p(int(stream)) if stream else None, m, n, code, pa, lda,
+                                       pb, px, pr, py, ph, pd)
+    if st != OK:
+        raise ModapError(st, lib().modap_strerror(st).decode())
 
 
 def _is_torch(a):

@@ -258,6 +258,26 @@ __global__ __launch_bounds__(256) void prime_work(const StageArgs a) {
     }
 }
 
+// Working vectors of a stateless sweep at x: x in the accumulation type, no
+// translation, no previous direction (zero-padded to ldA).
+template <typename Acc>
+__global__ __launch_bounds__(256) void stage_point(const double *x, int64_t n, int64_t ldA, void *work) {
+    Acc *w = reinterpret_cast<Acc *>(work);
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ldA; j += (int64_t)gridDim.x * blockDim.x) {
+        w[j] = j < n ? (Acc)x[j] : (Acc)0;
+        w[ldA + j] = (Acc)0;
+        w[2 * ldA + j] = (Acc)0;
+    }
+}
+
+// The totals of a reduction to caller memory (either pointer may be null).
+__global__ void copy_totals(const Totals *t, int64_t *h, double *dmax) {
+    if (threadIdx.x != 0) return;
+    const Totals v = *t;
+    if (h) *h = v.h;
+    if (dmax) *dmax = v.dmax;
+}
+
 // The control kernels below run between calls as a single thread (or a
 // single workgroup) on the committed state in slot `sl`.
 

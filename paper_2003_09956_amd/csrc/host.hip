@@ -28,6 +28,7 @@
 #include "aux_launch.hpp"
 #include "certify.hpp"
 #include "host_common.hpp"
+#include "internal.hpp"
 #include "modap.h"
 #include "sweep_split.hpp"
 #include "modap_device.hpp"
@@ -1373,6 +1374,83 @@ hipError_t aux_rhs_exact(int dt, const void *A, int64_t ldA, int64_t m, int64_t 
         case 1: hipLaunchKernelGGL(rhs_exact<1>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, ctl, sl, bref, wsum, vpend, V, ldV, out); break;
         default: hipLaunchKernelGGL(rhs_exact<2>, dim3(nb), dim3(256), 0, s, A, ldA, m, n, ctl, sl, bref, wsum, vpend, V, ldV, out); break;
     }
+    return hipPeekAtLastError();
+}
+
+bool static_sweep_plan(int dt, int64_t ldA, int64_t m, int64_t n, int cu_count, StaticPlan *out) {
+    modap_tile t{};
+    if (!choose_shape(dt, ldA, &t) || t.kind != 0) return false;
+    const SweepKernel *k = find_kernel(dt, t.block, t.lanes_per_row, t.chunks, t.rows_per_step, t.depth, false);
+    if (!k) return false;
+    // the row mapping of configure() for a band of rows per workgroup
+    const int per_step = (t.block / t.lanes_per_row) * t.rows_per_step;
+    int grid = std::max(1, cu_count);
+    int64_t rpb = (m + grid - 1) / grid;
+    rpb = ((rpb + per_step - 1) / per_step) * per_step;
+    grid = (int)((m + rpb - 1) / rpb);
+    out->k = k;
+    out->grid = grid;
+    out->R = (int)((n + 63) / 64);
+    out->cov = coverage(dt, t.lanes_per_row, t.chunks);
+    out->rows_per_block = rpb;
+    out->block_stride = rpb;
+    out->step_stride = per_step;
+    return true;
+}
+
+hipError_t static_sweep_launch(int dt, const StaticPlan &plan, const SweepScratch &s, const void *A, int64_t ldA,
+                               int64_t m, int64_t n, const double *b, const double *x, double *r, double *y,
+                               int64_t *h, double *max_viol, hipStream_t stream) {
+    hipLaunchKernelGGL(ctl_init, dim3(1), dim3(64), 0, stream, s.ctl);
+    hipError_t e = aux_row_norms(dt, A, ldA, m, n, s.nu, s.bad, stream);
+    if (e != hipSuccess) return e;
+    const int sg = (int)std::min<int64_t>(1024, (ldA + 255) / 256);
+    if (dt == 0)
+        hipLaunchKernelGGL(stage_point<double>, dim3(sg), dim3(256), 0, stream, x, n, ldA, s.work);
+    else
+        hipLaunchKernelGGL(stage_point<float>, dim3(sg), dim3(256), 0, stream, x, n, ldA, s.work);
+    SweepArgs a{};
+    a.A = A;
+    a.ldA = ldA;
+    a.m = m;
+    a.n = n;
+    a.b_in = b;
+    a.b_out = nullptr;
+    a.nu = s.nu;
+    a.work = s.work;
+    a.pd.ctl = s.ctl;
+    a.pd.j = 1;          // runs under the fresh state in slot 0
+    a.pd.decide = 0;
+    a.check_status = 0;
+    a.r_out = r;
+    a.part = s.part;
+    a.ldPart = plan.cov;
+    a.h_part = s.h_part;
+    a.dmax_part = s.dmax_part;
+    a.binf_part = s.binf_part;
+    a.rows_per_block = plan.rows_per_block;
+    a.block_stride = plan.block_stride;
+    a.step_stride = plan.step_stride;
+    if ((e = plan.k->launch(a, plan.grid, stream, nullptr, nullptr)) != hipSuccess) return e;
+    ReduceArgs ra{};
+    ra.part = s.part;
+    ra.ldPart = plan.cov;
+    ra.G = plan.grid;
+    ra.acc_f64 = dt == 0;
+    ra.Gs = plan.grid;
+    ra.n = n;
+    ra.ldA = ldA;
+    ra.y = y;
+    ra.h_part = s.h_part;
+    ra.dmax_part = s.dmax_part;
+    ra.binf_part = s.binf_part;
+    ra.tot = s.tot;
+    ra.ynp = s.ynp;
+    if (dt == 0)
+        hipLaunchKernelGGL(reduce_y<double>, dim3(plan.R), dim3(kReduceThreads), 0, stream, ra);
+    else
+        hipLaunchKernelGGL(reduce_y<float>, dim3(plan.R), dim3(kReduceThreads), 0, stream, ra);
+    hipLaunchKernelGGL(copy_totals, dim3(1), dim3(64), 0, stream, (const Totals *)s.tot, h, max_viol);
     return hipPeekAtLastError();
 }
 
