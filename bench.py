@@ -7,16 +7,14 @@ and the translation of the system by that iteration's drift vector, b <- b + A v
 -- then the fixed-order reduction of y and the ModAP step x <- x - lambda
 y/||y||):
 
-  default: FP32 non-stationary Gaussian system, n = 8192, m = 16384, rows
-  a_i ~ N(0,1) normalised and stored FP32; hidden point z ~ U(-1,1)^n,
-  b = A z + U(0,1); drift v ~ N(0, 1e-2^2)^n per iteration; x0 = 0; lambda = 1;
-  eps = 1e-6 * ||b||_inf.
-  --workload bf16-16384x65536: the same construction at n = 16384, m = 65536
-  with A stored BF16 (2 GiB), drift |v| = 1e-4 per iteration; it also chases
-  the system from x0 = 0 at drift norms 1e-5, 1e-4 and 1e-3 per iteration,
-  with the BF16 rows and with the FP64 rows they were rounded from, and
-  reports both forms' time-to-feasible and the violation of the BF16 results
-  on the FP64 system.
+  default: the BF16-stored Gaussian system n = 16384, m = 65536 (2 GiB of A):
+  rows a_i ~ N(0,1) normalised in FP64 and rounded to BF16, hidden point
+  z ~ U(-1,1)^n, b = A z + U(0,1) from the stored rows in FP64, generated on the
+  device with a seeded generator; drift |v| = 1e-4 per iteration; lambda = 1;
+  eps = 1e-6 * ||b||_inf.  FP32 accumulation, FP64 norms, stop test and step.
+  The same line carries the FP32 system n = 8192, m = 16384 (drift N(0,1e-2^2)
+  per coordinate per iteration) as a second object, `fp32_n8192_m16384`.
+  --workload f32-8192x16384 / f64-4096x32768: one of those systems alone.
 
 The timed loop runs in tracking mode (an eps-feasible check takes no step but
 the system keeps moving), so every timed step reads all of A.  The sweep runs
@@ -24,14 +22,17 @@ in the library's built-in launch shape unless --autotune or --tile is given.
 
 Printed JSON line: `value` is the whole-job algorithmic HBM throughput of the
 timed steps, m*n*sizeof(A) + 24*m bytes per step (A, b read and written,
-||a_i||^2), divided by wall time; `roofline` is the same byte count over the
-sweep kernel's average duration (HIP events recorded by the dispatches of every
-tenth timed iteration, on the library's stream); time-to-feasible p50/p99 comes
-from solves of the FP64 box-plus-sum system (n=256, m=513, 20 seeds) and of the
-default FP32 system from x0 = 0 under 10 drift sequences (at most 3000
-iterations each; a chase not ended by then counts as slower than every ended
-one); `cpu_baseline` times the CPU oracle on a
-bounded number of iterations of the same system on one core, and
+||a_i||^2), divided by wall time, inputs resident in HBM; `roofline` is the
+same byte count over the sweep kernel's average duration (HIP events recorded
+by the dispatches of every timed iteration when --steps <= 50, else of every
+tenth, on the library's stream).  Time-to-feasible p50/p99 (every stop
+certified by the library's FP64 certificate) comes from solves of the FP64
+box-plus-sum system (n=256, m=513, 20 seeds), of the FP32 system from x0 = 0
+under 10 drift sequences (at most 3000 iterations each; a chase not ended by
+then counts as slower than every ended one), and of the BF16 system and of
+the FP64 system its rows were rounded from, side by side, under the same 3
+drift sequences of norm 1e-4 per iteration.  `cpu_baseline` times the CPU
+oracle on a bounded number of iterations of the same system on one core, and
 `cpu_baseline_all_cores` the same oracle run by one thread per available core
 (at most 16) at once.
 """
@@ -197,68 +198,6 @@ def time_to_feasible(P, W, seeds):
     return out, iters
 
 
-def drift_speed_sweep(P, W, torch, sys16, seed):
-    """The BF16-stored system chased from x0 = 0 under a drift of norm |v| =
-    1e-5, 1e-4 and 1e-3 per iteration, and the FP64 system its rows were
-    rounded from chased under the same drift sequences: time-to-feasible of
-    both forms on the same GPU, and the violation that each BF16 result leaves
-    on the FP64 system (the error of the storage precision in the final point;
-    the FP64 path itself matches the oracle to 1e-12 per sweep).  ModAP with
-    lambda = 0.1, the step length that reaches eps on these systems in the
-    fewest iterations."""
-    import numpy as np
-    n, m = sys16.n, sys16.m
-    log("generating the FP64 system the BF16 rows were rounded from ...")
-    s64 = W.gaussian(n, m, sys16.meta["seed"], "f64")
-    dev = torch.device("cuda")
-    A64, b64 = torch.from_numpy(s64.A).to(dev), torch.from_numpy(s64.b).to(dev)
-    del s64
-    A16 = torch.from_numpy(sys16.A.view(np.int16)).to(dev)
-    b16 = torch.from_numpy(sys16.b).to(dev)
-    prm = P.params(lam=SPEED_LAMBDA, eps=1e-6, max_iters=SPEED_STEPS)
-    fin = lambda v: round(v, 3) if math.isfinite(v) else None
-    out = []
-    with P.Solver(0) as q16, P.Solver(0) as q64:
-        for k, speed in enumerate(DRIFT_SPEEDS):
-            runs = {"bf16": [], "f64": []}
-            viol, vrows, eps_abs = 0.0, 0, 0.0
-            for sd in range(SPEED_SEEDS):
-                g = torch.Generator(device="cuda")
-                g.manual_seed(seed * 1000 + k * 10 + sd)
-                V = torch.randn((SPEED_STEPS, n), generator=g, device=dev, dtype=torch.float64)
-                V *= speed / math.sqrt(n)
-                for name, q, A, b in (("bf16", q16, A16, b16), ("f64", q64, A64, b64)):
-                    q.set_system(A, b, dtype=name)
-                    q.set_drift(V)
-                    st, code = q.solve(prm, raise_on_stop=False)
-                    runs[name].append((code == 0, st.seconds * 1e3, int(st.iters), st.seconds * 1e3 / max(st.sweeps, 1)))
-                    log("drift", speed, sd, name, code, runs[name][-1])
-                    if name == "bf16":
-                        eps_abs = max(eps_abs, st.eps_abs)
-                # the BF16 result on the FP64 data as they stand at its final
-                # check (the translations of the steps it took)
-                x16, _, _ = q16.query()
-                steps = runs["bf16"][-1][2]
-                q64.set_system(A64, b64, dtype="f64")
-                if steps:
-                    q64.update_coeffs(translate=V[:steps].sum(dim=0).contiguous())
-                ev = q64.eval_sweep(torch.from_numpy(x16).to(dev), want_r=False)
-                viol, vrows = max(viol, float(ev.max_viol)), max(vrows, int(ev.h))
-                del V
-            row = {"v_norm": speed, "seeds": SPEED_SEEDS, "max_steps": SPEED_STEPS}
-            for name, rr in runs.items():
-                ms = [r[1] if r[0] else math.inf for r in rr]
-                row[name] = {"caught": sum(r[0] for r in rr),
-                             "p50_ms": fin(float(np.percentile(ms, 50, method="higher"))),
-                             "steps": [r[2] for r in rr],
-                             "ms_per_step": round(float(np.mean([r[3] for r in rr])), 4)}
-            row["bf16_result_on_fp64_system"] = {"max_viol": viol, "violated_rows": vrows, "eps_abs": eps_abs}
-            p16, p64 = row["bf16"]["p50_ms"], row["f64"]["p50_ms"]
-            row["p50_speedup_bf16_over_f64"] = round(p64 / p16, 2) if p16 and p64 else None
-            out.append(row)
-    return out
-
-
 def cpu_baseline(sys_, V, seconds_budget):
     """The CPU oracle, as it is, on the same system: iterations of translate +
     sweep + step, single thread, bounded to about `seconds_budget` seconds."""
@@ -319,8 +258,12 @@ def main():
     ap.add_argument("--no-ttf", action="store_true",
                     help="skip the time-to-feasible solves (catch-up workload: the bisection over rates)")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + sorted(MULTI), default="f32-8192x16384",
-                    help="system the timed steps run on (default: the FP32 n=8192 m=16384 system)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + sorted(MULTI), default="bf16-16384x65536",
+                    help="system the timed steps run on (default: the BF16 n=16384 m=65536 system, 2 GiB)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="single-system workloads: skip the second line of the FP32 n=8192 m=16384 system")
+    ap.add_argument("--drift-speeds", action="store_true",
+                    help="BF16 workload: chase at drift norms 1e-5, 1e-4 and 1e-3 (default: 1e-4 only)")
     ap.add_argument("--rate", type=float, default=5.0, help="serving: Poisson arrival rate per second")
     ap.add_argument("--horizon", type=float, default=10.0, help="serving: seconds of arrivals")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving: HBM budget of the server")
@@ -373,18 +316,63 @@ def main():
 
     K, WU = args.steps, args.warmup
     dt, n, m, sigma, desc = WORKLOADS[args.workload]
-    default_workload = args.workload == "f32-8192x16384"
     lam, eps = 1.0, 1e-6
     log(f"generating the {args.workload} system ...")
-    sys_ = W.gaussian(n, m, args.seed, dt)
+    sys_ = None
+    if dt == "bf16":
+        # built on the device (seeded; the host copy is made only for the CPU baseline)
+        A_d, b_d, _ = W.gaussian_device(n, m, seed=args.seed, dtype=dt)
+        A_in, b_in = A_d, b_d
+    else:
+        sys_ = W.gaussian(n, m, args.seed, dt)
+        A_in, b_in = sys_.A, sys_.b
     V = W.drift(n, K + WU, sigma=sigma, seed=args.seed)
-    bytes_per_step = m * n * ELEM_BYTES[dt] + 24 * m
+    res = timed_steps(P, torch, A_in, b_in, dt, V, K, WU, lam, eps, args)
+    line = step_line(args, dt, n, m, desc, res)
+    extra_fp32 = None
+    if dt != "f32" and not args.no_extra:
+        # the FP32 n = 8192, m = 16384 system of round numbers as a second line
+        log("generating the FP32 n=8192 m=16384 system ...")
+        s2 = W.gaussian(8192, 16384, args.seed, "f32")
+        V2 = W.drift(8192, K + WU, sigma=1e-2, seed=args.seed)
+        res2 = timed_steps(P, torch, s2.A, s2.b, "f32", V2, K, WU, lam, eps, args)
+        extra_fp32 = step_line(args, "f32", 8192, 16384, WORKLOADS["f32-8192x16384"][4], res2)
+        for key in ("metric", "unit", "n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline",
+                    "data"):
+            extra_fp32.pop(key, None)
+        line["fp32_n8192_m16384"] = extra_fp32
+    if not args.no_ttf:
+        ms, its = time_to_feasible(P, W, range(20))
+        line["time_to_feasible"] = {
+            "box_sum_f64_n256_m513": {"p50_ms": round(percentile(ms, 50), 3), "p99_ms": round(percentile(ms, 99), 3),
+                                      "seeds": 20, "steps_p50": percentile(its, 50)},
+        }
+        if dt == "f32" or extra_fp32 is not None:
+            s2 = sys_ if dt == "f32" else s2
+            line["time_to_feasible"]["gaussian_f32_n8192_m16384_drift"] = fp32_chase(P, W, s2, args.seed)
+        if dt == "bf16":
+            line["time_to_feasible"]["bf16_vs_f64_n16384_m65536"] = bf16_vs_f64_chase(
+                P, W, torch, n, m, args.seed, DRIFT_SPEEDS if args.drift_speeds else (1e-4,))
+    if not args.no_cpu_baseline:
+        if sys_ is None:
+            import numpy as np
+            Ah = A_d.view(torch.int16).cpu().numpy().view(np.uint16) if dt == "bf16" else A_d.cpu().numpy()
+            sys_ = W.System(Ah, b_d.cpu().numpy(), np.zeros(n), dt)
+        line.update(cpu_lines(args, sys_, V, res["bytes_per_step"], n, m, dt))
+    print(json.dumps(line), flush=True)
 
+
+def timed_steps(P, torch, A, b, dt, V, K, WU, lam, eps, args):
+    """K timed steps (after WU untimed ones) of one system in tracking mode.
+    Every timed iteration's kernels carry HIP events when K <= 50, else one
+    in PROFILE_EVERY."""
+    m, n = int(A.shape[0]), int(A.shape[1])
+    every = 1 if K <= 50 else PROFILE_EVERY
     with P.Solver(0) as s:
-        s.set_system(sys_.A, sys_.b, dtype=dt)      # first call: allocation and warm-up
+        s.set_system(A, b, dtype=dt)      # first call: allocation and warm-up
         torch.cuda.synchronize()
         u0 = time.perf_counter()
-        s.set_system(sys_.A, sys_.b, dtype=dt)      # host arrays: A, b over PCIe, then the row norms
+        s.set_system(A, b, dtype=dt)      # the upload (PCIe when A is a host array), then the row norms
         torch.cuda.synchronize()
         upload_s = time.perf_counter() - u0
         s.set_drift(V)
@@ -401,45 +389,32 @@ def main():
             log("tile (built-in)", tile)
         # the warm-up also profiles, as many iterations as the timed region
         # will, so that the profiling events exist before the clock starts
-        n_prof = (K + PROFILE_EVERY - 1) // PROFILE_EVERY
+        n_prof = (K + every - 1) // every
         s.iterate(WU, P.params(lam=lam, eps=eps, track=True, profile=max(1, WU // max(n_prof, 1))))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = s.iterate(K, P.params(lam=lam, eps=eps, track=True, profile=PROFILE_EVERY))
+        st = s.iterate(K, P.params(lam=lam, eps=eps, track=True, profile=every))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         if st.sweeps != K + WU or st.profiled != n_prof:
             raise RuntimeError(f"timed region ran {st.sweeps - WU} sweeps, expected {K}")
-        wall = t1 - t0
-        sweep_us = st.sweep_ms * 1e3 / st.profiled
-        reduce_us = st.reduce_ms * 1e3 / st.profiled
-        feasible_steps = int(st.sweeps - st.iters)
-        log(f"timed {K} steps in {wall * 1e3:.2f} ms; sweep {sweep_us:.1f} us, reduce {reduce_us:.1f} us")
+    wall = t1 - t0
+    sweep_us = st.sweep_ms * 1e3 / st.profiled
+    reduce_us = st.reduce_ms * 1e3 / st.profiled
+    log(f"{dt} n={n} m={m}: timed {K} steps in {wall * 1e3:.2f} ms; sweep {sweep_us:.1f} us, "
+        f"reduce {reduce_us:.1f} us ({st.profiled} profiled)")
+    return {"wall": wall, "sweep_us": sweep_us, "reduce_us": reduce_us, "profiled": int(st.profiled),
+            "tile": tile, "upload_s": upload_s, "host_bytes": int(A.nbytes if hasattr(A, "nbytes") else 0),
+            "feasible_steps": int(st.sweeps - st.iters), "bytes_per_step": m * n * ELEM_BYTES[dt] + 24 * m,
+            "on_host": not hasattr(A, "is_cuda")}
 
-        # time-to-feasible on the same moving system, from x0 = 0, over
-        # DRIFT_SEEDS drift sequences (whether and when the chase ends is
-        # decided by the random walk of the drift, so one sequence says little)
-        ttf_drift = None
-        if not args.no_ttf and default_workload:
-            runs = []
-            for sd in range(DRIFT_SEEDS):
-                s.set_system(sys_.A, sys_.b, dtype=dt)
-                s.set_drift(W.drift(n, DRIFT_STEPS, sigma=sigma, seed=args.seed + 1 + sd))
-                st2, code = s.solve(P.params(lam=lam, eps=eps, max_iters=DRIFT_STEPS), raise_on_stop=False)
-                runs.append((code == 0, st2.seconds * 1e3, int(st2.iters)))
-                log("ttf under drift", sd, runs[-1])
-            # a sequence not caught within DRIFT_STEPS counts as slower than any caught one
-            import numpy as np
-            ms = [r[1] if r[0] else math.inf for r in runs]
-            its = [r[2] if r[0] else math.inf for r in runs]
-            pct = lambda v, q: float(np.percentile(np.asarray(v), q, method="higher"))
-            fin = lambda v: round(v, 3) if math.isfinite(v) else None
-            ttf_drift = {"seeds": DRIFT_SEEDS, "caught": int(sum(r[0] for r in runs)), "max_steps": DRIFT_STEPS,
-                         "p50_ms": fin(pct(ms, 50)), "p99_ms": fin(pct(ms, 99)),
-                         "steps_p50": fin(pct(its, 50))}
 
-    value = bytes_per_step * K / wall / 1e9
-    achieved = bytes_per_step / (sweep_us * 1e-6) / 1e9
+def step_line(args, dt, n, m, desc, res):
+    K, WU = args.steps, args.warmup
+    tile, wall = res["tile"], res["wall"]
+    bps = res["bytes_per_step"]
+    value = bps * K / wall / 1e9
+    achieved = bps / (res["sweep_us"] * 1e-6) / 1e9
     kind = "sweep_split" if tile["kind"] == 1 else "sweep_wide"
     line = {
         "metric": METRIC,
@@ -453,48 +428,131 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": dt,
-        "data": "synthetic",
+        "data": "synthetic (seeded" + (", generated on the device)" if not res["on_host"] else ")"),
         "config": {"workload": desc, "n": n, "m": m, "storage": dt,
                    "accumulate": "f64" if dt == "f64" else "f32 dot, f64 scalars",
-                   "bytes_per_step": bytes_per_step, "tile": tile},
+                   "bytes_per_step": bps, "tile": tile},
         "pct_of_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "iterations_per_s": round(K / wall, 1),
-        "feasible_checks_in_timed_steps": feasible_steps,
-        "host_upload": {"ms": round(upload_s * 1e3, 3), "bytes": int(sys_.A.nbytes + sys_.b.nbytes),
-                        "pcie_inclusive_GBs": round(bytes_per_step * K / (wall + upload_s) / 1e9, 2)},
+        "feasible_checks_in_timed_steps": res["feasible_steps"],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(dt, n, m, tile) if tile["kind"] == 0 else None,
                      "kernel": f"{kind}<{DT_CODE[dt]},{tile['block']},{tile['lanes_per_row']},{tile['chunks']},"
                                f"{tile['rows_per_step']},{tile['depth']},true>",
-                     "avg_us": round(sweep_us, 3), "reduce_avg_us": round(reduce_us, 3)},
+                     "avg_us": round(res["sweep_us"], 3), "reduce_avg_us": round(res["reduce_us"], 3),
+                     "profiled_sweeps": res["profiled"]},
     }
-    if not args.no_ttf:
-        ms, its = time_to_feasible(P, W, range(20))
-        line["time_to_feasible"] = {
-            "box_sum_f64_n256_m513": {"p50_ms": round(percentile(ms, 50), 3), "p99_ms": round(percentile(ms, 99), 3),
-                                      "seeds": 20, "steps_p50": percentile(its, 50)},
-        }
-        if ttf_drift is not None:
-            line["time_to_feasible"]["gaussian_f32_n8192_m16384_drift"] = ttf_drift
-        if dt == "bf16":
-            line["drift_speeds"] = drift_speed_sweep(P, W, torch, sys_, args.seed)
-    if not args.no_cpu_baseline:
-        steps, secs = cpu_baseline(sys_, V, args.cpu_seconds)
-        line["cpu_baseline"] = {"value": round(bytes_per_step * steps / secs / 1e9, 4), "unit": "GB/s", "cores": 1,
-                                "kind": "oracle",
-                                "sample": f"{steps} iterations (translate, sweep, step) of the full n={n} m={m} "
-                                          f"{dt} system, {secs:.1f} s, single-threaded extended-precision oracle"}
-        # every core the process may use (at most 16, the host share of one GPU)
-        threads = max(1, min(16, len(os.sched_getaffinity(0))))
-        per = max(1, steps // 2)
-        secs_all = cpu_baseline_all_cores(sys_, V, per, threads)
-        line["cpu_baseline_all_cores"] = {
-            "value": round(bytes_per_step * per * threads / secs_all / 1e9, 4), "unit": "GB/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{threads} threads, each {per} iterations of the same system from its own copy of the "
-                      f"iterate, {secs_all:.1f} s wall"}
-    print(json.dumps(line), flush=True)
+    if res["on_host"]:
+        line["host_upload"] = {"ms": round(res["upload_s"] * 1e3, 3), "bytes": res["host_bytes"],
+                               "pcie_inclusive_GBs": round(bps * K / (wall + res["upload_s"]) / 1e9, 2)}
+    return line
+
+
+def fp32_chase(P, W, sys_, seed):
+    """Time-to-feasible of the FP32 system chased from x0 = 0 under DRIFT_SEEDS
+    drift sequences (whether and when a chase ends is decided by the random
+    walk of the drift, so one sequence says little); every stop certified in
+    FP64.  A sequence not caught within DRIFT_STEPS counts as slower than any
+    caught one."""
+    import numpy as np
+    n = sys_.n
+    runs = []
+    with P.Solver(0) as s:
+        for sd in range(DRIFT_SEEDS):
+            s.set_system(sys_.A, sys_.b, dtype="f32")
+            s.set_drift(W.drift(n, DRIFT_STEPS, sigma=1e-2, seed=seed + 1 + sd))
+            st2, code = s.solve(P.params(lam=1.0, eps=1e-6, max_iters=DRIFT_STEPS), raise_on_stop=False)
+            runs.append((code == 0 and st2.certified == 1, st2.seconds * 1e3, int(st2.iters), st2.b_drift,
+                         st2.eps_abs))
+            log("fp32 chase", sd, runs[-1])
+    ms = [r[1] if r[0] else math.inf for r in runs]
+    its = [r[2] if r[0] else math.inf for r in runs]
+    pct = lambda v, q: float(np.percentile(np.asarray(v), q, method="higher"))
+    fin = lambda v: round(v, 3) if math.isfinite(v) else None
+    return {"seeds": DRIFT_SEEDS, "caught": int(sum(r[0] for r in runs)), "max_steps": DRIFT_STEPS,
+            "certified": True, "p50_ms": fin(pct(ms, 50)), "p99_ms": fin(pct(ms, 99)),
+            "steps_p50": fin(pct(its, 50)),
+            "max_b_drift_over_eps_abs": round(max(r[3] / r[4] for r in runs if r[4] > 0), 4)}
+
+
+def bf16_vs_f64_chase(P, W, torch, n, m, seed, speeds):
+    """The BF16-stored system chased from x0 = 0 under drifts of norm |v| per
+    iteration, and the FP64 system its rows were rounded from (same random
+    numbers before rounding) chased under the same drift sequences on the
+    same GPU: p50/p99 time-to-feasible of both forms, every stop certified in
+    FP64; and the violation each BF16 result leaves on the FP64 system (the
+    error of the storage precision in the final point).  ModAP with
+    lambda = SPEED_LAMBDA, the step length that reaches eps on these systems
+    in the fewest iterations."""
+    import numpy as np
+    dev = torch.device("cuda")
+    log("generating the BF16 system and the FP64 system its rows were rounded from ...")
+    A16, b16, _ = W.gaussian_device(n, m, seed=seed, dtype="bf16")
+    A64, b64, _ = W.gaussian_device(n, m, seed=seed, dtype="f64")
+    prm = P.params(lam=SPEED_LAMBDA, eps=1e-6, max_iters=SPEED_STEPS)
+    fin = lambda v: round(v, 3) if math.isfinite(v) else None
+    pct = lambda v, q: float(np.percentile(np.asarray(v), q, method="higher"))
+    out = []
+    with P.Solver(0) as q16, P.Solver(0) as q64:
+        for k, speed in enumerate(speeds):
+            runs = {"bf16": [], "f64": []}
+            viol, vrows, eps_abs = 0.0, 0, 0.0
+            for sd in range(SPEED_SEEDS):
+                g = torch.Generator(device="cuda")
+                g.manual_seed(seed * 1000 + k * 10 + sd)
+                V = torch.randn((SPEED_STEPS, n), generator=g, device=dev, dtype=torch.float64)
+                V *= speed / math.sqrt(n)
+                for name, q, A, b in (("bf16", q16, A16, b16), ("f64", q64, A64, b64)):
+                    q.set_system(A, b, dtype=name)
+                    q.set_drift(V)
+                    st, code = q.solve(prm, raise_on_stop=False)
+                    runs[name].append((code == 0 and st.certified == 1, st.seconds * 1e3, int(st.iters),
+                                       st.seconds * 1e3 / max(st.sweeps, 1)))
+                    log("drift", speed, sd, name, code, runs[name][-1])
+                    if name == "bf16":
+                        eps_abs = max(eps_abs, st.eps_abs)
+                # the BF16 result on the FP64 data as they stand at its final
+                # check (the translations of the steps it took)
+                x16, _, _ = q16.query()
+                steps = runs["bf16"][-1][2]
+                q64.set_system(A64, b64, dtype="f64")
+                if steps:
+                    q64.update_coeffs(translate=V[:steps].sum(dim=0).contiguous())
+                ev = q64.eval_sweep(torch.from_numpy(x16).to(dev), want_r=False)
+                viol, vrows = max(viol, float(ev.max_viol)), max(vrows, int(ev.h))
+                del V
+            row = {"v_norm": speed, "seeds": SPEED_SEEDS, "max_steps": SPEED_STEPS, "lambda": SPEED_LAMBDA,
+                   "certified": True}
+            for name, rr in runs.items():
+                ms = [r[1] if r[0] else math.inf for r in rr]
+                row[name] = {"caught": sum(r[0] for r in rr), "p50_ms": fin(pct(ms, 50)), "p99_ms": fin(pct(ms, 99)),
+                             "steps": [r[2] for r in rr],
+                             "ms_per_step": round(float(np.mean([r[3] for r in rr])), 4)}
+            row["bf16_result_on_fp64_system"] = {"max_viol": viol, "violated_rows": vrows, "eps_abs": eps_abs}
+            p16, p64 = row["bf16"]["p50_ms"], row["f64"]["p50_ms"]
+            row["p50_speedup_bf16_over_f64"] = round(p64 / p16, 2) if p16 and p64 else None
+            out.append(row)
+    del A16, b16, A64, b64
+    return out if len(out) > 1 else out[0]
+
+
+def cpu_lines(args, sys_, V, bytes_per_step, n, m, dt):
+    steps, secs = cpu_baseline(sys_, V, args.cpu_seconds)
+    out = {"cpu_baseline": {"value": round(bytes_per_step * steps / secs / 1e9, 4), "unit": "GB/s", "cores": 1,
+                            "kind": "oracle",
+                            "sample": f"{steps} iterations (translate, sweep, step) of the full n={n} m={m} "
+                                      f"{dt} system, {secs:.1f} s, single-threaded extended-precision oracle"}}
+    # every core the process may use (at most 16, the host share of one GPU)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    per = max(1, steps // 2)
+    secs_all = cpu_baseline_all_cores(sys_, V, per, threads)
+    out["cpu_baseline_all_cores"] = {
+        "value": round(bytes_per_step * per * threads / secs_all / 1e9, 4), "unit": "GB/s", "cores": threads,
+        "kind": "oracle",
+        "sample": f"{threads} threads, each {per} iterations of the same system from its own copy of the "
+                  f"iterate, {secs_all:.1f} s wall"}
+    return out
 
 
 def bench_batch(args, P, W, torch):
