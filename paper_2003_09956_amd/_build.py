@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libmodap.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["host.hip", "batch.hip", "server.hip", "sweep_f64.hip", "sweep_f32.hip", "sweep_bf16.hip",
-           "validate.cpp", "noalloc.hip"]
+           "validate.cpp", "noalloc.hip", "resident.hip"]
 ARCH = "gfx950"
 
 CFLAGS = [

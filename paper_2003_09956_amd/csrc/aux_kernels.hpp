@@ -300,6 +300,8 @@ __global__ void ctl_init(Ctrl *c) {
     c->st[1] = s;
     c->step_limit = INT64_MAX;
     c->sched_len = 0;
+    c->barrier = 0;
+    c->fault = 0;
 }
 
 // A new approximation: counters restart, no step is pending.

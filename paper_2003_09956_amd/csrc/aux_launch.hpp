@@ -36,6 +36,12 @@ hipError_t aux_ctl_set_drift(Ctrl *c, int sl, int64_t T, hipStream_t s);
 hipError_t aux_rhs_exact(int dt, const void *A, int64_t ldA, int64_t m, int64_t n, const Ctrl *ctl, int sl,
                          const double *bref, const double *wsum, const double *vpend, const double *V, int64_t ldV,
                          double *out, hipStream_t s);
+struct ResidentArgs;
+// Cooperative launch of the resident iteration (resident.hpp) with `grid`
+// workgroups and `lds` bytes of dynamic LDS each.
+hipError_t aux_resident_launch(int dt, const ResidentArgs &a, int grid, size_t lds, hipStream_t s);
+// Dynamic LDS of a resident workgroup holding `rows` rows of ldR elements.
+size_t resident_lds_bytes(int dt, int rows, int ldR);
 // Queue the FP64 certificate of the stop in slot a.sl (see certify.hpp); R and Gs are filled in.
 hipError_t aux_certify(int dt, CertArgs a, hipStream_t s);
 

@@ -30,6 +30,7 @@
 #include "host_common.hpp"
 #include "internal.hpp"
 #include "modap.h"
+#include "resident.hpp"
 #include "sweep_split.hpp"
 #include "modap_device.hpp"
 #include "sweep_table.hpp"
@@ -92,6 +93,15 @@ struct modap_ctx {
     // staging for host-side update inputs
     void *stage = nullptr;
     size_t stage_bytes = 0;
+
+    // resident iteration of small systems (resident.hpp): one launch of many
+    // iterations on a few workgroups holding their rows in LDS
+    bool res_ok = false;
+    int res_grid = 0, res_rows = 0, res_ldR = 0;
+    size_t res_lds = 0;
+    void *res_part = nullptr;
+    int64_t *res_h = nullptr;
+    double *res_dmax = nullptr, *res_binf = nullptr;
 
     // FP64 certificate scratch (allocated at the first certificate of a system)
     double *cert_wt = nullptr, *cert_part = nullptr, *cert_y = nullptr, *cert_ynp = nullptr;
@@ -562,8 +572,12 @@ modap_status enqueue_settle(modap_ctx *c, const modap_params *p, int track) {
 }
 
 modap_status read_state(modap_ctx *c, State *out) {
+    uint32_t bf[2] = {0, 0};
     HIP_TRY(c, hipMemcpyAsync(out, &c->ctl->st[last_slot(c)], sizeof(State), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(bf, &c->ctl->barrier, sizeof bf, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (bf[1])
+        return fail(c, MODAP_E_DEVICE, "a resident launch gave up waiting at a grid barrier; the context's data are void");
     return MODAP_OK;
 }
 
@@ -626,8 +640,17 @@ void release_cert(modap_ctx *c) {
     c->cert_bands = 0;
 }
 
+void release_resident(modap_ctx *c) {
+    free_dev(c->res_part);
+    free_dev(c->res_h);
+    free_dev(c->res_dmax);
+    free_dev(c->res_binf);
+    c->res_ok = false;
+}
+
 void release_system(modap_ctx *c) {
     release_cert(c);
+    release_resident(c);
     free_dev(c->bref);
     free_dev(c->wsum);
     free_dev(c->claim);
@@ -652,6 +675,91 @@ void release_system(modap_ctx *c) {
 modap_status launch_scatter(modap_ctx *c, int64_t k, const int64_t *rows, const void *new_rows, const double *nb) {
     HIP_TRY(c, aux_scatter_rows(c->dt, c->A, c->ldA, c->m, c->n, k, rows, new_rows, nb, c->b, c->bref, c->nu,
                                 c->ctl, last_slot(c), c->vpend, c->V, c->ldA, c->wsum, c->stream));
+    return MODAP_OK;
+}
+
+// Resident iteration (resident.hpp): systems whose rows hold at most 512
+// elements and whose A, with rows padded to a multiple of 64 elements, fits
+// in the LDS of at most kResidentMaxGrid workgroups at kResidentBand bytes
+// each.  The grid is the larger of that minimum and one workgroup per
+// kResidentRows rows (fewer rows per workgroup shorten the sweep; more
+// workgroups lengthen the barrier).
+constexpr int64_t kResidentBand = 96 * 1024;
+constexpr int64_t kResidentRows = 32;
+constexpr int64_t kResidentTimeoutTicks = 100000000;   // one second of the 100 MHz constant clock
+
+modap_status plan_resident(modap_ctx *c) {
+    release_resident(c);
+    const int64_t ldR = (c->n + 63) / 64 * 64;
+    if (ldR > kResidentMaxCols) return MODAP_OK;
+    const int64_t row_bytes = ldR * (int64_t)c->es;
+    const int64_t gmin = (c->m * row_bytes + kResidentBand - 1) / kResidentBand;
+    if (gmin > kResidentMaxGrid) return MODAP_OK;
+    int64_t rows_target = kResidentRows;
+    if (const char *e = std::getenv("MODAP_RESIDENT_ROWS")) rows_target = std::max<int64_t>(4, std::atoll(e));
+    int64_t grid = std::min<int64_t>(kResidentMaxGrid, std::max(gmin, (c->m + rows_target - 1) / rows_target));
+    const int64_t rows = (c->m + grid - 1) / grid;
+    grid = (c->m + rows - 1) / rows;
+    const size_t lds = resident_lds_bytes(c->dt, (int)rows, (int)ldR);
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess ||
+        lds + 1024 > (size_t)max_lds)
+        return MODAP_OK;
+    const size_t acc = acc_size(c->dt);
+    HIP_TRY(c, hipMalloc(&c->res_part, 2 * (size_t)kResidentMaxGrid * (size_t)ldR * acc));
+    HIP_TRY(c, hipMalloc(&c->res_h, 2 * sizeof(int64_t) * (size_t)grid));
+    HIP_TRY(c, hipMalloc(&c->res_dmax, 2 * sizeof(double) * (size_t)grid));
+    HIP_TRY(c, hipMalloc(&c->res_binf, 2 * sizeof(double) * (size_t)grid));
+    c->res_grid = (int)grid;
+    c->res_rows = (int)rows;
+    c->res_ldR = (int)ldR;
+    c->res_lds = lds;
+    c->res_ok = true;
+    return MODAP_OK;
+}
+
+// The resident path runs unless the caller forced a tile of the two-kernel
+// sweep, asked for per-iteration kernel timings, or set MODAP_RESIDENT=0.
+bool use_resident(const modap_ctx *c, const modap_params *p) {
+    if (!c->res_ok || c->tile_forced || p->profile > 0) return false;
+    const char *e = std::getenv("MODAP_RESIDENT");
+    return !(e && e[0] == '0');
+}
+
+// Queue K resident iterations from the committed state (the launch settles
+// every check it makes, so no stage kernel follows).
+modap_status launch_resident(modap_ctx *c, const modap_params *p, int track, int64_t K, double *bytes) {
+    const bool hv = translation_possible(c);
+    HIP_TRY(c, hipMemsetAsync(&c->ctl->barrier, 0, 2 * sizeof(uint32_t), c->stream));
+    ResidentArgs r{};
+    r.A = c->A;
+    r.ldA = c->ldA;
+    r.m = c->m;
+    r.n = c->n;
+    r.ldR = c->res_ldR;
+    r.rows = c->res_rows;
+    r.b = c->b;
+    r.nu = c->nu;
+    r.x = c->x;
+    r.y = c->y;
+    r.wsum = c->wsum;
+    r.vpend = c->vpend;
+    r.V = c->V;
+    r.ldV = c->ldA;
+    r.work = c->work;
+    r.ctl = c->ctl;
+    r.j0 = c->jn;
+    r.K = K;
+    r.dp = decide_params(p, track);
+    r.part = c->res_part;
+    r.h_part = c->res_h;
+    r.dmax_part = c->res_dmax;
+    r.binf_part = c->res_binf;
+    r.timeout_ticks = kResidentTimeoutTicks;
+    if (const char *e = std::getenv("MODAP_RESIDENT_TIMEOUT_TICKS")) r.timeout_ticks = std::atoll(e);   // tests
+    HIP_TRY(c, aux_resident_launch(c->dt, r, c->res_grid, c->res_lds, c->stream));
+    c->jn += K;
+    *bytes += (double)K * sweep_bytes(c, hv);
     return MODAP_OK;
 }
 
@@ -943,6 +1051,10 @@ modap_status modap_set_system(modap_ctx *c, int64_t m, int64_t n, modap_dtype st
             return st;
         }
     }
+    if ((st = plan_resident(c))) {
+        release_system(c);
+        return st;
+    }
     c->loaded = true;
     c->err.clear();
     return MODAP_OK;
@@ -1060,14 +1172,23 @@ modap_status modap_iterate(modap_ctx *c, const modap_params *p, int64_t k, modap
     const auto t0 = std::chrono::steady_clock::now();
     hipLaunchKernelGGL(ctl_begin, dim3(1), dim3(64), 0, c->stream, c->ctl, last_slot(c), (int64_t)-1);
     LAUNCH_TRY(c, "ctl_begin launch");
-    if ((st = enqueue_prime(c, c->work, c->x))) return st;
     size_t ev = 0;
     double bytes = 0.0;
     const int track = p->track != 0;
-    if ((st = reserve_events(c, k, p->profile))) return st;
-    for (int64_t i = 0; i < k; ++i)
-        if ((st = enqueue_iteration(c, p, track, i, &ev, &bytes))) return st;
-    if (k > 0 && (st = enqueue_settle(c, p, track))) return st;
+    if (use_resident(c, p)) {
+        // one launch of many iterations (each launch settles its own checks)
+        for (int64_t done = 0; done < k;) {
+            const int64_t K = std::min<int64_t>(k - done, int64_t(1) << 20);
+            if ((st = launch_resident(c, p, track, K, &bytes))) return st;
+            done += K;
+        }
+    } else {
+        if ((st = enqueue_prime(c, c->work, c->x))) return st;
+        if ((st = reserve_events(c, k, p->profile))) return st;
+        for (int64_t i = 0; i < k; ++i)
+            if ((st = enqueue_iteration(c, p, track, i, &ev, &bytes))) return st;
+        if (k > 0 && (st = enqueue_settle(c, p, track))) return st;
+    }
     if (k > 0 && p->certify && (st = enqueue_certify(c, p))) return st;
     if (!out) return MODAP_OK;
     State kc;
@@ -1089,9 +1210,10 @@ modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) 
     const auto t0 = std::chrono::steady_clock::now();
     hipLaunchKernelGGL(ctl_begin, dim3(1), dim3(64), 0, c->stream, c->ctl, last_slot(c), (int64_t)p->max_iters);
     LAUNCH_TRY(c, "ctl_begin launch");
-    if ((st = enqueue_prime(c, c->work, c->x))) return st;
+    const bool resident = use_resident(c, p);
+    if (!resident && (st = enqueue_prime(c, c->work, c->x))) return st;
     const int64_t total = p->max_iters + 1;  // the last sweep checks the last step
-    if ((st = reserve_events(c, std::min<int64_t>(total, 4096), p->profile))) return st;
+    if (!resident && (st = reserve_events(c, std::min<int64_t>(total, 4096), p->profile))) return st;
     size_t ev = 0;
     double bytes = 0.0;
     auto observed = t0;
@@ -1099,18 +1221,25 @@ modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) 
     // Passes of queued iterations until the device stops; a stop at
     // eps-feasibility that the FP64 certificate does not confirm has taken a
     // step instead, and the next pass goes on from there.  The step limit is
-    // the device's, so a pass may queue more iterations than remain.
+    // the device's, so a pass may queue more iterations than remain.  The host
+    // reads the state of the chunk before the newest one, so the device never
+    // waits for it.
     for (;;) {
-        int64_t queued = 0, chunk = 1;
+        int64_t queued = 0, chunk = resident ? 16 : 1;
         int slot = 0, pending = -1;
         bool done = false;
         while (queued < total && !done) {
             const int64_t cnt = std::min(chunk, total - queued);
-            for (int64_t i = 0; i < cnt; ++i)
-                if ((st = enqueue_iteration(c, p, 0, queued + i, &ev, &bytes))) return st;
+            if (resident) {
+                if ((st = launch_resident(c, p, 0, cnt, &bytes))) return st;
+            } else {
+                for (int64_t i = 0; i < cnt; ++i)
+                    if ((st = enqueue_iteration(c, p, 0, queued + i, &ev, &bytes))) return st;
+            }
             queued += cnt;
             // the newest settled state: the check before the last queued sweep
-            HIP_TRY(c, hipMemcpyAsync(&c->hst[slot], &c->ctl->st[slot_of(c->jn - 2)], sizeof(State),
+            // (two-kernel path), or the last check of the launch (resident path)
+            HIP_TRY(c, hipMemcpyAsync(&c->hst[slot], &c->ctl->st[slot_of(c->jn - (resident ? 1 : 2))], sizeof(State),
                                       hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(c, hipEventRecord(c->sync_ev[slot], c->stream));
             if (pending >= 0) {
@@ -1119,9 +1248,9 @@ modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) 
             }
             pending = slot;
             slot ^= 1;
-            chunk = std::min<int64_t>(chunk * 2, 64);
+            chunk = std::min<int64_t>(chunk * 2, resident ? 1024 : 64);
         }
-        if ((st = enqueue_settle(c, p, 0))) return st;
+        if (!resident && (st = enqueue_settle(c, p, 0))) return st;
         if ((st = read_state(c, &kc))) return st;
         observed = std::chrono::steady_clock::now();
         if (!(p->certify && kc.status == ST_CONVERGED && !kc.certified)) break;

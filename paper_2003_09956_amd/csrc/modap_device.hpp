@@ -46,7 +46,9 @@ struct alignas(128) Ctrl {
     State st[2];
     int64_t step_limit;   // no step is taken once steps reaches this (set per call)
     int64_t sched_len;    // rows in the drift schedule
-    int64_t pad[14];
+    uint32_t barrier;     // arrivals at the grid barriers of a resident launch (zero before each)
+    uint32_t fault;       // a resident launch gave up waiting at a grid barrier
+    int64_t pad[13];
 };
 
 // Totals of the sweep's per-workgroup scalars, formed by the reduction.
@@ -291,6 +293,17 @@ __device__ __forceinline__ T wave_total(T v) {
 // NaN-propagating maximum (fmax would drop a NaN).
 __device__ __forceinline__ double max_nan(double a, double b) {
     return (b > a || b != b) ? b : a;
+}
+
+// NaN-propagating maximum over the 64 lanes of a wavefront whose lanes are
+// all active (the moves of wave_total, with max_nan for the adds); every lane
+// returns the same value.
+__device__ __forceinline__ double wave_max_nan(double v) {
+    v = max_nan(v, dpp_move<0xB1>(v));
+    v = max_nan(v, dpp_move<0x4E>(v));
+    v = max_nan(v, dpp_move<0x141>(v));
+    v = max_nan(v, dpp_move<0x140>(v));
+    return max_nan(max_nan(lane_value(v, 0), lane_value(v, 16)), max_nan(lane_value(v, 32), lane_value(v, 48)));
 }
 
 // ||y|| from its per-workgroup parts, in a fixed order.  Called by a whole
