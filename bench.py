@@ -81,6 +81,9 @@ MULTI = {
     "batch-f32-512": "512 FP32 Gaussian systems (n ~ U{64..2048}, m ~ U{2n..8n}), each with its own drift "
                      "N(0,1e-3^2) per coordinate per iteration, advanced together (one persistent sweep launch "
                      "per iteration), lambda=1, eps=1e-6*||b||inf, autotuned tiles",
+    "batch-f32-512-n256": "512 FP32 Gaussian systems of n=256, m=2048 (1 KiB rows), each with its own drift "
+                          "N(0,1e-3^2) per coordinate per iteration, advanced together (one persistent sweep "
+                          "launch per iteration), lambda=1, eps=1e-6*||b||inf, autotuned tiles",
     "catchup-box": "box-plus-sum system (FP64, dense, m=2n+1) translated along (1,...,1) at r units per "
                    "coordinate per wall-clock second; the highest r at which ModAP (lambda=1) still reaches "
                    "eps-feasibility (distance 1e-6) from x0=0 one unit outside (the translation experiment of "
@@ -147,18 +150,21 @@ def batch_tile_str(tile) -> str:
     return ",".join(str(k) for k in tile["item_kib"]) + f",{tile['grid']}"
 
 
-def batch_counters_path(tile: str) -> str:
-    """Committed rocprofv3 counter summary of the batched sweep of the
+BATCH_FAMILY_FILES = {"batch-f32-512": "sweep_batch_f32_512sys", "batch-f32-512-n256": "sweep_batch_f32_512x256"}
+
+
+def batch_counters_path(tile: str, workload: str = "batch-f32-512") -> str:
+    """Committed rocprofv3 counter summary of the batched sweep of one
     512-system FP32 family at one tile (item_kib for the four buckets, grid)."""
-    return os.path.join(ROOT, "profiles", f"sweep_batch_f32_512sys_tile{tile.replace(',', '-')}_counters.txt")
+    return os.path.join(ROOT, "profiles", f"{BATCH_FAMILY_FILES[workload]}_tile{tile.replace(',', '-')}_counters.txt")
 
 
-def measured_batch_traffic(tile):
+def measured_batch_traffic(tile, workload="batch-f32-512"):
     """HBM bytes per batched sweep launch from the committed counter summary
     taken on the current batch kernel source at this tile; else None."""
     want = batch_tile_str(tile)
     try:
-        with open(batch_counters_path(want)) as f:
+        with open(batch_counters_path(want, workload)) as f:
             kv = dict(l.split(" = ", 1) for l in f.read().splitlines() if " = " in l and not l.startswith("#"))
     except OSError:
         return None
@@ -307,7 +313,7 @@ def main():
         print(json.dumps({"copy_bytes": nbytes, "launches": 5}), flush=True)
         return
     P.lib()
-    if args.workload == "batch-f32-512":
+    if args.workload in ("batch-f32-512", "batch-f32-512-n256"):
         return bench_batch(args, P, W, torch)
     if args.workload == "serve-bf16-poisson":
         return bench_serve(args, P, W, torch)
@@ -559,7 +565,7 @@ def bench_batch(args, P, W, torch):
     """One step = one iteration of all 512 systems (one sweep launch, one
     reduction launch); data generated on the device with a seeded generator."""
     K, WU = args.steps, args.warmup
-    shapes = W.batch_shapes(512, seed=args.seed)
+    shapes = W.batch_shapes(512, seed=args.seed) if args.workload == "batch-f32-512" else [(256, 2048)] * 512
     B = P.Batch("f32")
     bytes_per_step = 0
     for i, (n, m) in enumerate(shapes):
@@ -597,11 +603,11 @@ def bench_batch(args, P, W, torch):
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": K, "warmup": WU,
         "ms_per_step": round(wall * 1e3 / K, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic (generated on the device, seeded)",
-        "config": {"workload": MULTI["batch-f32-512"], "systems": 512, "elements": int(sum(n * m for n, m in shapes)),
+        "config": {"workload": MULTI[args.workload], "systems": 512, "elements": int(sum(n * m for n, m in shapes)),
                    "bytes_per_step": bytes_per_step, "tile": tile},
         "pct_of_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_batch_traffic(tile),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_batch_traffic(tile, args.workload),
                      "kernel": "sweep_batch<1>",
                      "avg_us": round(sweep_us, 3), "reduce_avg_us": round(reduce_us, 3)},
     }

@@ -16,6 +16,7 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <unordered_set>
@@ -65,6 +66,7 @@ struct modap_batch {
     int device = 0;
     hipStream_t stream = nullptr;
     int cu_count = 0;
+    int per_cu = 0;         // sweep_batch workgroups resident per CU (0: not asked yet)
     std::string err;
     int dt = 1;
     size_t es = 4;
@@ -161,6 +163,22 @@ BSys *find_sys(modap_batch *c, int64_t id) {
     return &c->sys[(size_t)id];
 }
 
+// The form of the batched sweep for a system: rows of at most 64 VEC
+// elements are swept four to a wavefront (16 lanes each, RPW = 4), longer
+// ones a wavefront each (RPW = 1); C is the lane's 16-byte chunks of a row.
+// MODAP_BATCH_SHORT=0 keeps every row on a wavefront of its own.
+void kernel_form(int dt, const BSys &s, int32_t *rpw, int32_t *chunks) {
+    *rpw = 1;
+    *chunks = s.C;
+    if (s.C != 1) return;
+    const char *e = std::getenv("MODAP_BATCH_SHORT");
+    if (e && e[0] == '0') return;
+    *rpw = 4;
+    const int64_t per = 16 * (int64_t)vec_elems(dt);
+    const int64_t k = (s.ldA + per - 1) / per;
+    *chunks = k <= 1 ? 1 : k <= 2 ? 2 : 4;
+}
+
 // Largest row (padded length) the batched sweep covers.
 int64_t max_row(int dt) { return 64 * (int64_t)vec_elems(dt) * kBatchCmax; }
 
@@ -207,6 +225,8 @@ int64_t rows_per_item(const modap_batch *c, const BSys &s) {
     return std::min<int64_t>(r, (s.m + kBatchWaves - 1) / kBatchWaves * kBatchWaves);
 }
 
+const void *sweep_fn(int dt);
+
 modap_status rebuild(modap_batch *c) {
     if (!c->dirty) return MODAP_OK;
     HIP_TRY(c, hipStreamSynchronize(c->stream));  // the previous tables may still be read
@@ -237,7 +257,7 @@ modap_status rebuild(modap_batch *c) {
         d.tot = s.tot;
         d.ynp = s.ynp;
         d.R = (int32_t)((s.n + 63) / 64);
-        d.C = s.C;
+        kernel_form(c->dt, s, &d.RPW, &d.C);
         d.rows_per_item = rows_per_item(c, s);
         d.item0 = items;
         d.nitems = (s.m + d.rows_per_item - 1) / d.rows_per_item;
@@ -295,10 +315,15 @@ modap_status rebuild(modap_batch *c) {
         HIP_TRY(c, hipMemcpyAsync(c->d_cols, c->h_cols.data(), sizeof(BatchCol) * c->h_cols.size(),
                                   hipMemcpyHostToDevice, c->stream));
     }
-    // persistent grid: one workgroup per CU unless tuned.  With items of a
-    // few MiB a second workgroup per CU adds no bandwidth, and when the items
-    // are about as many as the workgroups it leaves the CUs unevenly loaded.
-    c->grid = c->tile.grid > 0 ? c->tile.grid : c->cu_count;
+    // persistent grid: as many workgroups as are resident at once (two per CU
+    // for FP32 and FP64 storage, one for BF16) unless tuned.  Measured on the
+    // 512-system FP32 families: the mix 6.40 against 6.28 TB/s at one per CU,
+    // the n = 256 family (short rows) 4.95 against 3.87 TB/s.
+    if (c->per_cu == 0 &&
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c->per_cu, sweep_fn(c->dt), 256, 0) != hipSuccess ||
+         c->per_cu < 1))
+        c->per_cu = 1;
+    c->grid = c->tile.grid > 0 ? c->tile.grid : c->cu_count * c->per_cu;
     c->grid = std::max(1, std::min(c->grid, std::max(1, c->nitems)));
     c->dirty = false;
     return MODAP_OK;
@@ -981,7 +1006,8 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
     if ((st = rebuild(c))) return st;
     if (c->h_sys.empty()) return fail(c, MODAP_E_STATE, "the batch has no systems");
     bool present[4] = {false, false, false, false};
-    for (const BatchSys &d : c->h_sys) present[bucket_of(d.C)] = true;
+    for (const BSys &s : c->sys)
+        if (s.alive) present[bucket_of(s.C)] = true;
     hipEvent_t e0 = event_at(c, 0), e1 = event_at(c, 1);
     if (!e0 || !e1) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
     // one timing: `reps` stateless sweeps (no decision, no b written)
@@ -1038,13 +1064,10 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
         }
         cur.item_kib[q] = pick;
     }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep_fn(c->dt), 256, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
     float win = 0.f;
-    if ((st = time_tile(cur, &win))) return st;   // grid 0: one workgroup per CU
+    if ((st = time_tile(cur, &win))) return st;   // grid 0: every resident workgroup
     int pick = cur.grid;
-    for (int mult = 2; mult <= per_cu; ++mult) {
+    for (int mult = 1; mult < c->per_cu; ++mult) {
         modap_batch_tile t = cur;
         t.grid = c->cu_count * mult;
         float ms = 0.f;

@@ -46,7 +46,9 @@ struct BatchSys {
     Totals *tot;
     double *ynp;            // [R] norm parts of y
     int32_t R;              // 64-column blocks: ceil(n/64)
-    int32_t C;              // 16-byte chunks per lane: 64*VEC*C >= ldA
+    int32_t C;              // 16-byte chunks per lane: (64/RPW)*VEC*C >= ldA
+    int32_t RPW;            // rows a wavefront sweeps at once: 1, or 4 (16 lanes per row)
+    int32_t pad;
     int64_t item0, nitems;  // the system's work items
     int64_t part0;          // Acc offset of the first item's partial y (stride ldA)
     int64_t rows_per_item;
@@ -79,6 +81,130 @@ struct BatchArgs {
 
 constexpr int kBatchWaves = 4;  // wavefronts per workgroup of sweep_batch
 constexpr int kBatchCmax = 8;   // largest C compiled
+
+// Stage the item's x_j = x_{j-1} - s*y_{j-1} (one rounding) and v in LDS,
+// zero from ldA to COLS (all threads of the workgroup; the caller syncs).
+template <int DT>
+__device__ __forceinline__ void batch_stage(const BatchSys &S, bool apply_v, double s, typename Store<DT>::Acc *xs,
+                                            typename Store<DT>::Acc *vs, int COLS) {
+    using Acc = typename Store<DT>::Acc;
+    constexpr int AV = 16 / (int)sizeof(Acc);
+    const int tid = threadIdx.x;
+    const int64_t ldA = S.ldA;
+    const Acc *wx = reinterpret_cast<const Acc *>(S.work);
+    const Acc *wv = wx + ldA;
+    const Acc *wy = wx + 2 * ldA;
+    for (int col = tid * AV; col < COLS; col += 256 * AV) {
+        Acc xv[AV], vv[AV];
+        if (col < ldA) {
+            const uint4 ux = load_global(reinterpret_cast<const uint4 *>(wx + col));
+            __builtin_memcpy(xv, &ux, 16);
+            if (s != 0.0) {
+                Acc yv[AV];
+                const uint4 uy = load_global(reinterpret_cast<const uint4 *>(wy + col));
+                __builtin_memcpy(yv, &uy, 16);
+#pragma unroll
+                for (int q = 0; q < AV; ++q) xv[q] = (Acc)step_point((double)xv[q], s, (double)yv[q]);
+            }
+            if (apply_v) {
+                const uint4 uv = load_global(reinterpret_cast<const uint4 *>(wv + col));
+                __builtin_memcpy(vv, &uv, 16);
+            } else {
+#pragma unroll
+                for (int q = 0; q < AV; ++q) vv[q] = (Acc)0;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < AV; ++q) xv[q] = vv[q] = (Acc)0;
+        }
+        uint4 ux, uv;
+        __builtin_memcpy(&ux, xv, 16);
+        __builtin_memcpy(&uv, vv, 16);
+        *reinterpret_cast<uint4 *>(xs + col) = ux;
+        *reinterpret_cast<uint4 *>(vs + col) = uv;
+    }
+}
+
+// End of a work item: the wavefronts' partials of y summed in LDS and
+// written as the item's partial (lanes with `owner` set hold the partial of
+// their columns col_of(c)), and the item's h, dmax and ||b||inf.
+template <int DT, int C, typename ColOf>
+__device__ __forceinline__ void batch_item_end(const BatchArgs &a, const BatchSys &S, int64_t k, int64_t band,
+                                               typename Store<DT>::Acc (&yacc)[C][Store<DT>::VEC], int64_t h,
+                                               double dmax, double binf,
+                                               typename Store<DT>::Acc (*lds)[kBatchCmax * 64 * Store<DT>::VEC],
+                                               int64_t *hsh, double *dsh, double *bsh, ColOf col_of, bool owner) {
+    using Acc = typename Store<DT>::Acc;
+    constexpr int VEC = Store<DT>::VEC;
+    constexpr int AV = 16 / (int)sizeof(Acc);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t ldA = S.ldA;
+    // The wavefronts' partials are summed pairwise in LDS (the staging space
+    // is free once every wavefront has left the row loop):
+    // (w0 + w2) + (w1 + w3); wavefront 0 writes the item's partial.
+    auto put = [&](Acc *dst) {
+        if (!owner) return;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int e = 0; e < VEC; e += AV) {
+                uint4 w;
+                __builtin_memcpy(&w, &yacc[c][e], 16);
+                *reinterpret_cast<uint4 *>(dst + col_of(c) + e) = w;
+            }
+    };
+    auto add = [&](const Acc *src) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int e = 0; e < VEC; e += AV) {
+                Acc t4[AV];
+                const uint4 u = *reinterpret_cast<const uint4 *>(src + col_of(c) + e);
+                __builtin_memcpy(t4, &u, 16);
+#pragma unroll
+                for (int q = 0; q < AV; ++q) yacc[c][e + q] += t4[q];
+            }
+    };
+    if (lane == 0) {
+        hsh[wave] = h;
+        dsh[wave] = dmax;
+        bsh[wave] = binf;
+    }
+    __syncthreads();
+    if (wave >= 2) put(lds[wave - 2]);
+    __syncthreads();
+    if (wave < 2) add(lds[wave]);
+    __syncthreads();
+    if (wave == 1) put(lds[0]);
+    __syncthreads();
+    if (wave == 0 && owner) {
+        add(lds[0]);
+        Acc *part = reinterpret_cast<Acc *>(a.part) + S.part0 + band * ldA;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (col_of(c) >= ldA) continue;
+#pragma unroll
+            for (int e = 0; e < VEC; e += AV) {
+                uint4 w;
+                __builtin_memcpy(&w, &yacc[c][e], 16);
+                *reinterpret_cast<uint4 *>(part + col_of(c) + e) = w;
+            }
+        }
+    }
+    if (tid == 0) {
+        int64_t hh = 0;
+        double dd = 0.0, bm = 0.0;
+        for (int g = 0; g < kBatchWaves; ++g) {
+            hh += hsh[g];
+            dd = max_nan(dd, dsh[g]);
+            bm = max_nan(bm, bsh[g]);
+        }
+        a.h_part[k] = hh;
+        a.dmax_part[k] = dd;
+        a.binf_part[k] = bm;
+    }
+}
 
 // One work item: rows [r0, r1) of system S, wavefront w taking rows r0+w,
 // r0+w+4, ...  The item's x (with the previous step applied) and v are staged
@@ -139,40 +265,9 @@ __device__ void batch_item(const BatchArgs &a, const BatchSys &Sref, int64_t k,
     const double s = a.decide ? st.s : 0.0;
 
     // stage x_j = x_{j-1} - s*y_{j-1} (one rounding) and v, zero past ldA
-    Acc *xs = lds[0];
-    Acc *vs = lds[1];
-    const Acc *wx = reinterpret_cast<const Acc *>(S.work);
-    const Acc *wv = wx + ldA;
-    const Acc *wy = wx + 2 * ldA;
-    for (int col = tid * AV; col < COLS; col += 256 * AV) {
-        Acc xv[AV], vv[AV];
-        if (col < ldA) {
-            const uint4 ux = load_global(reinterpret_cast<const uint4 *>(wx + col));
-            __builtin_memcpy(xv, &ux, 16);
-            if (s != 0.0) {
-                Acc yv[AV];
-                const uint4 uy = load_global(reinterpret_cast<const uint4 *>(wy + col));
-                __builtin_memcpy(yv, &uy, 16);
-#pragma unroll
-                for (int q = 0; q < AV; ++q) xv[q] = (Acc)step_point((double)xv[q], s, (double)yv[q]);
-            }
-            if (apply_v) {
-                const uint4 uv = load_global(reinterpret_cast<const uint4 *>(wv + col));
-                __builtin_memcpy(vv, &uv, 16);
-            } else {
-#pragma unroll
-                for (int q = 0; q < AV; ++q) vv[q] = (Acc)0;
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < AV; ++q) xv[q] = vv[q] = (Acc)0;
-        }
-        uint4 ux, uv;
-        __builtin_memcpy(&ux, xv, 16);
-        __builtin_memcpy(&uv, vv, 16);
-        *reinterpret_cast<uint4 *>(xs + col) = ux;
-        *reinterpret_cast<uint4 *>(vs + col) = uv;
-    }
+    batch_stage<DT>(S, apply_v, s, lds[0], lds[1], COLS);
+    const Acc *xs = lds[0];
+    const Acc *vs = lds[1];
     __syncthreads();
 
     Acc yacc[C][VEC];
@@ -251,69 +346,172 @@ __device__ void batch_item(const BatchArgs &a, const BatchSys &Sref, int64_t k,
         if (keep_b) write_b(t);
     }
 
-    // The wavefronts' partials are summed pairwise in LDS (the staging space
-    // is free once every wavefront has left the row loop):
-    // (w0 + w2) + (w1 + w3); wavefront 0 writes the item's partial.
-    auto put = [&](Acc *dst) {
+    batch_item_end<DT, C>(a, S, k, band, yacc, h, dmax, binf, lds, hsh, dsh, bsh, col_of, true);
+}
+
+// One work item of a system with short rows (ldA <= 16 VEC C elements): a row
+// takes 16 lanes, so a wavefront sweeps RPW = 4 consecutive rows at once.
+// Their dot products are reduced over 16 lanes (DPP only), and their
+// residuals, weights and counts are formed by their own lanes; the row
+// groups' partials of y are added once per item.  At step t wavefront w takes
+// rows r0 + 4 (4 t + w) + g, g = lane / 16.  The item's rows are read through
+// one buffer resource, padding columns and rows past the item as zeros.  (A
+// form with eight rows of 8 lanes measured no faster, and its registers cost
+// the whole persistent kernel an occupancy level.)
+template <int DT, int C>
+__device__ void batch_item_short(const BatchArgs &a, const BatchSys &Sref, int64_t k,
+                                 typename Store<DT>::Acc (*lds)[kBatchCmax * 64 * Store<DT>::VEC],
+                                 int64_t *hsh, double *dsh, double *bsh) {
+    using St = Store<DT>;
+    using Acc = typename St::Acc;
+    using T = typename St::T;
+    constexpr int VEC = St::VEC;
+    constexpr int RPW = 4, LPR = 16;               // rows per wavefront, lanes per row
+    constexpr int CW = LPR * VEC;                  // columns per chunk
+    constexpr int AV = 16 / (int)sizeof(Acc);
+    constexpr int COLS = C * CW;
+    constexpr int64_t PER = kBatchWaves * RPW;     // rows per step of the workgroup
+    constexpr uint32_t kOutside = 0x80000000u;     // a byte offset past every item
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane / LPR, gl = lane % LPR;
+    const BatchSys S = Sref;
+    const int64_t band = k - S.item0;
+    const int64_t r0 = band * S.rows_per_item;
+    const int64_t r1 = min(S.m, r0 + S.rows_per_item);
+    const int64_t ldA = S.ldA;
+    auto col_of = [&](int c) -> int { return c * CW + gl * VEC; };
+    const int64_t row_bytes = ldA * (int64_t)sizeof(T);
+    const int64_t nrows = r1 - r0;
+    const int64_t nmine = nrows > wave * RPW ? (nrows - wave * RPW + PER - 1) / PER : 0;
+    auto row_of = [&](int64_t t) -> int64_t { return r0 + (t * kBatchWaves + wave) * RPW + g; };
+    const __amdgpu_buffer_rsrc_t rr =
+        row_resource(reinterpret_cast<const char *>(S.A) + r0 * row_bytes, (uint32_t)(nrows * row_bytes));
+    // as in batch_item, a step past the wavefront's last one issues the same
+    // loads (here all outside the item: zeros, no memory traffic)
+    auto load_rows = [&](uint4 (&buf)[C], double &bi, double &ni, int64_t t) {
+        const int64_t row = row_of(t);
+        const bool ok = t < nmine && row < r1;
+        const int64_t rc = ok ? row : r0;
+        bi = load_global(S.b + rc);
+        ni = load_global(S.nu + rc);
+        const uint32_t base = (uint32_t)((rc - r0) * row_bytes);
 #pragma unroll
         for (int c = 0; c < C; ++c)
-#pragma unroll
-            for (int e = 0; e < VEC; e += AV) {
-                uint4 w;
-                __builtin_memcpy(&w, &yacc[c][e], 16);
-                *reinterpret_cast<uint4 *>(dst + col_of(c) + e) = w;
-            }
+            buf[c] = load_row_vec(rr, ok && col_of(c) < ldA ? base + (uint32_t)(col_of(c) * (int)sizeof(T)) : kOutside);
     };
-    auto add = [&](const Acc *src) {
+    uint4 bufA[C], bufB[C];
+    double bA, nA, bB, nB;
+    load_rows(bufA, bA, nA, 0);
+    load_rows(bufB, bB, nB, 1);
+
+    Pending pd{S.ctl, a.j, S.tot, S.ynp, S.R, a.decide, a.dp};
+    const State st = sweep_state(pd, lane, band == 0 && tid == 0);
+    if (a.check_status && st.status != ST_RUNNING) return;
+    const bool apply_v = st.vpend_valid || st.v_idx >= 0;
+    batch_stage<DT>(S, apply_v, a.decide ? st.s : 0.0, lds[0], lds[1], COLS);
+    const Acc *xs = lds[0];
+    const Acc *vs = lds[1];
+    __syncthreads();
+
+    Acc yacc[C][VEC];
 #pragma unroll
-        for (int c = 0; c < C; ++c)
+    for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int e = 0; e < VEC; e += AV) {
-                Acc t4[AV];
-                const uint4 u = *reinterpret_cast<const uint4 *>(src + col_of(c) + e);
-                __builtin_memcpy(t4, &u, 16);
-#pragma unroll
-                for (int q = 0; q < AV; ++q) yacc[c][e + q] += t4[q];
-            }
+        for (int e = 0; e < VEC; ++e) yacc[c][e] = (Acc)0;
+    int64_t h = 0;
+    double dmax = 0.0, binf = 0.0;
+    // the translated b of the wavefront's rows, collected as in batch_item:
+    // lane i holds that of the wavefront's row 64 q + i (its rows numbered
+    // 4 t + g), written for 64 rows at a time
+    const bool keep_b = apply_v && a.write_b;
+    double bkeep = 0.0;
+    auto write_b = [&](int64_t t_last) {
+        const int64_t q_last = t_last * RPW + RPW - 1;
+        const int64_t q = (q_last & ~(int64_t)63) + lane;
+        if (q <= q_last) {
+            const int64_t row = r0 + ((q / RPW) * kBatchWaves + wave) * RPW + q % RPW;
+            if (row < r1) store_global(S.b + row, bkeep);
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // the stores are done before rows are counted again
     };
-    if (lane == 0) {
-        hsh[wave] = h;
-        dsh[wave] = dmax;
-        bsh[wave] = binf;
-    }
-    __syncthreads();
-    if (wave >= 2) put(lds[wave - 2]);
-    __syncthreads();
-    if (wave < 2) add(lds[wave]);
-    __syncthreads();
-    if (wave == 1) put(lds[0]);
-    __syncthreads();
-    if (wave == 0) {
-        add(lds[0]);
-        Acc *part = reinterpret_cast<Acc *>(a.part) + S.part0 + band * ldA;
+    auto process = [&](uint4 (&buf)[C], double bi, double ni, int64_t t) {
+        const bool ok = row_of(t) < r1;
+        Acc dot = (Acc)0, tdot = (Acc)0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            if (col_of(c) >= ldA) continue;
+            Acc av[VEC], xv[VEC], vv[VEC];
+            unpack<DT>(buf[c], av);
 #pragma unroll
             for (int e = 0; e < VEC; e += AV) {
-                uint4 w;
-                __builtin_memcpy(&w, &yacc[c][e], 16);
-                *reinterpret_cast<uint4 *>(part + col_of(c) + e) = w;
+                const uint4 ux = *reinterpret_cast<const uint4 *>(xs + col_of(c) + e);
+                __builtin_memcpy(&xv[e], &ux, 16);
+            }
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) dot = fma(xv[e], av[e], dot);
+            if (apply_v) {
+#pragma unroll
+                for (int e = 0; e < VEC; e += AV) {
+                    const uint4 uv = *reinterpret_cast<const uint4 *>(vs + col_of(c) + e);
+                    __builtin_memcpy(&vv[e], &uv, 16);
+                }
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) tdot = fma(vv[e], av[e], tdot);
             }
         }
-    }
-    if (tid == 0) {
-        int64_t hh = 0;
-        double dd = 0.0, bm = 0.0;
-        for (int g = 0; g < kBatchWaves; ++g) {
-            hh += hsh[g];
-            dd = max_nan(dd, dsh[g]);
-            bm = max_nan(bm, bsh[g]);
+        dot = row_total(dot);
+        double bb = bi;
+        if (apply_v) bb += (double)row_total(tdot);
+        if (keep_b) {
+#pragma unroll
+            for (int q = 0; q < RPW; ++q) {
+                const double bq = lane_value(bb, q * LPR);
+                if (lane == (int)((t * RPW + q) & 63)) bkeep = bq;
+            }
         }
-        a.h_part[k] = hh;
-        a.dmax_part[k] = dd;
-        a.binf_part[k] = bm;
+        const double r = ok ? (double)dot - bb : -1.0;
+        if (ok) binf = max_nan(binf, fabs(bb));
+        const bool pos = r > 0.0;
+        h += (pos && gl == 0) ? 1 : 0;
+        const double d = r / sqrt(ni);
+        dmax = pos ? max_nan(dmax, d) : (r != r ? r : dmax);
+        const Acc w = pos ? (Acc)(r / ni) : (Acc)0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            Acc av[VEC];
+            unpack<DT>(buf[c], av);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) yacc[c][e] = fma(w, av[e], yacc[c][e]);
+        }
+    };
+    int64_t t = 0;
+    for (; t + 2 <= nmine; t += 2) {
+        process(bufA, bA, nA, t);   // t is even: its rows never end a group of 64
+        load_rows(bufA, bA, nA, t + 2);
+        process(bufB, bB, nB, t + 1);
+        if (keep_b && ((((t + 2) * RPW) & 63) == 0 || t + 2 == nmine)) write_b(t + 1);
+        load_rows(bufB, bB, nB, t + 3);
     }
+    if (t < nmine) {
+        process(bufA, bA, nA, t);
+        if (keep_b) write_b(t);
+    }
+    // the row groups' partials (lanes gl, gl + 16, gl + 32, gl + 48 hold the
+    // same columns), added pairwise: (g0 + g1) + (g2 + g3), the same bits in
+    // every group
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            Acc v = yacc[c][e];
+#pragma unroll
+            for (int o = LPR; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+            yacc[c][e] = v;
+        }
+    h = wave_sum(h);
+    dmax = wave_max_nan(dmax);
+    binf = wave_max_nan(binf);
+    batch_item_end<DT, C>(a, S, k, band, yacc, h, dmax, binf, lds, hsh, dsh, bsh, col_of, g == 0);
 }
 
 // Persistent sweep over every item of the batch.  Each workgroup takes queue
@@ -339,11 +537,19 @@ __global__ __launch_bounds__(256) void sweep_batch(const BatchArgs a) {
         if (threadIdx.x == 0) next = atomicAdd(a.queue, 1);
         const int k = load_global(a.item_order + pos);
         const BatchSys &S = a.sys[a.item_sys[k]];
-        switch (S.C) {
-            case 1: batch_item<DT, 1>(a, S, k, lds, hsh, dsh, bsh); break;
-            case 2: batch_item<DT, 2>(a, S, k, lds, hsh, dsh, bsh); break;
-            case 4: batch_item<DT, 4>(a, S, k, lds, hsh, dsh, bsh); break;
-            default: batch_item<DT, 8>(a, S, k, lds, hsh, dsh, bsh); break;
+        if (S.RPW == 4) {
+            switch (S.C) {
+                case 1: batch_item_short<DT, 1>(a, S, k, lds, hsh, dsh, bsh); break;
+                case 2: batch_item_short<DT, 2>(a, S, k, lds, hsh, dsh, bsh); break;
+                default: batch_item_short<DT, 4>(a, S, k, lds, hsh, dsh, bsh); break;
+            }
+        } else {
+            switch (S.C) {
+                case 1: batch_item<DT, 1>(a, S, k, lds, hsh, dsh, bsh); break;
+                case 2: batch_item<DT, 2>(a, S, k, lds, hsh, dsh, bsh); break;
+                case 4: batch_item<DT, 4>(a, S, k, lds, hsh, dsh, bsh); break;
+                default: batch_item<DT, 8>(a, S, k, lds, hsh, dsh, bsh); break;
+            }
         }
         if (threadIdx.x == 0) s_pos = next;
         __syncthreads();  // the item's use of LDS is over, and s_pos is set

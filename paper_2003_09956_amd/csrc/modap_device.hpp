@@ -274,19 +274,25 @@ __device__ __forceinline__ double lane_value(double v, int l) {
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Sum over the 64 lanes of a wavefront whose lanes are all active, the same
-// bits in every lane, without the LDS permute unit: DPP adds finish each row
-// of 16 lanes (partners xor 1, xor 2, then the half-row and row mirrors; the
-// two operands of every add are the same pair in both lanes, so all 16 lanes
-// hold identical sums), then the four row sums are read as scalars and added
-// as (row0 + row1) + (row2 + row3).  Used on the per-row paths, where the
-// permute round trips of wave_sum sit on the critical path.
+// Sum over each row of 16 lanes of a wavefront whose lanes are all active,
+// without the LDS permute unit: DPP adds with partners xor 1, xor 2, then the
+// half-row and row mirrors.  The two operands of every add are the same pair
+// in both lanes, so all 16 lanes of a row hold identical sums.
 template <typename T>
-__device__ __forceinline__ T wave_total(T v) {
+__device__ __forceinline__ T row_total(T v) {
     v += dpp_move<0xB1>(v);   // quad permutation [1,0,3,2]
     v += dpp_move<0x4E>(v);   // quad permutation [2,3,0,1]
     v += dpp_move<0x141>(v);  // half-row mirror
     v += dpp_move<0x140>(v);  // row mirror
+    return v;
+}
+// Sum over the 64 lanes of a wavefront whose lanes are all active, the same
+// bits in every lane: the row sums, read as scalars and added as
+// (row0 + row1) + (row2 + row3).  Used on the per-row paths, where the
+// permute round trips of wave_sum sit on the critical path.
+template <typename T>
+__device__ __forceinline__ T wave_total(T v) {
+    v = row_total(v);
     return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 

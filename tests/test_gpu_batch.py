@@ -207,6 +207,44 @@ def test_batch_long_items_write_b_in_the_row_loop(P):
             x = x1
 
 
+# short rows (at most 64 VEC elements): 1, 2 and 4 chunks per lane of the
+# 16-lanes-per-row form, ragged row counts, items long enough that the
+# translated b is written inside the row loop
+SHORT = [("f32", 20, 777), ("f32", 200, 3001), ("bf16", 500, 2501), ("bf16", 130, 901), ("f64", 50, 1999),
+         ("f64", 100, 2999)]
+
+
+@pytest.mark.parametrize("form", ["short", "wavefront"])
+@pytest.mark.parametrize("dtype,n,m", SHORT)
+def test_batch_short_rows_follow_oracle(P, monkeypatch, dtype, n, m, form):
+    """Short rows swept four to a wavefront (16 lanes each) and, for
+    comparison, one to a wavefront: three steps with a drift schedule, each
+    step and the translated b against the oracle."""
+    monkeypatch.setenv("MODAP_BATCH_SHORT", "1" if form == "short" else "0")
+    sys_ = W.gaussian(n, m, seed=n * 7 + m, dtype=dtype)
+    V = W.drift(n, 10, sigma=1e-3, seed=n)
+    lam = 0.3
+    prm = P.params(lam=lam, eps=1e-9)
+    x = sys_.z + 0.3
+    b = sys_.b.copy()
+    with P.Batch(dtype) as B:
+        B.set_tile(item_kib=[256, 2048, 4096, 8192])   # items of 260-3300 rows
+        sid = B.add(sys_.A, sys_.b, x0=x)
+        B.set_drift(sid, V)
+        for k in range(3):
+            say(f"batch short rows {dtype} n={n} m={m} form={form} k={k}")
+            B.iterate(1, prm)
+            x1, b1, q = B.query(sid, want_b=True)
+            o = oracle.sweep(sys_.A, dtype, b, x)
+            xo, status = oracle.step(o.y, o.h, 0, lam, x)
+            assert status == 0 and q.iters == k + 1
+            assert np.linalg.norm(x1 - xo) <= step_bound(sys_, dtype, o, x, lam), k
+            b = oracle.translate(sys_.A, dtype, b, V[k])
+            scale = np.abs(W.stored_to_f64(sys_.A, dtype)) @ np.abs(V[:k + 1]).sum(axis=0) + np.abs(sys_.b)
+            assert np.max(np.abs(b1 - b) / scale) <= TOL[dtype], k
+            x = x1
+
+
 def test_batch_solve_reaches_feasibility(P):
     """Systems of several sizes solved together, each stopping on its own:
     box-plus-sum systems (a ball of radius 100 inside, so ModAP with lambda = 1
