@@ -50,7 +50,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_EVERY = 10      # one iteration in ten carries HIP events on its kernel dispatches
 DRIFT_SEEDS = 10        # drift sequences of the time-to-feasible chase on the default system
 DRIFT_STEPS = 3000      # iterations allowed per chase
 DRIFT_SPEEDS = (1e-5, 1e-4, 1e-3)   # drift norms |v| per iteration swept on the BF16 system
@@ -332,7 +331,7 @@ def main():
     else:
         sys_ = W.gaussian(n, m, args.seed, dt)
         A_in, b_in = sys_.A, sys_.b
-    V = W.drift(n, K + WU, sigma=sigma, seed=args.seed)
+    V = W.drift(n, 2 * (K + WU), sigma=sigma, seed=args.seed)
     res = timed_steps(P, torch, A_in, b_in, dt, V, K, WU, lam, eps, args)
     line = step_line(args, dt, n, m, desc, res)
     extra_fp32 = None
@@ -340,7 +339,7 @@ def main():
         # the FP32 n = 8192, m = 16384 system of round numbers as a second line
         log("generating the FP32 n=8192 m=16384 system ...")
         s2 = W.gaussian(8192, 16384, args.seed, "f32")
-        V2 = W.drift(8192, K + WU, sigma=1e-2, seed=args.seed)
+        V2 = W.drift(8192, 2 * (K + WU), sigma=1e-2, seed=args.seed)
         res2 = timed_steps(P, torch, s2.A, s2.b, "f32", V2, K, WU, lam, eps, args)
         extra_fp32 = step_line(args, "f32", 8192, 16384, WORKLOADS["f32-8192x16384"][4], res2)
         for key in ("metric", "unit", "n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline",
@@ -369,11 +368,12 @@ def main():
 
 
 def timed_steps(P, torch, A, b, dt, V, K, WU, lam, eps, args):
-    """K timed steps (after WU untimed ones) of one system in tracking mode.
-    Every timed iteration's kernels carry HIP events when K <= 50, else one
-    in PROFILE_EVERY."""
+    """K timed steps (after WU untimed ones) of one system in tracking mode,
+    then the same K steps again with HIP events on every iteration's kernel
+    dispatches (the roofline's kernel durations).  The events cost 8-10 us per
+    step on this stack, so the throughput is taken from the first pass, which
+    carries none.  V needs 2 (K + WU) rows."""
     m, n = int(A.shape[0]), int(A.shape[1])
-    every = 1 if K <= 50 else PROFILE_EVERY
     with P.Solver(0) as s:
         s.set_system(A, b, dtype=dt)      # first call: allocation and warm-up
         torch.cuda.synchronize()
@@ -393,24 +393,32 @@ def timed_steps(P, torch, A, b, dt, V, K, WU, lam, eps, args):
         else:
             tile = s.get_tile()
             log("tile (built-in)", tile)
-        # the warm-up also profiles, as many iterations as the timed region
-        # will, so that the profiling events exist before the clock starts
-        n_prof = (K + every - 1) // every
-        s.iterate(WU, P.params(lam=lam, eps=eps, track=True, profile=max(1, WU // max(n_prof, 1))))
+        s.iterate(WU, P.params(lam=lam, eps=eps, track=True))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = s.iterate(K, P.params(lam=lam, eps=eps, track=True, profile=every))
+        st = s.iterate(K, P.params(lam=lam, eps=eps, track=True))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        if st.sweeps != K + WU or st.profiled != n_prof:
+        if st.sweeps != K + WU:
             raise RuntimeError(f"timed region ran {st.sweeps - WU} sweeps, expected {K}")
+        # the profiled pass: WU untimed iterations that also create the events
+        # (none is created while the device runs ahead), then K with events
+        s.iterate(WU, P.params(lam=lam, eps=eps, track=True, profile=1))
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        sp = s.iterate(K, P.params(lam=lam, eps=eps, track=True, profile=1))
+        torch.cuda.synchronize()
+        p1 = time.perf_counter()
+        if sp.profiled != K:
+            raise RuntimeError(f"profiled pass timed {sp.profiled} sweeps, expected {K}")
     wall = t1 - t0
-    sweep_us = st.sweep_ms * 1e3 / st.profiled
-    reduce_us = st.reduce_ms * 1e3 / st.profiled
-    log(f"{dt} n={n} m={m}: timed {K} steps in {wall * 1e3:.2f} ms; sweep {sweep_us:.1f} us, "
-        f"reduce {reduce_us:.1f} us ({st.profiled} profiled)")
-    return {"wall": wall, "sweep_us": sweep_us, "reduce_us": reduce_us, "profiled": int(st.profiled),
-            "tile": tile, "upload_s": upload_s, "host_bytes": int(A.nbytes if hasattr(A, "nbytes") else 0),
+    sweep_us = sp.sweep_ms * 1e3 / sp.profiled
+    reduce_us = sp.reduce_ms * 1e3 / sp.profiled
+    log(f"{dt} n={n} m={m}: timed {K} steps in {wall * 1e3:.2f} ms ({(p1 - p0) * 1e3:.2f} ms with events); "
+        f"sweep {sweep_us:.1f} us, reduce {reduce_us:.1f} us ({sp.profiled} profiled)")
+    return {"wall": wall, "wall_profiled": p1 - p0, "sweep_us": sweep_us, "reduce_us": reduce_us,
+            "profiled": int(sp.profiled), "tile": tile, "upload_s": upload_s,
+            "host_bytes": int(A.nbytes if hasattr(A, "nbytes") else 0),
             "feasible_steps": int(st.sweeps - st.iters), "bytes_per_step": m * n * ELEM_BYTES[dt] + 24 * m,
             "on_host": not hasattr(A, "is_cuda")}
 
@@ -447,7 +455,9 @@ def step_line(args, dt, n, m, desc, res):
                      "kernel": f"{kind}<{DT_CODE[dt]},{tile['block']},{tile['lanes_per_row']},{tile['chunks']},"
                                f"{tile['rows_per_step']},{tile['depth']},true>",
                      "avg_us": round(res["sweep_us"], 3), "reduce_avg_us": round(res["reduce_us"], 3),
-                     "profiled_sweeps": res["profiled"]},
+                     "profiled_sweeps": res["profiled"],
+                     "profiled_pass": "the same K steps again, every kernel dispatch carrying HIP events "
+                                      f"({res['wall_profiled'] * 1e3 / K:.4f} ms per step with them)"},
     }
     if res["on_host"]:
         line["host_upload"] = {"ms": round(res["upload_s"] * 1e3, 3), "bytes": res["host_bytes"],
@@ -573,7 +583,7 @@ def bench_batch(args, P, W, torch):
         sid = B.add(A, b)
         g = torch.Generator(device="cuda")
         g.manual_seed(args.seed * 7 + i)
-        B.set_drift(sid, torch.randn((K + WU, n), generator=g, device="cuda", dtype=torch.float64) * 1e-3)
+        B.set_drift(sid, torch.randn((2 * (K + WU), n), generator=g, device="cuda", dtype=torch.float64) * 1e-3)
         bytes_per_step += m * n * 4 + 24 * m
         del A, b
     torch.cuda.synchronize()
@@ -586,13 +596,20 @@ def bench_batch(args, P, W, torch):
         tile = B.autotune(5)
         log("batch tile (autotuned)", tile)
     lam, eps = 1.0, 1e-6
-    n_prof = (K + PROFILE_EVERY - 1) // PROFILE_EVERY
-    B.iterate(WU, P.params(lam=lam, eps=eps, track=True, profile=max(1, WU // max(n_prof, 1))))
+    # the timed pass carries no events; the same K steps again with events on
+    # every iteration give the kernel durations (as in timed_steps)
+    B.iterate(WU, P.params(lam=lam, eps=eps, track=True))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = B.iterate(K, P.params(lam=lam, eps=eps, track=True, profile=PROFILE_EVERY))
+    B.iterate(K, P.params(lam=lam, eps=eps, track=True))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    B.iterate(WU, P.params(lam=lam, eps=eps, track=True, profile=1))
+    torch.cuda.synchronize()
+    st = B.iterate(K, P.params(lam=lam, eps=eps, track=True, profile=1))
+    torch.cuda.synchronize()
+    if st.profiled != K:
+        raise RuntimeError(f"profiled pass timed {st.profiled} sweeps, expected {K}")
     sweep_us = st.sweep_ms * 1e3 / st.profiled
     reduce_us = st.reduce_ms * 1e3 / st.profiled
     B.close()

@@ -577,7 +577,8 @@ modap_status read_state(modap_ctx *c, State *out) {
     HIP_TRY(c, hipMemcpyAsync(bf, &c->ctl->barrier, sizeof bf, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (bf[1])
-        return fail(c, MODAP_E_DEVICE, "a resident launch gave up waiting at a grid barrier; the context's data are void");
+        return fail(c, MODAP_E_DEVICE,
+                    "a resident launch gave up waiting at a grid barrier; the context's data are void until set_system");
     return MODAP_OK;
 }
 
@@ -730,7 +731,7 @@ bool use_resident(const modap_ctx *c, const modap_params *p) {
 // every check it makes, so no stage kernel follows).
 modap_status launch_resident(modap_ctx *c, const modap_params *p, int track, int64_t K, double *bytes) {
     const bool hv = translation_possible(c);
-    HIP_TRY(c, hipMemsetAsync(&c->ctl->barrier, 0, 2 * sizeof(uint32_t), c->stream));
+    HIP_TRY(c, hipMemsetAsync(&c->ctl->barrier, 0, sizeof(uint32_t), c->stream));   // the fault flag stays raised
     ResidentArgs r{};
     r.A = c->A;
     r.ldA = c->ldA;

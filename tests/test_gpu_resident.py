@@ -159,3 +159,10 @@ def test_resident_barrier_timeout_is_reported(P, monkeypatch):
         say("forced barrier timeout")
         with pytest.raises(P.ModapError, match="E_DEVICE"):
             s.iterate(5, P.params(lam=1.0, eps=1e-6))
+        # the data stay void (the report is sticky) until the system is set again
+        monkeypatch.delenv("MODAP_RESIDENT_TIMEOUT_TICKS")
+        with pytest.raises(P.ModapError, match="E_DEVICE"):
+            s.iterate(5, P.params(lam=1.0, eps=1e-6))
+        s.set_system(sys_.A, sys_.b, x0=sys_.x0, dtype="f64")
+        st = s.iterate(5, P.params(lam=1.0, eps=1e-6))
+        assert st.iters == 5
