@@ -274,6 +274,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving: HBM budget of the server")
     ap.add_argument("--iters-per-round", type=int, default=64,
                     help="serving: iterations every live request takes per round of the server")
+    ap.add_argument("--max-long", type=int, default=1,
+                    help="serving: live requests with rows too long for the batch at most (0: no limit)")
     ap.add_argument("--n", type=int, default=32000, help="translation experiment: number of variables")
     ap.add_argument("--lam", type=float, default=1.0, help="translation experiment: ModAP step length")
     ap.add_argument("--tile", type=str, default=None,
@@ -803,7 +805,7 @@ def bench_catchup(args, P, W, torch):
     print(json.dumps(line), flush=True)
 
 
-def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8):
+def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8, max_long=0):
     """Drive one server over the arrivals: requests generated on the device at
     their arrival time, every 10 ms each live request translated (|v| = 1e-4)
     and 1% of its rows replaced by fresh rows that keep its moving hidden point
@@ -816,6 +818,8 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8):
     S = P.Server(storage, budget_bytes=args.budget_gb * 1e9, prm=prm, iters_per_round=ipr)
     if max_live:
         S.set_max_live(max_live)
+    if max_long:
+        S.set_max_long(max_long)
     # the generators run on torch's stream; waiting for that stream alone
     # leaves the server's iterations in flight
     gen = torch.Generator(device="cuda")
@@ -871,11 +875,16 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8):
     tot = S.totals()
     S.close()
     ttf = [inf["t_done"] - inf["t_submit"] for inf in infos if inf["state"] == 2 and inf["status"] == 1]
+    done = sorted(((inf["t_done"] - inf["t_submit"], tk) for tk, inf in zip(reqs, infos)
+                   if inf["state"] == 2 and inf["status"] == 1), reverse=True)
+    slowest = [{"n": reqs[tk]["n"], "t_submit_s": round(infos[list(reqs).index(tk)]["t_submit"], 3),
+                "ttf_ms": round(1e3 * t, 1)} for t, tk in done[:3]]
     out = {"p50_ms": round(1e3 * percentile(ttf, 50), 3) if ttf else None,
            "p99_ms": round(1e3 * percentile(ttf, 99), 3) if ttf else None,
            "feasible": len(ttf), "requests": len(reqs), "censored": sum(1 for inf in infos if inf["state"] < 2),
            "GBs": round(tot["hbm_bytes"] / wall / 1e9, 2), "rounds": rounds, "wall_s": round(wall, 3),
-           "storage": storage, "max_live": max_live or None}
+           "storage": storage, "max_live": max_live or None, "max_long": max_long or None,
+           "slowest": slowest}
     return out, tot["hbm_bytes"], wall, rounds
 
 
@@ -887,7 +896,8 @@ def bench_serve(args, P, W, torch):
     log(f"{len(arrivals)} arrivals over {args.horizon} s at {args.rate}/s")
     cap = max(60.0, 6.0 * args.horizon)
     ipr = args.iters_per_round
-    served, bytes_, wall, rounds = serve_pass(args, P, W, torch, arrivals, "bf16", 0, cap, ipr=ipr)
+    served, bytes_, wall, rounds = serve_pass(args, P, W, torch, arrivals, "bf16", 0, cap, ipr=ipr,
+                                              max_long=args.max_long)
     log("served", served)
     queue, _, _, _ = serve_pass(args, P, W, torch, arrivals, "bf16", 1, cap, ipr=ipr)
     log("bf16 one at a time", queue)
@@ -899,7 +909,8 @@ def bench_serve(args, P, W, torch):
         "ms_per_step": round(wall * 1e3 / max(rounds, 1), 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic (generated on the device, seeded)",
         "config": {"workload": MULTI["serve-bf16-poisson"], "rate_per_s": args.rate, "horizon_s": args.horizon,
-                   "budget_gb": args.budget_gb, "iters_per_round": ipr, "requests": len(arrivals)},
+                   "budget_gb": args.budget_gb, "iters_per_round": ipr, "max_long": args.max_long,
+                   "requests": len(arrivals)},
         "pct_of_peak": round(100 * value / HBM_PEAK_GBS, 2),
         # no single kernel dominates a served pass: the aggregate algorithmic
         # bytes of every sweep of every live request over the pass's wall time

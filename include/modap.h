@@ -431,6 +431,16 @@ modap_status modap_server_round(modap_server *server, double now, int64_t *outst
  * budget); 1 serves the requests one after the other.  Errors: E_INVAL. */
 modap_status modap_server_set_max_live(modap_server *server, int64_t max_live);
 
+/* Keep at most max_long requests live whose rows are too long for the
+ * batched sweep (each gets a context of its own; 0, the default: no limit
+ * besides the budget).  A long request beyond the limit waits in the queue,
+ * and requests behind it whose rows fit the batch may be admitted past it;
+ * so the long requests run with the device's bandwidth between their
+ * updates instead of sharing it, while the short ones keep flowing.  A
+ * request's result still depends only on its own data, updates and rounds.
+ * Errors: E_INVAL. */
+modap_status modap_server_set_max_long(modap_server *server, int64_t max_long);
+
 /* State and statistics of a request.  Errors: E_INVAL. */
 modap_status modap_server_info(modap_server *server, int64_t ticket, modap_request_info *out);
 

@@ -39,6 +39,7 @@ EXPORTS = ["modap_create", "modap_destroy", "modap_set_system", "modap_set_x", "
            "modap_batch_last_error", "modap_server_create", "modap_server_destroy", "modap_server_submit",
            "modap_server_update", "modap_server_round", "modap_server_info", "modap_server_result",
            "modap_server_totals", "modap_server_last_error", "modap_server_set_max_live",
+           "modap_server_set_max_long",
            "modap_eval_sweep_static"]
 
 
@@ -163,6 +164,7 @@ def lib():
         L.modap_server_last_error.argtypes = [vp]
         L.modap_server_last_error.restype = C.c_char_p
         L.modap_server_set_max_live.argtypes = [vp, i64]
+        L.modap_server_set_max_long.argtypes = [vp, i64]
         L.modap_eval_sweep_static.argtypes = [i32, vp, i64, i64, i32, vp, i64, dp, dp, dp, dp, dp, dp]
         for name in EXPORTS:
             if name not in ("modap_destroy", "modap_strerror", "modap_last_error", "modap_batch_destroy",
@@ -615,6 +617,9 @@ class Server:
 
     def set_max_live(self, k):
         self._check(lib().modap_server_set_max_live(self._h, int(k)))
+
+    def set_max_long(self, k):
+        self._check(lib().modap_server_set_max_long(self._h, int(k)))
 
     def totals(self):
         b, r, u = C.c_double(), C.c_int64(), C.c_double()

@@ -80,6 +80,8 @@ struct modap_server {
     modap_params params{};
     int iters_per_round = 8;
     int64_t max_live = 0;       // 0: no limit besides the budget
+    int64_t max_long = 0;       // live requests with contexts of their own at most (0: no limit)
+    int64_t long_live = 0;
     int64_t live = 0;
     int64_t max_sweeps = 0;
     modap_batch *batch = nullptr;
@@ -103,6 +105,10 @@ int64_t padded(int dt, int64_t n) {
 
 // Rows the batched sweep covers (64 lanes x 16-byte vectors x 8 chunks).
 int64_t batch_row_limit(int dt) { return 64 * (int64_t)vec_elems(dt) * 8; }
+
+// A request whose rows fit the batched sweep joins the batch; a longer one
+// gets a context of its own.
+bool batched(const modap_server *s, const Req &r) { return r.ldA <= batch_row_limit(s->dt); }
 
 // A staging buffer of at least `bytes` whose last update has run, from the
 // server's pool (grown when none is free).
@@ -159,7 +165,10 @@ void drop(modap_server *s, Req &r) {
         (void)modap_batch_remove(s->batch, r.bid);
         --s->batch_live;
     }
-    if (r.ctx) modap_destroy(r.ctx);
+    if (r.ctx) {
+        modap_destroy(r.ctx);
+        --s->long_live;
+    }
     if (r.stream) (void)hipStreamDestroy(r.stream);
     r.ctx = nullptr;
     r.stream = nullptr;
@@ -177,7 +186,7 @@ modap_status admit(modap_server *s, Req &r, double now) {
     const double *b = od ? r.db : r.hb.data();
     const double *x0 = !r.has_x0 ? nullptr : od ? r.dx0 : r.hx0.data();
     const double *V = r.T == 0 ? nullptr : od ? r.dV : r.hV.data();
-    if (r.ldA <= batch_row_limit(s->dt)) {
+    if (batched(s, r)) {
         int64_t id = -1;
         if ((st = modap_batch_add(s->batch, r.m, r.n, A, r.n, b, x0, od, &id))) {
             r.error = modap_batch_last_error(s->batch);
@@ -213,6 +222,7 @@ modap_status admit(modap_server *s, Req &r, double now) {
     r.t_admit = now;
     s->used += r.footprint;
     ++s->live;
+    if (!r.in_batch) ++s->long_live;
     return MODAP_OK;
 }
 
@@ -405,11 +415,16 @@ modap_status modap_server_round(modap_server *s, double now, int64_t *outstandin
     DeviceGuard g(s->device);
     const auto t0 = std::chrono::steady_clock::now();
     modap_status st;
-    // admission in arrival order while the footprint fits
-    while (!s->pending.empty()) {
-        Req &r = s->reqs[(size_t)s->pending.front()];
+    // admission in arrival order while the footprint fits; a long-row request
+    // beyond max_long waits, and the requests behind it may pass it
+    for (auto it = s->pending.begin(); it != s->pending.end();) {
+        Req &r = s->reqs[(size_t)*it];
+        if (!batched(s, r) && s->max_long > 0 && s->long_live >= s->max_long) {
+            ++it;
+            continue;
+        }
         if (!admissible(s->used, r.footprint, s->budget, s->live, s->max_live)) break;
-        s->pending.pop_front();
+        it = s->pending.erase(it);
         st = admit(s, r, now + elapsed_since(t0));
         release_inputs(r);  // the request's data now live in the batch or its context
         if (st) {
@@ -471,6 +486,13 @@ modap_status modap_server_round(modap_server *s, double now, int64_t *outstandin
         for (const Req &r : s->reqs) cnt += r.state == RQ_LIVE;
         *outstanding = cnt;
     }
+    return MODAP_OK;
+}
+
+modap_status modap_server_set_max_long(modap_server *s, int64_t max_long) {
+    if (!s) return MODAP_E_INVAL;
+    if (max_long < 0) return fail(s, MODAP_E_INVAL, "max_long < 0");
+    s->max_long = max_long;
     return MODAP_OK;
 }
 

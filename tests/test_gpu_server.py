@@ -88,6 +88,40 @@ def test_server_result_same_alone_and_in_mix(P, dtype):
         assert o.dmax <= 1e-6 * o.binf * (1 + 1e-12)
 
 
+def test_server_long_requests_one_at_a_time(P):
+    """max_long = 1: a second request with long rows waits in the queue while
+    the first is live, a short one submitted after it is admitted past it,
+    and the waiting request's result is the same bits as served alone."""
+    dtype = "f32"
+    long1 = W.gaussian(2500, 5000, seed=21, dtype=dtype)
+    long2 = W.gaussian(2600, 5200, seed=22, dtype=dtype)
+    short = W.gaussian(300, 1200, seed=23, dtype=dtype)
+    prm = P.params(lam=0.1, eps=1e-6, max_iters=5000)
+    with P.Server(dtype, budget_bytes=40e9, prm=prm, iters_per_round=8) as S:
+        S.set_max_long(1)
+        t1 = S.submit(long1.A, long1.b)
+        t2 = S.submit(long2.A, long2.b)
+        ts = S.submit(short.A, short.b)
+        say("server max_long=1")
+        S.round(now=1.0)
+        assert S.info(t1)["state"] == 1 and S.info(ts)["state"] == 1
+        assert S.info(t2)["state"] == 0, "the second long request waits"
+        for k in range(2, 20000):   # the round index is the clock
+            left = S.round(now=float(k))
+            if S.info(t1)["state"] != 2:
+                assert S.info(t2)["state"] == 0
+            if left == 0:
+                break
+        infos = [S.info(t) for t in (t1, t2, ts)]
+        assert all(i["state"] == 2 and i["status"] == 1 for i in infos), infos
+        assert infos[1]["t_admit"] >= infos[0]["t_done"]
+        x2, it2 = S.result(t2), infos[1]["iters"]
+    with P.Server(dtype, budget_bytes=40e9, prm=prm, iters_per_round=8) as S:
+        t2 = S.submit(long2.A, long2.b)
+        run_until_done(S, [t2])
+        assert S.info(t2)["iters"] == it2 and np.array_equal(S.result(t2), x2)
+
+
 def test_server_admission_respects_budget(P):
     """A budget that holds about one request: the requests are served one
     after the other, memory in use never exceeds the budget, and all finish."""
