@@ -1,8 +1,11 @@
 // Fused sweep shapes for IEEE binary64 storage (16-byte vector = 2 elements):
-// (workgroup, lanes per row, chunks, rows per step, steps in flight + 1).
+// (workgroup, lanes per row, chunks, rows per step, steps in flight + 1); 16 or 32 lanes per row
+// sweep four or two short rows per wavefront.
 // Every shape listed compiles without register spills.
 #define MODAP_DT 0
 #define MODAP_SHAPES                                                                             \
+    MODAP_SHAPE(256, 16, 1, 1, 2), MODAP_SHAPE(256, 16, 2, 1, 2), MODAP_SHAPE(256, 16, 4, 1, 2),          \
+    MODAP_SHAPE(256, 32, 4, 1, 2),                                                                         \
     MODAP_SHAPE(256, 64, 1, 1, 2), MODAP_SHAPE(256, 64, 2, 1, 2), MODAP_SHAPE(256, 64, 4, 1, 2),          \
     MODAP_SHAPE(256, 64, 1, 2, 2), MODAP_SHAPE(256, 64, 2, 2, 2), MODAP_SHAPE(256, 64, 4, 2, 2),          \
     MODAP_SHAPE(256, 256, 2, 1, 2), MODAP_SHAPE(256, 256, 4, 1, 2), MODAP_SHAPE(256, 256, 8, 1, 2),       \

@@ -13,7 +13,8 @@
 // reduction kernel, in the accumulation type; the step decided on the previous
 // check (x_j = x_{j-1} - s*y_{j-1}) is applied while they are staged.
 //
-// Thread shape: LPR lanes (a multiple of the 64-wide wavefront) share a row;
+// Thread shape: LPR lanes (a multiple of the 64-wide wavefront, or 16 or 32
+// for short rows, several rows to a wavefront) share a row;
 // a workgroup of BLOCK lanes holds BLOCK/LPR row groups, and each row group
 // takes RS consecutive rows per step, with the rows of the next PD-1 steps in
 // flight (PD at the start).  The row is cut into C chunks of LPR*VEC
@@ -50,6 +51,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_resource(const char *row, 
 __device__ __forceinline__ uint4 load_row_vec(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 2);
     return make_uint4(t.x, t.y, t.z, t.w);
+}
+
+// Sum over each group of LPR = 16 or 32 consecutive lanes (every lane of a
+// group holds the same bits): the DPP stages of a 16-lane row, then for 32
+// lanes one exchange with the partner row.
+template <int LPR, typename T>
+__device__ __forceinline__ T group_total(T v) {
+    static_assert(LPR == 16 || LPR == 32, "groups of 16 or 32 lanes");
+    v = row_total(v);
+    if constexpr (LPR == 32) v += __shfl_xor(v, 16, 64);
+    return v;
 }
 
 template <int DT>
@@ -91,16 +103,20 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
     constexpr int NW = BLOCK / 64;
     constexpr int CW = LPR * VEC;     // columns per chunk
     constexpr int AV = 16 / (int)sizeof(Acc);  // working-vector elements per 16-byte load
-    static_assert(LPR % 64 == 0 && BLOCK % LPR == 0, "row groups are whole wavefronts");
+    // SUB: rows of 16 or 32 lanes, 64/LPR of them to a wavefront
+    constexpr bool SUB = LPR < 64;
+    constexpr int GPW = SUB ? 64 / LPR : 1;   // row groups per wavefront
+    static_assert((LPR % 64 == 0 || LPR == 16 || LPR == 32) && BLOCK % LPR == 0 && BLOCK % 64 == 0,
+                  "row groups are whole wavefronts, or 16 or 32 lanes");
     static_assert(VEC % AV == 0, "a lane's columns are whole 16-byte vectors of the working vectors");
     static_assert(PD >= 2, "at least one step is in flight while another is reduced");
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    // the row group is the same for every lane of a wavefront (LPR is a
-    // multiple of 64): say so, so that row addresses stay in scalar registers
-    const int grp = __builtin_amdgcn_readfirstlane(tid / LPR);
+    // the row group is the same for every lane of a wavefront when LPR is a
+    // multiple of 64: say so, so that row addresses stay in scalar registers
+    const int grp = SUB ? tid / LPR : __builtin_amdgcn_readfirstlane(tid / LPR);
     const int gl = tid % LPR;
     const int rot = (int)(blockIdx.x % C);
 
@@ -136,19 +152,44 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
     uint32_t coff[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) coff[c] = (uint32_t)(col_of(c) * (int64_t)sizeof(T));
+    // Short rows (SUB): the wavefront's GPW*RS consecutive rows of a step
+    // through one resource based at its first row; a lane's chunk past its
+    // padded row, and a row past the band, are given an offset outside the
+    // range (zeros, no memory traffic).
+    constexpr uint32_t kOutside = 0x80000000u;
+    bool cin[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) cin[c] = col_of(c) < a.ldA;
     auto load_rows = [&](uint4 (&buf)[RS][C], double (&bi)[RS], double (&nui)[RS], int64_t t) {
         const bool live = t < nsteps;
+        if constexpr (SUB) {
+            const int64_t rw = r0 + t * a.step_stride + (int64_t)(wave * GPW) * RS;   // uniform
+            const int64_t rb = live ? min(rw, r1 - 1) : 0;
+            const __amdgpu_buffer_rsrc_t rr = row_resource(Ab + rb * row_bytes, (uint32_t)(GPW * RS) * row_range);
 #pragma unroll
-        for (int q = 0; q < RS; ++q) {
-            const int64_t row = live ? min(row_of(t, q), r1 - 1) : 0;
-            // b and nu first: loads return in order, so once the row has
-            // arrived they have too, and no register of a reduced row is
-            // still waiting for data when the buffer is refilled
-            bi[q] = a.b_in[row];
-            nui[q] = a.nu[row];
-            const __amdgpu_buffer_rsrc_t rr = row_resource(Ab + row * row_bytes, row_range);
+            for (int q = 0; q < RS; ++q) {
+                const int64_t row = row_of(t, q);
+                const bool ok = live && row < r1;
+                const int64_t rc = ok ? row : rb;
+                bi[q] = a.b_in[rc];
+                nui[q] = a.nu[rc];
+                const uint32_t base = (uint32_t)((rc - rb) * row_bytes);
 #pragma unroll
-            for (int c = 0; c < C; ++c) buf[q][c] = load_row_vec(rr, coff[c]);
+                for (int c = 0; c < C; ++c) buf[q][c] = load_row_vec(rr, ok && cin[c] ? base + coff[c] : kOutside);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < RS; ++q) {
+                const int64_t row = live ? min(row_of(t, q), r1 - 1) : 0;
+                // b and nu first: loads return in order, so once the row has
+                // arrived they have too, and no register of a reduced row is
+                // still waiting for data when the buffer is refilled
+                bi[q] = a.b_in[row];
+                nui[q] = a.nu[row];
+                const __amdgpu_buffer_rsrc_t rr = row_resource(Ab + row * row_bytes, row_range);
+#pragma unroll
+                for (int c = 0; c < C; ++c) buf[q][c] = load_row_vec(rr, coff[c]);
+            }
         }
     };
 
@@ -257,8 +298,13 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
         }
 #pragma unroll
         for (int q = 0; q < RS; ++q) {
-            dot[q] = wave_total(dot[q]);
-            if (HAS_V) tdot[q] = wave_total(tdot[q]);
+            if constexpr (SUB) {
+                dot[q] = group_total<LPR>(dot[q]);
+                if (HAS_V) tdot[q] = group_total<LPR>(tdot[q]);
+            } else {
+                dot[q] = wave_total(dot[q]);
+                if (HAS_V) tdot[q] = wave_total(tdot[q]);
+            }
         }
         if (WPG > 1) {
             const int pp = (int)(t & 1);
@@ -281,6 +327,34 @@ __global__ __launch_bounds__(BLOCK) void sweep_wide(const SweepArgs a) {
                 dot[q] = d;
                 tdot[q] = td;
             }
+        }
+        if constexpr (SUB) {
+            // the groups of a wavefront settle their rows side by side, without
+            // branches (a row past the band counts as satisfied)
+#pragma unroll
+            for (int q = 0; q < RS; ++q) {
+                const bool ok = row_of(t, q) < r1;
+                double bb = bi[q];
+                if (apply_v) bb += (double)tdot[q];
+                const double r = ok ? (double)dot[q] - bb : -1.0;
+                const int si = (int)(t % KS) * SR + grp * RS + q;
+                if (ok && stage_b && gl == 0) bst[si] = bb;
+                if (ok && stage_r && gl == 0) rst[si] = r;
+                if (ok) binf = max_nan(binf, fabs(bb));
+                const bool pos = r > 0.0;
+                h += pos ? 1 : 0;
+                const double d = r / sqrt(nui[q]);
+                dmax = pos ? max_nan(dmax, d) : (r != r ? r : dmax);
+                const Acc w = pos ? (Acc)(r / nui[q]) : (Acc)0;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    Acc av[VEC];
+                    unpack<DT>(buf[q][c], av);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) yacc[c][e] = fma(w, av[e], yacc[c][e]);
+                }
+            }
+            return;
         }
 #pragma unroll
         for (int q = 0; q < RS; ++q) {

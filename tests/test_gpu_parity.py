@@ -54,11 +54,13 @@ def test_eval_sweep_matches_oracle(P, dtype, n, m):
 
 ALL_SHAPES = {  # (block, lanes per row, chunks, rows per step, depth), as compiled
     "f64": [
+            (256, 16, 1, 1, 2), (256, 16, 2, 1, 2), (256, 16, 4, 1, 2), (256, 32, 4, 1, 2),
             (256, 64, 1, 1, 2), (256, 64, 2, 1, 2), (256, 64, 4, 1, 2), (256, 64, 1, 2, 2), (256, 64, 2, 2, 2),
             (256, 64, 4, 2, 2), (256, 256, 2, 1, 2), (256, 256, 4, 1, 2), (256, 256, 8, 1, 2), (256, 256, 2, 2, 2),
             (256, 256, 4, 2, 2), (512, 512, 2, 1, 2), (512, 512, 4, 1, 2),
             (512, 512, 2, 2, 2), (512, 512, 4, 2, 2)],
     "f32": [
+            (256, 16, 1, 1, 2), (256, 16, 2, 1, 2), (256, 16, 4, 1, 2), (256, 32, 2, 1, 2), (256, 32, 4, 1, 2),
             (256, 64, 1, 1, 2), (256, 64, 2, 1, 2), (256, 64, 4, 1, 2), (256, 64, 1, 2, 2), (256, 64, 2, 2, 2),
             (256, 64, 4, 2, 2), (256, 256, 2, 1, 2), (256, 256, 4, 1, 2), (256, 256, 8, 1, 2), (256, 256, 2, 2, 2),
             (256, 256, 4, 2, 2), (256, 256, 2, 4, 2), (512, 512, 2, 1, 2), (512, 512, 4, 1, 2),
@@ -66,6 +68,7 @@ ALL_SHAPES = {  # (block, lanes per row, chunks, rows per step, depth), as compi
             (1024, 1024, 2, 1, 2), (512, 256, 8, 1, 2), (512, 256, 4, 1, 2),
             (512, 512, 4, 1, 3), (512, 512, 4, 1, 4), (1024, 1024, 2, 1, 3)],
     "bf16": [
+            (256, 16, 1, 1, 2), (256, 16, 2, 1, 2), (256, 16, 4, 1, 2), (256, 32, 2, 1, 2),
             (256, 64, 1, 1, 2), (256, 64, 2, 1, 2), (256, 64, 4, 1, 2), (256, 64, 1, 2, 2), (256, 64, 2, 2, 2),
             (256, 256, 2, 1, 2), (256, 256, 4, 1, 2), (256, 256, 2, 2, 2), (512, 512, 2, 1, 2),
             (512, 512, 4, 1, 2), (512, 512, 2, 2, 2), (1024, 1024, 1, 1, 2), (1024, 1024, 1, 1, 4),
@@ -101,6 +104,69 @@ def test_every_kernel_shape_and_grid(P, dtype):
                             label=f"{dtype} {blk}/{lpr}/{ch}/{rs}/{pd}/{il}/{grid}")
                 ys.append(g.y)
     assert len(ys) >= 4
+
+
+SHORT_ROWS = [("f32", 37, 1999), ("f32", 100, 2003), ("bf16", 90, 1501), ("bf16", 250, 999), ("f64", 29, 2011),
+              ("f64", 60, 1500), ("f64", 120, 997)]
+
+
+@pytest.mark.parametrize("dtype,n,m", SHORT_ROWS)
+def test_short_row_shapes_and_grids(P, dtype, n, m):
+    """Short rows: every compiled shape that covers the row (16 and 32 lanes
+    per row -- four or two rows to a wavefront -- and the wider ones), at
+    several grids and in both row orders, gives the oracle's sweep; ragged n
+    and m give rows past the band and chunks past the padded row."""
+    sys_ = W.gaussian(n, m, seed=n + m, dtype=dtype)
+    x = probe_point(sys_, 0.2, seed=5)
+    o = oracle.sweep(sys_.A, dtype, sys_.b, x)
+    done = 0
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype=dtype)
+        for (blk, lpr, ch, rs, pd) in ALL_SHAPES[dtype]:
+            if lpr * VEC[dtype] * ch < n or lpr * VEC[dtype] * ch > 4 * 64 * VEC[dtype]:
+                continue
+            for grid, il in ((0, 0), (7, 0), (3, 1), (2, 0)):
+                say(f"short rows dtype={dtype} n={n} m={m} block={blk} lpr={lpr} chunks={ch} grid={grid} il={il}")
+                s.set_tile(blk, lpr, ch, grid, rs, depth=pd, interleave=il)
+                g = s.eval_sweep(x)
+                check_sweep(sys_.A, dtype, o, g.y, g.h, g.max_viol, g.r,
+                            label=f"{dtype} n={n} {blk}/{lpr}/{ch}/{rs}/{pd}/{il}/{grid}")
+                done += 1
+    assert done >= 4
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f64"])
+def test_short_row_steps_with_translation(P, monkeypatch, dtype):
+    """The built-in shape of a long system of short rows (16 lanes per row),
+    on the two-kernel path: each step, with a drift schedule translating the
+    data in the same sweep, against the oracle's step from the GPU's x."""
+    monkeypatch.setenv("MODAP_RESIDENT", "0")
+    n, m = {"f32": 50, "bf16": 100, "f64": 40}[dtype], 20001
+    sys_ = W.gaussian(n, m, seed=31, dtype=dtype)
+    V = W.drift(n, 10, sigma=1e-3, seed=31)
+    lam = 0.3
+    prm = P.params(lam=lam, eps=1e-9)
+    x = sys_.z + 0.3
+    b = sys_.b.copy()
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, x0=x, dtype=dtype)
+        assert s.get_tile()["lanes_per_row"] in (16, 32)
+        s.set_drift(V)
+        for k in range(3):
+            say(f"short-row steps dtype={dtype} k={k}")
+            s.iterate(1, prm)
+            x1, b1, q = s.query(want_b=True)
+            o = oracle.sweep(sys_.A, dtype, b, x)
+            xo, status = oracle.step(o.y, o.h, 0, lam, x)
+            assert status == 0 and q.iters == k + 1
+            tol = TOL[dtype]
+            near = o.r > -tol * o.t
+            s_y = np.linalg.norm(weighted_abs_rows(sys_.A, dtype, np.where(near, o.t / o.nu, 0)))
+            assert np.linalg.norm(x1 - xo) <= tol * (np.linalg.norm(x) + lam * s_y / np.linalg.norm(o.y)), k
+            b = oracle.translate(sys_.A, dtype, b, V[k])
+            scale = np.abs(W.stored_to_f64(sys_.A, dtype)) @ np.abs(V[:k + 1]).sum(axis=0) + np.abs(sys_.b)
+            assert np.max(np.abs(b1 - b) / scale) <= tol, k
+            x = x1
 
 
 def test_box_sum_closed_form_on_gpu(P):
