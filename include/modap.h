@@ -121,7 +121,9 @@ typedef struct {
     int64_t profiled;       /* profile: number of sweeps timed in this call */
     int32_t certified;      /* 1 if the last stop was confirmed by the FP64 certificate (max_viol
                                is then its upper bound of the largest distance) */
-    int32_t pad;
+    int32_t resident;       /* iterate and solve: 1 if the iterations ran in the resident form (one
+                               launch of many iterations, the rows held in LDS, a grid barrier per
+                               iteration), 0 if in the two-kernel form; 0 from every other call */
     double b_drift;         /* last certificate: largest |b_i - exact b_i| of the working
                                right-hand side, which the certificate then corrected */
 } modap_stats;

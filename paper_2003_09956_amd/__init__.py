@@ -55,7 +55,7 @@ class Stats(C.Structure):
                 ("y_norm", C.c_double), ("b_inf", C.c_double), ("eps_abs", C.c_double),
                 ("seconds", C.c_double), ("hbm_bytes", C.c_double), ("sweep_ms", C.c_double),
                 ("reduce_ms", C.c_double), ("profiled", C.c_int64), ("certified", C.c_int32),
-                ("pad", C.c_int32), ("b_drift", C.c_double)]
+                ("resident", C.c_int32), ("b_drift", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}

@@ -1198,6 +1198,7 @@ modap_status modap_iterate(modap_ctx *c, const modap_params *p, int64_t k, modap
     fill_stats(out, kc);
     out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     out->hbm_bytes = bytes;
+    out->resident = use_resident(c, p) ? 1 : 0;
     if (p->profile && (st = profile_totals(c, ev, out))) return st;
     if (!kc.vpend_valid && kc.v_idx < 0) c->vpend_maybe = false;
     return status_of(c, kc, false);
@@ -1266,6 +1267,7 @@ modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) 
         fill_stats(out, kc);
         out->seconds = std::chrono::duration<double>(observed - t0).count();
         out->hbm_bytes = bytes;
+        out->resident = resident ? 1 : 0;
         if (p->profile && (st = profile_totals(c, ev, out))) return st;
     }
     if (!kc.vpend_valid && kc.v_idx < 0) c->vpend_maybe = false;

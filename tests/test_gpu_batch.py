@@ -245,6 +245,44 @@ def test_batch_short_rows_follow_oracle(P, monkeypatch, dtype, n, m, form):
             x = x1
 
 
+# the degenerate sizes: one column, one row, one of each, beside a system
+# that spans several items
+TINY = [(1, 1), (1, 6), (3, 1), (7, 2), (40, 900)]
+
+
+@pytest.mark.parametrize("form", ["short", "wavefront"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f64"])
+def test_batch_tiny_systems_follow_oracle(P, monkeypatch, dtype, form):
+    """Systems of one row and of one column in one batch: three steps each
+    against the oracle, a system that the oracle finds feasible stopping in
+    place."""
+    monkeypatch.setenv("MODAP_BATCH_SHORT", "1" if form == "short" else "0")
+    systems = [W.gaussian(n, m, seed=n * 11 + m, dtype=dtype) for (n, m) in TINY]
+    lam = 0.4
+    prm = P.params(lam=lam, eps=1e-12)
+    xs = [s_.z + np.random.default_rng(i).normal(scale=1.0, size=s_.n) for i, s_ in enumerate(systems)]
+    stopped = [False] * len(systems)
+    with P.Batch(dtype) as B:
+        ids = [B.add(s_.A, s_.b, x0=x) for s_, x in zip(systems, xs)]
+        for k in range(3):
+            say(f"batch tiny {dtype} form={form} k={k}")
+            B.iterate(1, prm)
+            for i, (s_, sid) in enumerate(zip(systems, ids)):
+                x1, _, q = B.query(sid)
+                if stopped[i]:
+                    assert np.array_equal(x1, xs[i])
+                    continue
+                o = oracle.sweep(s_.A, dtype, s_.b, xs[i])
+                xo, status = oracle.step(o.y, o.h, 0, lam, xs[i])
+                if status != 0:
+                    assert q.converged == 1 and np.array_equal(x1, xs[i]), (i, k)
+                    stopped[i] = True
+                    continue
+                assert q.iters == k + 1, (i, k)
+                assert np.linalg.norm(x1 - xo) <= step_bound(s_, dtype, o, xs[i], lam), (i, k)
+                xs[i] = x1
+
+
 def test_batch_solve_reaches_feasibility(P):
     """Systems of several sizes solved together, each stopping on its own:
     box-plus-sum systems (a ball of radius 100 inside, so ModAP with lambda = 1

@@ -147,6 +147,65 @@ def test_resident_and_two_kernel_paths_agree_per_step(P):
     assert d <= 15 * TOL["f32"] * (np.linalg.norm(xs["two-kernel"]) + 0.05 * 15), d
 
 
+# Edge shapes of the resident form: one row and one column; one workgroup;
+# the longest row it holds (512 columns, eight per lane, with a ragged last
+# lane group at n=449); the most workgroups (32) with full bands (FP64,
+# n=512, m=768) and with a ragged last band (m=4097 at n=64, 129 rows a band).
+RESIDENT_EDGES = [("f64", 1, 1), ("f32", 1, 1), ("bf16", 1, 1), ("f32", 5, 17), ("bf16", 449, 333),
+                  ("f64", 512, 768), ("f32", 64, 4097), ("f64", 63, 130)]
+
+
+@pytest.mark.parametrize("dtype,n,m", RESIDENT_EDGES)
+def test_resident_edge_shapes_step_like_the_oracle(P, dtype, n, m):
+    """Six single resident iterations from a point with violated rows, each
+    against the oracle's step from the GPU's previous point, and the stats
+    report that the resident form ran."""
+    sys_ = W.gaussian(n, m, seed=n * 3 + m, dtype=dtype)
+    rng = np.random.default_rng(m)
+    x = sys_.z + rng.normal(scale=2.0 / np.sqrt(n) + 0.5, size=n)
+    lam, tol = 0.7, TOL[dtype]
+    prm = P.params(lam=lam, eps=1e-12)
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, x0=x, dtype=dtype)
+        for k in range(6):
+            say(f"resident edge dtype={dtype} n={n} m={m} k={k}")
+            st = s.iterate(1, prm)
+            assert st.resident == 1
+            x1, _, st = s.query()
+            o = oracle.sweep(sys_.A, dtype, sys_.b, x)
+            xo, status = oracle.step(o.y, o.h, 0, lam, x)
+            if status != 0:      # the oracle's point is feasible: the device stops there too
+                assert st.converged == 1 and np.array_equal(x1, x)
+                break
+            assert st.iters == k + 1
+            near = o.r > -tol * o.t
+            s_y = np.linalg.norm(weighted_abs_rows(sys_.A, dtype, np.where(near, o.t / o.nu, 0)))
+            bound = tol * (np.linalg.norm(x) + lam * s_y / np.linalg.norm(o.y))
+            assert np.linalg.norm(x1 - xo) <= bound, (k, np.linalg.norm(x1 - xo), bound)
+            x = x1
+
+
+@pytest.mark.parametrize("dtype,n,m", [("f64", 513, 100), ("f64", 512, 769), ("f32", 64, 12289)])
+def test_systems_beyond_the_resident_limits_take_the_two_kernel_form(P, dtype, n, m):
+    """A row longer than 512 columns, or rows that do not fit in the LDS of
+    32 workgroups, leave the resident form; the step is the oracle's all the
+    same."""
+    sys_ = W.gaussian(n, m, seed=5, dtype=dtype)
+    x = sys_.z + np.random.default_rng(1).normal(scale=0.5, size=n)
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, x0=x, dtype=dtype)
+        say(f"beyond resident dtype={dtype} n={n} m={m}")
+        st = s.iterate(1, P.params(lam=0.7, eps=1e-12))
+        assert st.resident == 0 and st.iters == 1
+        x1 = s.query()[0]
+    o = oracle.sweep(sys_.A, dtype, sys_.b, x)
+    xo, status = oracle.step(o.y, o.h, 0, 0.7, x)
+    assert status == 0
+    near = o.r > -TOL[dtype] * o.t
+    s_y = np.linalg.norm(weighted_abs_rows(sys_.A, dtype, np.where(near, o.t / o.nu, 0)))
+    assert np.linalg.norm(x1 - xo) <= TOL[dtype] * (np.linalg.norm(x) + 0.7 * s_y / np.linalg.norm(o.y))
+
+
 def test_resident_barrier_timeout_is_reported(P, monkeypatch):
     """A wait at the grid barrier that exceeds its bound (here forced from the
     host with a bound of zero clock ticks, so the first workgroup to arrive
