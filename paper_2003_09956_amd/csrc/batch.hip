@@ -25,6 +25,7 @@
 #include "aux_launch.hpp"
 #include "batch_kernels.hpp"
 #include "host_common.hpp"
+#include "trace.hpp"
 #include "internal.hpp"
 #include "modap.h"
 
@@ -577,6 +578,7 @@ modap_status certify_stopped(modap_batch *c, const modap_params *p, int *count) 
 // Certificate of the stops of the given systems (used by the server, which
 // reads each request's state after a round).  Synchronises.
 modap_status modap_batch_certify_ids(modap_batch *c, const modap_params *p, const int64_t *ids, int64_t count) {
+    TraceRange trace_("modap_batch_certify_ids");
     if (!c) return MODAP_E_INVAL;
     DeviceGuard g(c->device);
     modap_status st;
@@ -659,6 +661,7 @@ void modap_batch_destroy(modap_batch *c) {
 
 modap_status modap_batch_add(modap_batch *c, int64_t m, int64_t n, const void *A, int64_t lda, const double *b,
                              const double *x0, int on_dev, int64_t *id) {
+    TraceRange trace_("modap_batch_add");
     if (!c) return MODAP_E_INVAL;
     if (!id) return fail(c, MODAP_E_INVAL, "id is NULL");
     const char *msg = nullptr;
@@ -749,6 +752,7 @@ modap_status modap_batch_add(modap_batch *c, int64_t m, int64_t n, const void *A
 }
 
 modap_status modap_batch_remove(modap_batch *c, int64_t id) {
+    TraceRange trace_("modap_batch_remove");
     if (!c) return MODAP_E_INVAL;
     BSys *s = find_sys(c, id);
     if (!s) return fail(c, MODAP_E_INVAL, "unknown system id");
@@ -789,6 +793,7 @@ modap_status modap_batch_set_drift(modap_batch *c, int64_t id, int64_t T, const 
 
 modap_status modap_batch_update(modap_batch *c, int64_t id, int64_t k, const int64_t *rows, const void *new_rows,
                                 const double *new_b, const double *v, int on_dev) {
+    TraceRange trace_("modap_batch_update");
     if (!c) return MODAP_E_INVAL;
     BSys *s = find_sys(c, id);
     if (!s) return fail(c, MODAP_E_INVAL, "unknown system id");
@@ -849,6 +854,7 @@ modap_status modap_batch_update(modap_batch *c, int64_t id, int64_t k, const int
 }
 
 modap_status modap_batch_iterate(modap_batch *c, const modap_params *p, int64_t k, modap_batch_stats *out) {
+    TraceRange trace_("modap_batch_iterate");
     if (!c) return MODAP_E_INVAL;
     modap_status st;
     if ((st = check_params(c, p))) return st;
@@ -881,6 +887,7 @@ modap_status modap_batch_iterate(modap_batch *c, const modap_params *p, int64_t 
 }
 
 modap_status modap_batch_solve(modap_batch *c, const modap_params *p, modap_batch_stats *out) {
+    TraceRange trace_("modap_batch_solve");
     if (!c) return MODAP_E_INVAL;
     modap_status st;
     if ((st = check_params(c, p))) return st;
@@ -943,6 +950,7 @@ modap_status modap_batch_solve(modap_batch *c, const modap_params *p, modap_batc
 }
 
 modap_status modap_batch_query(modap_batch *c, int64_t id, double *x, double *b, modap_stats *out, int on_dev) {
+    TraceRange trace_("modap_batch_query");
     if (!c) return MODAP_E_INVAL;
     BSys *s = find_sys(c, id);
     if (!s) return fail(c, MODAP_E_INVAL, "unknown system id");
@@ -999,6 +1007,7 @@ modap_status modap_batch_get_tile(modap_batch *c, modap_batch_tile *t) {
 }
 
 modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *best) {
+    TraceRange trace_("modap_batch_autotune");
     if (!c) return MODAP_E_INVAL;
     if (reps < 1) return fail(c, MODAP_E_INVAL, "reps < 1");
     DeviceGuard g(c->device);

@@ -28,6 +28,7 @@
 #include "aux_launch.hpp"
 #include "certify.hpp"
 #include "host_common.hpp"
+#include "trace.hpp"
 #include "internal.hpp"
 #include "modap.h"
 #include "resident.hpp"
@@ -949,6 +950,7 @@ void modap_destroy(modap_ctx *c) {
 
 modap_status modap_set_system(modap_ctx *c, int64_t m, int64_t n, modap_dtype storage, const void *A, int64_t lda,
                               const double *b, const double *x0, int on_dev) {
+    TraceRange trace_("modap_set_system");
     modap_status st = check_ctx(c, false);
     if (st) return st;
     const char *msg = nullptr;
@@ -1062,6 +1064,7 @@ modap_status modap_set_system(modap_ctx *c, int64_t m, int64_t n, modap_dtype st
 }
 
 modap_status modap_set_x(modap_ctx *c, const double *x, int on_dev) {
+    TraceRange trace_("modap_set_x");
     modap_status st = check_ctx(c, true);
     if (st) return st;
     if (x && !on_dev && !all_finite(x, c->n)) return fail(c, MODAP_E_INVAL, "x has a non-finite entry");
@@ -1078,6 +1081,7 @@ modap_status modap_set_x(modap_ctx *c, const double *x, int on_dev) {
 
 modap_status modap_update_coeffs(modap_ctx *c, int64_t k, const int64_t *rows, const void *new_rows,
                                  const double *new_b, const double *v, int on_dev) {
+    TraceRange trace_("modap_update_coeffs");
     modap_status st = check_ctx(c, true);
     if (st) return st;
     const char *msg = nullptr;
@@ -1122,6 +1126,7 @@ modap_status modap_update_coeffs(modap_ctx *c, int64_t k, const int64_t *rows, c
 }
 
 modap_status modap_set_drift(modap_ctx *c, int64_t T, const double *V, int64_t ldv, int on_dev) {
+    TraceRange trace_("modap_set_drift");
     modap_status st = check_ctx(c, true);
     if (st) return st;
     const char *msg = nullptr;
@@ -1165,6 +1170,7 @@ modap_status modap_set_drift(modap_ctx *c, int64_t T, const double *V, int64_t l
 }
 
 modap_status modap_iterate(modap_ctx *c, const modap_params *p, int64_t k, modap_stats *out) {
+    TraceRange trace_("modap_iterate");
     modap_status st = check_ctx(c, true);
     if (st) return st;
     if ((st = check_params(c, p))) return st;
@@ -1205,6 +1211,7 @@ modap_status modap_iterate(modap_ctx *c, const modap_params *p, int64_t k, modap
 }
 
 modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) {
+    TraceRange trace_("modap_solve");
     modap_status st = check_ctx(c, true);
     if (st) return st;
     if ((st = check_params(c, p))) return st;
@@ -1231,6 +1238,7 @@ modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) 
         int slot = 0, pending = -1;
         bool done = false;
         while (queued < total && !done) {
+            TraceRange trace_chunk("modap_solve chunk");
             const int64_t cnt = std::min(chunk, total - queued);
             if (resident) {
                 if ((st = launch_resident(c, p, 0, cnt, &bytes))) return st;
@@ -1277,6 +1285,7 @@ modap_status modap_solve(modap_ctx *c, const modap_params *p, modap_stats *out) 
 
 modap_status modap_eval_sweep(modap_ctx *c, const double *x, double *r, double *y, int64_t *h, double *max_viol,
                               int on_dev) {
+    TraceRange trace_("modap_eval_sweep");
     modap_status st = check_ctx(c, true);
     if (st) return st;
     if (!x || !y) return fail(c, MODAP_E_INVAL, "x and y are required");
@@ -1306,6 +1315,7 @@ modap_status modap_eval_sweep(modap_ctx *c, const double *x, double *r, double *
 }
 
 modap_status modap_query(modap_ctx *c, double *x, double *b, modap_stats *out, int on_dev) {
+    TraceRange trace_("modap_query");
     modap_status st = check_ctx(c, true);
     if (st) return st;
     DeviceGuard g(c->device);
@@ -1355,6 +1365,7 @@ modap_status modap_set_tile(modap_ctx *c, const modap_tile *t) {
 }
 
 modap_status modap_autotune(modap_ctx *c, int reps, modap_tile *best) {
+    TraceRange trace_("modap_autotune");
     modap_status st = check_ctx(c, true);
     if (st) return st;
     if (reps < 1) return fail(c, MODAP_E_INVAL, "reps < 1");

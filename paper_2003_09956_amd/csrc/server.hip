@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "host_common.hpp"
+#include "trace.hpp"
 #include "internal.hpp"
 #include "modap.h"
 
@@ -59,7 +60,13 @@ struct Req {
     double bytes = 0.0;
     std::string error;
     std::vector<double> x;
+    uint64_t trace = 0;   // the request's range on the tracing timeline, open until it ends
 };
+
+void end_trace(Req &r) {
+    if (r.trace) trace_stop(r.trace);
+    r.trace = 0;
+}
 
 // Device memory for the inputs of one update, reusable once the update that
 // read it has run (its event has completed).
@@ -234,6 +241,7 @@ void finish(modap_server *s, Req &r, const modap_stats &q, double now) {
     r.eps_abs = q.eps_abs;
     r.t_done = now;
     r.state = RQ_DONE;
+    end_trace(r);
 }
 
 }  // namespace
@@ -285,6 +293,7 @@ void modap_server_destroy(modap_server *s) {
     for (Req &r : s->reqs) {
         if (r.state == RQ_LIVE) drop(s, r);
         release_inputs(r);
+        end_trace(r);
     }
     modap_batch_destroy(s->batch);
     for (Stage &t : s->stages) {
@@ -300,6 +309,7 @@ void modap_server_destroy(modap_server *s) {
 modap_status modap_server_submit(modap_server *s, int64_t m, int64_t n, const void *A, const double *b,
                                  const double *x0, int64_t T, const double *V, int64_t ldv, int ptrs_on_device,
                                  double now, int64_t *ticket) {
+    TraceRange trace_("modap_server_submit");
     if (!s) return MODAP_E_INVAL;
     if (!ticket) return fail(s, MODAP_E_INVAL, "ticket is NULL");
     const char *msg = nullptr;
@@ -352,6 +362,7 @@ modap_status modap_server_submit(modap_server *s, int64_t m, int64_t n, const vo
         }
     }
     r.t_submit = now;
+    r.trace = trace_start("modap request");
     *ticket = (int64_t)s->reqs.size();
     s->reqs.push_back(std::move(r));
     s->pending.push_back(*ticket);
@@ -361,6 +372,7 @@ modap_status modap_server_submit(modap_server *s, int64_t m, int64_t n, const vo
 modap_status modap_server_update(modap_server *s, int64_t ticket, int64_t k, const int64_t *rows,
                                  const void *new_rows, const double *new_b, const double *translate_v,
                                  int ptrs_on_device) {
+    TraceRange trace_("modap_server_update");
     if (!s) return MODAP_E_INVAL;
     if (ticket < 0 || ticket >= (int64_t)s->reqs.size()) return fail(s, MODAP_E_INVAL, "unknown ticket");
     Req &r = s->reqs[(size_t)ticket];
@@ -411,6 +423,7 @@ modap_status modap_server_update(modap_server *s, int64_t ticket, int64_t k, con
 }
 
 modap_status modap_server_round(modap_server *s, double now, int64_t *outstanding) {
+    TraceRange trace_("modap_server_round");
     if (!s) return MODAP_E_INVAL;
     DeviceGuard g(s->device);
     const auto t0 = std::chrono::steady_clock::now();
@@ -431,6 +444,7 @@ modap_status modap_server_round(modap_server *s, double now, int64_t *outstandin
             r.state = RQ_FAILED;
             r.status = -(int32_t)st;
             if (r.error.empty()) r.error = "admission failed";
+            end_trace(r);
         }
     }
     // the same number of iterations for every live request
@@ -524,6 +538,7 @@ modap_status modap_server_info(modap_server *s, int64_t ticket, modap_request_in
 }
 
 modap_status modap_server_result(modap_server *s, int64_t ticket, double *x) {
+    TraceRange trace_("modap_server_result");
     if (!s) return MODAP_E_INVAL;
     if (ticket < 0 || ticket >= (int64_t)s->reqs.size() || !x) return fail(s, MODAP_E_INVAL, "unknown ticket");
     const Req &r = s->reqs[(size_t)ticket];

@@ -103,3 +103,44 @@ def test_product_never_imports_the_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".inc", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower(), f
+
+
+C_TYPES = {"int32_t": C.c_int32, "int64_t": C.c_int64, "double": C.c_double}
+
+
+@pytest.mark.parametrize("cls,name", [("Params", "modap_params"), ("Stats", "modap_stats"), ("Tile", "modap_tile"),
+                                      ("BatchStats", "modap_batch_stats"), ("BatchTile", "modap_batch_tile"),
+                                      ("RequestInfo", "modap_request_info")])
+def test_binding_structs_follow_the_header(cls, name):
+    """Every struct the binding passes across the boundary has the header's
+    fields, in the header's order, with the header's types."""
+    import paper_2003_09956_amd as P
+    code = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r";", code).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        for nm in names.split(","):
+            arr = re.fullmatch(r"\s*(\w+)\s*\[(\d+)\]\s*", nm)
+            fields.append((arr.group(1), C_TYPES[ctype] * int(arr.group(2))) if arr else (nm.strip(), C_TYPES[ctype]))
+    # (a field named by a Python keyword carries a trailing underscore)
+    got = [(f.rstrip("_"), t) for f, t in getattr(P, cls)._fields_]
+    assert [f for f, _ in got] == [f for f, _ in fields]
+    for (f, t), (_, u) in zip(got, fields):
+        assert C.sizeof(t) == C.sizeof(u) and getattr(t, "_type_", t) == getattr(u, "_type_", u), f
+
+
+def test_library_records_its_tracing_ranges():
+    """The library links the ROCm tracing-range API (one range per call, per
+    queued chunk of a solve, per served request)."""
+    import paper_2003_09956_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("library not built")
+    out = subprocess.run(["readelf", "-d", P.LIB_PATH], capture_output=True, text=True).stdout
+    assert "librocprofiler-sdk-roctx" in out
+    und = subprocess.run(["nm", "-D", "--undefined-only", P.LIB_PATH], capture_output=True, text=True).stdout
+    for sym in ("roctxRangePushA", "roctxRangePop", "roctxRangeStartA", "roctxRangeStop"):
+        assert sym in und, sym
