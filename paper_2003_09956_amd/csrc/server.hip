@@ -96,8 +96,9 @@ struct modap_server {
     hipStream_t copy_stream = nullptr;    // staging of device-side update inputs
     std::vector<Stage> stages;
     int batch_live = 0;
-    std::vector<Req> reqs;
+    std::vector<Req> reqs;              // every request, indexed by ticket
     std::deque<int64_t> pending;
+    std::vector<int64_t> live_ids;      // tickets of the live requests, in admission order
     double bytes = 0.0;
     int64_t rounds = 0;
     std::string err;
@@ -165,6 +166,13 @@ void release_inputs(Req &r) {
     free_dev(r.db);
     free_dev(r.dx0);
     free_dev(r.dV);
+}
+
+// Remove retired tickets from the list of live requests.
+void compact_live(modap_server *s) {
+    s->live_ids.erase(std::remove_if(s->live_ids.begin(), s->live_ids.end(),
+                                     [s](int64_t id) { return s->reqs[(size_t)id].state != RQ_LIVE; }),
+                      s->live_ids.end());
 }
 
 void drop(modap_server *s, Req &r) {
@@ -428,6 +436,7 @@ modap_status modap_server_round(modap_server *s, double now, int64_t *outstandin
     DeviceGuard g(s->device);
     const auto t0 = std::chrono::steady_clock::now();
     modap_status st;
+    compact_live(s);
     // admission in arrival order while the footprint fits; a long-row request
     // beyond max_long waits, and the requests behind it may pass it
     for (auto it = s->pending.begin(); it != s->pending.end();) {
@@ -437,9 +446,11 @@ modap_status modap_server_round(modap_server *s, double now, int64_t *outstandin
             continue;
         }
         if (!admissible(s->used, r.footprint, s->budget, s->live, s->max_live)) break;
+        const int64_t ticket = *it;
         it = s->pending.erase(it);
         st = admit(s, r, now + elapsed_since(t0));
         release_inputs(r);  // the request's data now live in the batch or its context
+        if (!st) s->live_ids.push_back(ticket);
         if (st) {
             r.state = RQ_FAILED;
             r.status = -(int32_t)st;
@@ -451,18 +462,25 @@ modap_status modap_server_round(modap_server *s, double now, int64_t *outstandin
     const int64_t k = s->iters_per_round;
     if (s->batch_live > 0 && (st = modap_batch_iterate(s->batch, &s->params, k, nullptr)))
         return fail(s, st, modap_batch_last_error(s->batch));
-    for (Req &r : s->reqs)
+    // (the list is compacted at the end of a round; an error return may leave
+    // retired tickets in it until then, hence the state checks)
+    for (int64_t id : s->live_ids) {
+        Req &r = s->reqs[(size_t)id];
         if (r.state == RQ_LIVE && !r.in_batch && (st = modap_iterate(r.ctx, &s->params, k, nullptr)))
             return fail(s, st, modap_last_error(r.ctx));
+    }
     // wait, then retire the requests that stopped
     HIP_TRY(s, hipStreamSynchronize(s->batch_stream));
-    for (Req &r : s->reqs)
+    for (int64_t id : s->live_ids) {
+        const Req &r = s->reqs[(size_t)id];
         if (r.state == RQ_LIVE && !r.in_batch) HIP_TRY(s, hipStreamSynchronize(r.stream));
+    }
     // Stops of batched requests get their FP64 certificate here (a request
     // with a context of its own had it queued after its iterations).
     if (s->params.certify && s->batch_live > 0) {
         std::vector<int64_t> ids;
-        for (Req &r : s->reqs) {
+        for (int64_t id : s->live_ids) {
+            Req &r = s->reqs[(size_t)id];
             if (r.state != RQ_LIVE || !r.in_batch) continue;
             modap_stats q{};
             if ((st = modap_batch_query(s->batch, r.bid, nullptr, nullptr, &q, 0)))
@@ -473,7 +491,8 @@ modap_status modap_server_round(modap_server *s, double now, int64_t *outstandin
             return fail(s, st, modap_batch_last_error(s->batch));
     }
     const double t_end = now + elapsed_since(t0);
-    for (Req &r : s->reqs) {
+    for (int64_t id : s->live_ids) {
+        Req &r = s->reqs[(size_t)id];
         if (r.state != RQ_LIVE) continue;
         modap_stats q{};
         st = r.in_batch ? modap_batch_query(s->batch, r.bid, nullptr, nullptr, &q, 0)
@@ -494,12 +513,9 @@ modap_status modap_server_round(modap_server *s, double now, int64_t *outstandin
         if (!stopped) r.status = 4;  // the step limit of the server's parameters
         drop(s, r);
     }
+    compact_live(s);
     ++s->rounds;
-    if (outstanding) {
-        int64_t cnt = (int64_t)s->pending.size();
-        for (const Req &r : s->reqs) cnt += r.state == RQ_LIVE;
-        *outstanding = cnt;
-    }
+    if (outstanding) *outstanding = (int64_t)s->pending.size() + (int64_t)s->live_ids.size();
     return MODAP_OK;
 }
 
