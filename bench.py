@@ -146,7 +146,9 @@ def batch_source_hash() -> str:
 
 
 def batch_tile_str(tile) -> str:
-    return ",".join(str(k) for k in tile["item_kib"]) + f",{tile['grid']}"
+    """k1,k2,k3,k4,grid, then ,min_items when it is not the library's choice (0)."""
+    s = ",".join(str(k) for k in tile["item_kib"]) + f",{tile['grid']}"
+    return s + (f",{tile['min_items']}" if tile.get("min_items", 0) else "")
 
 
 BATCH_FAMILY_FILES = {"batch-f32-512": "sweep_batch_f32_512sys", "batch-f32-512-n256": "sweep_batch_f32_512x256"}
@@ -286,8 +288,9 @@ def main():
                     help="single-system workloads: run the sweep autotuner before timing (default: the library's "
                          "built-in shape, so that a kernel trace of the same command names the same kernel)")
     ap.add_argument("--batch-tile", type=str, default=None,
-                    help="batched workload: force item_kib for the four row-length buckets and the grid, "
-                         "k1,k2,k3,k4,grid (skips the batch autotuner)")
+                    help="batched workload: force item_kib for the four row-length buckets, the grid and "
+                         "optionally the least items per system, k1,k2,k3,k4,grid[,min_items] (skips the "
+                         "batch autotuner)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes five times (counter calibration)")
     args = ap.parse_args()
@@ -613,8 +616,10 @@ def bench_batch(args, P, W, torch):
         del A, b
     torch.cuda.synchronize()
     if args.batch_tile:
-        *kib, grid = (int(v) for v in args.batch_tile.split(","))
-        B.set_tile(item_kib=kib, grid=grid)
+        v = [int(x) for x in args.batch_tile.split(",")]
+        if len(v) not in (5, 6):
+            raise SystemExit("--batch-tile takes k1,k2,k3,k4,grid[,min_items]")
+        B.set_tile(item_kib=v[:4], grid=v[4], min_items=v[5] if len(v) == 6 else 0)
         tile = B.get_tile()
         log("batch tile (forced)", tile)
     else:
@@ -680,7 +685,7 @@ def batch_time_to_feasible(args, P, W, torch, shapes, tile):
         ids.append(B.add(A, b))
         B.set_drift(ids[-1], drift_of(i, n))
         del A, b
-    B.set_tile(item_kib=tile["item_kib"], grid=tile["grid"])
+    B.set_tile(item_kib=tile["item_kib"], grid=tile["grid"], min_items=tile.get("min_items", 0))
     torch.cuda.synchronize()
     bst = B.solve(prm)
     steps = [int(B.query(sid, want_x=False)[2].iters) for sid in ids]

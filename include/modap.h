@@ -283,12 +283,15 @@ typedef struct {
 
 /* Batch tuning: target bytes of A per work item for each row-length bucket
  * (rows of at most 64*VEC*C elements, C = 1, 2, 4, 8, VEC = 16 bytes / element
- * size), and the persistent grid (0 = one workgroup per CU).  A
- * system smaller than 8 items of that size is cut into 8 items of at least
- * 32 KiB instead; the cut of a system never depends on the other systems. */
+ * size), the persistent grid, and the least number of items per system.  A
+ * system smaller than min_items items of its bucket's size is cut into
+ * min_items items of at least 32 KiB instead.  The cut of a system depends on
+ * the system and this tile only, never on the other systems; a system's
+ * results depend on its cut (the order in which item partials are added). */
 typedef struct {
     int32_t item_kib[4];    /* largest KiB of A per work item, buckets C = 1, 2, 4, 8 (>= 1) */
-    int32_t grid;           /* workgroups of the batch sweep (0: the library's choice) */
+    int32_t grid;           /* workgroups of the batch sweep (0: every workgroup that can be resident) */
+    int32_t min_items;      /* items per system at least, 1 .. 64 (0: the library's choice, 8) */
 } modap_batch_tile;
 
 /* Create an empty batch for systems stored in `storage` on HIP device

@@ -82,10 +82,10 @@ class BatchStats(C.Structure):
 
 
 class BatchTile(C.Structure):
-    _fields_ = [("item_kib", C.c_int32 * 4), ("grid", C.c_int32)]
+    _fields_ = [("item_kib", C.c_int32 * 4), ("grid", C.c_int32), ("min_items", C.c_int32)]
 
     def as_dict(self):
-        return {"item_kib": list(self.item_kib), "grid": self.grid}
+        return {"item_kib": list(self.item_kib), "grid": self.grid, "min_items": self.min_items}
 
 
 class RequestInfo(C.Structure):
@@ -515,15 +515,15 @@ class Batch:
         self._check(lib().modap_batch_query(self._h, int(sid), px, pb, C.byref(out), 0))
         return x, b, out
 
-    def set_tile(self, item_kib=None, grid=0):
+    def set_tile(self, item_kib=None, grid=0, min_items=0):
         if item_kib is None:
-            # the library's built-in item sizes, with the grid asked for
+            # the library's built-in item sizes, with the grid and item count asked for
             self._check(lib().modap_batch_set_tile(self._h, None))
-            if grid == 0:
+            if grid == 0 and min_items == 0:
                 return
             item_kib = self.get_tile()["item_kib"]
         kib = list(item_kib)
-        t = BatchTile((C.c_int32 * 4)(*[int(v) for v in kib]), int(grid))
+        t = BatchTile((C.c_int32 * 4)(*[int(v) for v in kib]), int(grid), int(min_items))
         self._check(lib().modap_batch_set_tile(self._h, C.byref(t)))
 
     def get_tile(self):

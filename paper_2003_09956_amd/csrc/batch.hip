@@ -61,7 +61,7 @@ int bucket_of(int C) { return C == 1 ? 0 : C == 2 ? 1 : C == 4 ? 2 : 3; }
 // items for the longest rows took the sweep from 2.51 to 2.48 ms (fewer items,
 // each with a cost of its own; the largest are handed out first, so they do
 // not end the sweep late).
-constexpr modap_batch_tile kBuiltinTile{{512, 2048, 4096, 8192}, 0};
+constexpr modap_batch_tile kBuiltinTile{{512, 2048, 4096, 8192}, 0, 0};
 
 struct modap_batch {
     int device = 0;
@@ -209,18 +209,21 @@ modap_status ensure_buf(modap_batch *c, P *&p, size_t &cap, size_t count) {
 }
 
 // Rows of one work item of a system: about item_kib KiB of A, but a small
-// system is still cut into kMinItems items of at least kMinItemKib KiB, so
+// system is still cut into min_items items of at least kMinItemKib KiB, so
 // that a batch of few systems spreads over the device; a multiple of the
 // wavefronts of a workgroup.  The partition depends on the system and the
 // tile only, never on the other systems of the batch.  Eight items per system
-// rather than sixteen: on a batch of many systems every item costs a few
-// microseconds of its own, and four to eight measured best.
+// by default: a batch of few systems needs them to fill the device, while on
+// a batch of many small systems every item costs a few microseconds of its
+// own and fewer measure faster (the autotuner tries 1 to 16).
 constexpr int64_t kMinItems = 8;
 constexpr int64_t kMinItemKib = 32;
+constexpr int32_t kMaxMinItems = 64;
 int64_t rows_per_item(const modap_batch *c, const BSys &s) {
     const int64_t sys_kib = s.m * s.ldA * (int64_t)c->es / 1024;
     const int64_t cap = std::max<int32_t>(1, c->tile.item_kib[bucket_of(s.C)]);
-    const int64_t kib = std::min(cap, std::max(kMinItemKib, sys_kib / kMinItems));
+    const int64_t least = c->tile.min_items > 0 ? c->tile.min_items : kMinItems;
+    const int64_t kib = std::min(cap, std::max(kMinItemKib, sys_kib / least));
     int64_t r = kib * 1024 / (s.ldA * (int64_t)c->es);
     r = std::max<int64_t>(kBatchWaves, (r + kBatchWaves - 1) / kBatchWaves * kBatchWaves);
     return std::min<int64_t>(r, (s.m + kBatchWaves - 1) / kBatchWaves * kBatchWaves);
@@ -993,6 +996,8 @@ modap_status modap_batch_set_tile(modap_batch *c, const modap_batch_tile *t) {
         for (int q = 0; q < 4; ++q)
             if (t->item_kib[q] < 1) return fail(c, MODAP_E_INVAL, "item_kib must be >= 1");
         if (t->grid < 0) return fail(c, MODAP_E_INVAL, "grid must be >= 0");
+        if (t->min_items < 0 || t->min_items > kMaxMinItems)
+            return fail(c, MODAP_E_INVAL, "min_items must be in 0 .. 64");
         c->tile = *t;
     }
     c->dirty = true;
@@ -1055,23 +1060,58 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
     // a work item costs a few microseconds beyond its rows (queue, state,
     // staging, partial): large items pay it rarely, small ones balance better
     const int sizes[] = {64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384};
-    for (int q = 0; q < 4; ++q) {
-        if (!present[q]) continue;
+    auto tune_sizes = [&]() -> modap_status {
+        for (int q = 0; q < 4; ++q) {
+            if (!present[q]) continue;
+            float win = 0.f;
+            modap_status s2;
+            if ((s2 = time_tile(cur, &win))) return s2;
+            int pick = cur.item_kib[q];
+            for (int kib : sizes) {
+                if (kib == cur.item_kib[q]) continue;
+                modap_batch_tile t = cur;
+                t.item_kib[q] = kib;
+                float ms = 0.f;
+                if ((s2 = time_tile(t, &ms))) return s2;
+                if (ms < win * kMargin) {
+                    win = ms;
+                    pick = kib;
+                }
+            }
+            cur.item_kib[q] = pick;
+        }
+        return MODAP_OK;
+    };
+    if ((st = tune_sizes())) return st;
+    // Then the least number of items per system: small systems of a large
+    // batch run faster in fewer, larger items.  The counts are compared with
+    // every present bucket's item size lifted to the largest, so that the
+    // count is what cuts the small systems; if another count wins, the sizes
+    // are tuned again under it.
+    {
+        modap_batch_tile lifted = cur;
+        for (int q = 0; q < 4; ++q)
+            if (present[q]) lifted.item_kib[q] = sizes[sizeof(sizes) / sizeof(sizes[0]) - 1];
+        const int inc = cur.min_items > 0 ? cur.min_items : (int)kMinItems;
         float win = 0.f;
-        if ((st = time_tile(cur, &win))) return st;
-        int pick = cur.item_kib[q];
-        for (int kib : sizes) {
-            if (kib == cur.item_kib[q]) continue;
-            modap_batch_tile t = cur;
-            t.item_kib[q] = kib;
+        if ((st = time_tile(lifted, &win))) return st;
+        int pick = inc;
+        for (int mi : {1, 2, 4, 8, 16}) {
+            if (mi == inc) continue;
+            modap_batch_tile t = lifted;
+            t.min_items = mi;
             float ms = 0.f;
             if ((st = time_tile(t, &ms))) return st;
             if (ms < win * kMargin) {
                 win = ms;
-                pick = kib;
+                pick = mi;
             }
         }
-        cur.item_kib[q] = pick;
+        if (pick != inc) {
+            cur = lifted;
+            cur.min_items = pick;
+            if ((st = tune_sizes())) return st;
+        }
     }
     float win = 0.f;
     if ((st = time_tile(cur, &win))) return st;   // grid 0: every resident workgroup

@@ -323,7 +323,7 @@ def test_batch_autotune_keeps_results(P):
         ids = [B.add(s.A, s.b, x0=s.z + 0.3) for s in systems]
         say("batch autotune")
         best = B.autotune(2)
-        assert best["grid"] >= 0 and all(k >= 32 for k in best["item_kib"])
+        assert best["grid"] >= 0 and all(k >= 32 for k in best["item_kib"]) and 0 <= best["min_items"] <= 16
         assert B.get_tile() == best
         B.iterate(1, P.params(lam=lam, eps=1e-9))
         for sid, sys_ in zip(ids, systems):
@@ -375,6 +375,40 @@ def test_full_size_batch_c4(P):
             assert B.query(sid, want_x=False)[2].iters == 1
 
 
+@pytest.mark.parametrize("min_items", [1, 2, 16])
+def test_batch_items_per_system_follow_oracle(P, min_items):
+    """The cut of each system into work items (whole systems as one item, two,
+    or sixteen of at least 32 KiB) changes only the order in which item
+    partials are added: two steps of every system against the oracle, and a
+    system's bits the same alone and in the mix at each cut."""
+    shapes = [(256, 2048), (100, 301), (1000, 2500), (40, 64)]
+    systems = [W.gaussian(n, m, seed=n + 3 * m, dtype="f32") for (n, m) in shapes]
+    lam = 0.3
+    prm = P.params(lam=lam, eps=1e-9)
+    xs = [s_.z + 0.3 for s_ in systems]
+    with P.Batch("f32") as B:
+        B.set_tile(item_kib=[16384] * 4, min_items=min_items)
+        assert B.get_tile()["min_items"] == min_items
+        ids = [B.add(s_.A, s_.b, x0=x) for s_, x in zip(systems, xs)]
+        for k in range(2):
+            say(f"batch min_items={min_items} k={k}")
+            B.iterate(1, prm)
+            for i, (s_, sid) in enumerate(zip(systems, ids)):
+                x1, _, q = B.query(sid)
+                o = oracle.sweep(s_.A, "f32", s_.b, xs[i])
+                xo, status = oracle.step(o.y, o.h, 0, lam, xs[i])
+                assert status == 0 and q.iters == k + 1
+                assert np.linalg.norm(x1 - xo) <= step_bound(s_, "f32", o, xs[i], lam), (i, k)
+                xs[i] = x1
+    with P.Batch("f32") as B:
+        B.set_tile(item_kib=[16384] * 4, min_items=min_items)
+        sid = B.add(systems[2].A, systems[2].b, x0=systems[2].z + 0.3)
+        B.iterate(1, prm)                   # the same call boundaries as above
+        B.iterate(1, prm)
+        alone = B.query(sid)[0]
+    assert np.array_equal(alone, xs[2])
+
+
 def test_batch_errors(P):
     with P.Batch("f32") as B:
         with pytest.raises(P.ModapError, match="E_STATE"):
@@ -392,3 +426,6 @@ def test_batch_errors(P):
         B.remove(sid)
         with pytest.raises(P.ModapError, match="E_INVAL"):
             B.remove(sid)
+        for bad in (-1, 65):                               # items per system out of range
+            with pytest.raises(P.ModapError, match="E_INVAL"):
+                B.set_tile(item_kib=[512, 2048, 4096, 8192], min_items=bad)
