@@ -560,32 +560,47 @@ __global__ __launch_bounds__(256) void sweep_batch(const BatchArgs a) {
 // Column sums of a system's item partials (item order, FP64), the previous
 // step made permanent in x, and the next sweep's working vectors.  One
 // workgroup per 64-column block; block 0 of a system also forms its totals.
-// Workgroup 0 empties the item queue for the next sweep.
+// Workgroup 0 empties the item queue for the next sweep.  The work of a block
+// is small, so its time is the chain of dependent loads: the system's fields
+// come in one request, and then the state, the partials and every vector of
+// the block's columns that does not depend on the state are requested
+// together; the state only decides whether they are used.  Only the drift
+// rows, whose index is in the state, wait for it.
 template <typename Acc>
 __global__ __launch_bounds__(256) void reduce_batch(const BatchArgs a, const BatchCol *cols) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.queue = 0;
     const BatchCol cb = cols[blockIdx.x];
-    const BatchSys &S = a.sys[cb.sys];
-    const State P = S.ctl->st[slot_of(a.j - 1)];
-    if (P.status != ST_RUNNING) return;
+    const BatchSys S = a.sys[cb.sys];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t col = (int64_t)cb.blk * 64 + lane;
+    const bool in = col < S.n;
+    const State P = S.ctl->st[slot_of(a.j - 1)];
+    const int64_t sched_len = S.ctl->sched_len;
     const Acc *part = reinterpret_cast<const Acc *>(a.part) + S.part0;
     double acc = 0.0;
-    if (col < S.n)
+    if (in)
         for (int64_t q = wave; q < S.nitems; q += kBatchWaves) acc += (double)part[q * S.ldA + col];
-    __shared__ double sh[kBatchWaves][64];
-    sh[wave][lane] = acc;
-    __shared__ int64_t hw[kBatchWaves];
-    __shared__ double dw[kBatchWaves], bw[kBatchWaves];
-    if (cb.blk == 0) {
-        int64_t h = 0;
-        double dm = 0.0, bm = 0.0;
+    double xo = 0.0, yprev = 0.0, ws = 0.0, vp = 0.0;
+    if (wave == 0 && in) {
+        xo = S.x[col];
+        yprev = S.y[col];
+        ws = S.wsum[col];
+        vp = S.vpend[col];
+    }
+    int64_t h = 0;
+    double dm = 0.0, bm = 0.0;
+    if (cb.blk == 0)
         for (int64_t q = tid; q < S.nitems; q += 256) {
             h += a.h_part[S.item0 + q];
             dm = max_nan(dm, a.dmax_part[S.item0 + q]);
             bm = max_nan(bm, a.binf_part[S.item0 + q]);
         }
+    if (P.status != ST_RUNNING) return;
+    __shared__ double sh[kBatchWaves][64];
+    sh[wave][lane] = acc;
+    __shared__ int64_t hw[kBatchWaves];
+    __shared__ double dw[kBatchWaves], bw[kBatchWaves];
+    if (cb.blk == 0) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             h += __shfl_xor(h, o, 64);
@@ -604,17 +619,15 @@ __global__ __launch_bounds__(256) void reduce_batch(const BatchArgs a, const Bat
 #pragma unroll
     for (int g = 0; g < kBatchWaves; ++g) yv += sh[g][lane];
     double sq = 0.0;
-    if (col < S.n) {
-        double xo = S.x[col];
+    if (in) {
         if (a.apply_step && P.s != 0.0) {
-            xo = step_point(xo, P.s, S.y[col]);
+            xo = step_point(xo, P.s, yprev);
             S.x[col] = xo;
         }
         // the translation the sweep applied joins the FP64 sum of translations
         const bool ap = P.vpend_valid != 0, ar = S.V && P.v_idx >= 0;
-        if (ap || ar)
-            S.wsum[col] += (ap ? S.vpend[col] : 0.0) + (ar ? S.V[P.v_idx * S.ldA + col] : 0.0);
-        const bool due = S.V && P.sched_pos < S.ctl->sched_len;
+        if (ap || ar) S.wsum[col] = ws + ((ap ? vp : 0.0) + (ar ? S.V[P.v_idx * S.ldA + col] : 0.0));
+        const bool due = S.V && P.sched_pos < sched_len;
         Acc *w = reinterpret_cast<Acc *>(S.work);
         w[col] = (Acc)xo;
         w[S.ldA + col] = due ? (Acc)S.V[P.sched_pos * S.ldA + col] : (Acc)0;
