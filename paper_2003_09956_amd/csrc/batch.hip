@@ -1016,6 +1016,18 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
     if (!c) return MODAP_E_INVAL;
     if (reps < 1) return fail(c, MODAP_E_INVAL, "reps < 1");
     DeviceGuard g(c->device);
+    // on any failure the batch keeps the tile it had
+    struct Restore {
+        modap_batch *c;
+        modap_batch_tile t;
+        bool armed;
+        ~Restore() {
+            if (armed) {
+                c->tile = t;
+                c->dirty = true;
+            }
+        }
+    } restore{c, c->tile, true};
     modap_status st;
     if ((st = rebuild(c))) return st;
     if (c->h_sys.empty()) return fail(c, MODAP_E_STATE, "the batch has no systems");
@@ -1131,6 +1143,7 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
     c->dirty = true;
     if ((st = rebuild(c))) return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    restore.armed = false;
     if (best) *best = c->tile;
     return MODAP_OK;
 }

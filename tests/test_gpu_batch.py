@@ -413,6 +413,10 @@ def test_batch_errors(P):
     with P.Batch("f32") as B:
         with pytest.raises(P.ModapError, match="E_STATE"):
             B.iterate(1)
+        B.set_tile(item_kib=[256, 1024, 2048, 4096], grid=0, min_items=4)
+        with pytest.raises(P.ModapError, match="E_STATE"):  # nothing to tune on; the tile stays
+            B.autotune(1)
+        assert B.get_tile() == {"item_kib": [256, 1024, 2048, 4096], "grid": 0, "min_items": 4}
         sys_ = W.gaussian(3000, 10, seed=1, dtype="f32")
         with pytest.raises(P.ModapError, match="E_INVAL"):
             B.add(sys_.A, sys_.b)                       # rows longer than the batched sweep covers
