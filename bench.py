@@ -134,7 +134,8 @@ def counters_path(dt: str, n: int, m: int, tile: str) -> str:
     return os.path.join(ROOT, "profiles", f"sweep_wide_{dt}_n{n}_m{m}_tile{tile.replace(',', '-')}_counters.txt")
 
 
-BATCH_SOURCES = ["paper_2003_09956_amd/csrc/batch_kernels.hpp", "paper_2003_09956_amd/csrc/batch.hip",
+# what fixes the batched sweep's traffic: its kernel sources and the host rules that cut systems into items
+BATCH_SOURCES = ["paper_2003_09956_amd/csrc/batch_kernels.hpp", "paper_2003_09956_amd/csrc/batch_plan.hpp",
                  "paper_2003_09956_amd/csrc/modap_device.hpp", "paper_2003_09956_amd/csrc/sweep_wide.hpp"]
 
 
@@ -270,7 +271,8 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + sorted(MULTI), default="bf16-16384x65536",
                     help="system the timed steps run on (default: the BF16 n=16384 m=65536 system, 2 GiB)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="single-system workloads: skip the second line of the FP32 n=8192 m=16384 system")
+                    help="single-system workloads: skip the second line of the FP32 n=8192 m=16384 system (and, "
+                         "on the default BF16 workload, the batched and served families measured after it)")
     ap.add_argument("--drift-speeds", action="store_true",
                     help="BF16 workload: chase at drift norms 1e-5, 1e-4 and 1e-3 (default: 1e-4 only)")
     ap.add_argument("--rate", type=float, default=5.0, help="serving: Poisson arrival rate per second")
@@ -371,6 +373,22 @@ def main():
             Ah = A_d.view(torch.int16).cpu().numpy().view(np.uint16) if dt == "bf16" else A_d.cpu().numpy()
             sys_ = W.System(Ah, b_d.cpu().numpy(), np.zeros(n), dt)
         line.update(cpu_lines(args, sys_, V, res["bytes_per_step"], n, m, dt))
+    if dt == "bf16" and not args.no_extra and not args.no_ttf:
+        # the batched and served families, measured in the same run: their
+        # lines (without the keys this line already carries) as objects of it
+        import copy
+        A_d = b_d = A_in = b_in = sys_ = None   # the BF16 system's device memory goes back
+        torch.cuda.empty_cache()
+        for wl, key, fn in (("batch-f32-512", "batch_f32_512", bench_batch),
+                            ("serve-bf16-poisson", "serve_bf16_poisson", bench_serve)):
+            a2 = copy.copy(args)
+            a2.workload, a2.batch_tile = wl, None
+            log(f"--- {wl} ---")
+            sub = fn(a2, P, W, torch, emit=False)
+            for k in ("metric", "unit", "n_gpus", "higher_is_better", "scaling", "vs_baseline"):
+                sub.pop(k, None)
+            line[key] = sub
+            torch.cuda.empty_cache()
     print(json.dumps(line), flush=True)
 
 
@@ -599,7 +617,7 @@ def cpu_lines(args, sys_, V, bytes_per_step, n, m, dt):
     return out
 
 
-def bench_batch(args, P, W, torch):
+def bench_batch(args, P, W, torch, emit=True):
     """One step = one iteration of all 512 systems (one sweep launch, one
     reduction launch); data generated on the device with a seeded generator."""
     K, WU = args.steps, args.warmup
@@ -660,7 +678,9 @@ def bench_batch(args, P, W, torch):
     }
     if not args.no_ttf:
         line["time_to_feasible"] = batch_time_to_feasible(args, P, W, torch, shapes, tile)
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
 
 
 def batch_time_to_feasible(args, P, W, torch, shapes, tile):
@@ -916,7 +936,7 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8, 
     return out, tot["hbm_bytes"], wall, rounds
 
 
-def bench_serve(args, P, W, torch):
+def bench_serve(args, P, W, torch, emit=True):
     """Served BF16 (continuous batching) against the same BF16 requests served
     one at a time (a queue alone) and the plain FP64 form served one at a
     time, on the same arrival process and update schedule."""
@@ -948,7 +968,9 @@ def bench_serve(args, P, W, torch):
         "time_to_feasible": {"served_bf16_continuous_batching": served, "bf16_queue_one_at_a_time": queue,
                              "fp64_single_system_one_at_a_time": plain},
     }
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
 
 
 if __name__ == "__main__":

@@ -26,6 +26,7 @@
 #include "batch_kernels.hpp"
 #include "host_common.hpp"
 #include "trace.hpp"
+#include "batch_plan.hpp"
 #include "internal.hpp"
 #include "modap.h"
 
@@ -50,8 +51,6 @@ struct BSys {
 };
 
 constexpr int kBuckets[4] = {1, 2, 4, 8};
-
-int bucket_of(int C) { return C == 1 ? 0 : C == 2 ? 1 : C == 4 ? 2 : 3; }
 
 }  // namespace
 
@@ -169,15 +168,8 @@ BSys *find_sys(modap_batch *c, int64_t id) {
 // ones a wavefront each (RPW = 1); C is the lane's 16-byte chunks of a row.
 // MODAP_BATCH_SHORT=0 keeps every row on a wavefront of its own.
 void kernel_form(int dt, const BSys &s, int32_t *rpw, int32_t *chunks) {
-    *rpw = 1;
-    *chunks = s.C;
-    if (s.C != 1) return;
     const char *e = std::getenv("MODAP_BATCH_SHORT");
-    if (e && e[0] == '0') return;
-    *rpw = 4;
-    const int64_t per = 16 * (int64_t)vec_elems(dt);
-    const int64_t k = (s.ldA + per - 1) / per;
-    *chunks = k <= 1 ? 1 : k <= 2 ? 2 : 4;
+    plan_row_form(s.ldA, (int64_t)vec_elems(dt), s.C, !(e && e[0] == '0'), rpw, chunks);
 }
 
 // Largest row (padded length) the batched sweep covers.
@@ -208,25 +200,9 @@ modap_status ensure_buf(modap_batch *c, P *&p, size_t &cap, size_t count) {
     return MODAP_OK;
 }
 
-// Rows of one work item of a system: about item_kib KiB of A, but a small
-// system is still cut into min_items items of at least kMinItemKib KiB, so
-// that a batch of few systems spreads over the device; a multiple of the
-// wavefronts of a workgroup.  The partition depends on the system and the
-// tile only, never on the other systems of the batch.  Eight items per system
-// by default: a batch of few systems needs them to fill the device, while on
-// a batch of many small systems every item costs a few microseconds of its
-// own and fewer measure faster (the autotuner tries 1 to 16).
-constexpr int64_t kMinItems = 8;
-constexpr int64_t kMinItemKib = 32;
-constexpr int32_t kMaxMinItems = 64;
 int64_t rows_per_item(const modap_batch *c, const BSys &s) {
-    const int64_t sys_kib = s.m * s.ldA * (int64_t)c->es / 1024;
-    const int64_t cap = std::max<int32_t>(1, c->tile.item_kib[bucket_of(s.C)]);
-    const int64_t least = c->tile.min_items > 0 ? c->tile.min_items : kMinItems;
-    const int64_t kib = std::min(cap, std::max(kMinItemKib, sys_kib / least));
-    int64_t r = kib * 1024 / (s.ldA * (int64_t)c->es);
-    r = std::max<int64_t>(kBatchWaves, (r + kBatchWaves - 1) / kBatchWaves * kBatchWaves);
-    return std::min<int64_t>(r, (s.m + kBatchWaves - 1) / kBatchWaves * kBatchWaves);
+    return plan_rows_per_item(s.m, s.ldA, (int64_t)c->es, c->tile.item_kib[bucket_of(s.C)], c->tile.min_items,
+                              kBatchWaves);
 }
 
 const void *sweep_fn(int dt);
