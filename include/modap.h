@@ -449,8 +449,17 @@ modap_status modap_server_set_max_long(modap_server *server, int64_t max_long);
 /* State and statistics of a request.  Errors: E_INVAL. */
 modap_status modap_server_info(modap_server *server, int64_t ticket, modap_request_info *out);
 
-/* The final x ([n] host memory) of a finished request.  Errors: E_INVAL, E_STATE. */
+/* The final x ([n] host memory) of a finished request.  Errors: E_INVAL,
+ * E_STATE (not finished, or its result released). */
 modap_status modap_server_result(modap_server *server, int64_t ticket, double *x);
+
+/* Free the stored result of a finished (done or failed) request.  The server
+ * keeps every result until it is released or the server is destroyed, so a
+ * long-running caller releases each one once it has been read.  The request's
+ * statistics stay readable with modap_server_info; modap_server_result then
+ * fails with E_STATE.  Releasing twice is a no-op.  Errors: E_INVAL (unknown
+ * ticket), E_STATE (the request is queued or live). */
+modap_status modap_server_release(modap_server *server, int64_t ticket);
 
 /* Totals: algorithmic bytes of all sweeps so far, rounds run, device bytes
  * held by live requests (any pointer may be NULL). */

@@ -39,7 +39,7 @@ EXPORTS = ["modap_create", "modap_destroy", "modap_set_system", "modap_set_x", "
            "modap_batch_last_error", "modap_server_create", "modap_server_destroy", "modap_server_submit",
            "modap_server_update", "modap_server_round", "modap_server_info", "modap_server_result",
            "modap_server_totals", "modap_server_last_error", "modap_server_set_max_live",
-           "modap_server_set_max_long",
+           "modap_server_set_max_long", "modap_server_release",
            "modap_eval_sweep_static"]
 
 
@@ -160,6 +160,7 @@ def lib():
         L.modap_server_round.argtypes = [vp, C.c_double, C.POINTER(C.c_int64)]
         L.modap_server_info.argtypes = [vp, i64, C.POINTER(RequestInfo)]
         L.modap_server_result.argtypes = [vp, i64, dp]
+        L.modap_server_release.argtypes = [vp, i64]
         L.modap_server_totals.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.modap_server_last_error.argtypes = [vp]
         L.modap_server_last_error.restype = C.c_char_p
@@ -614,6 +615,10 @@ class Server:
         x = np.empty(self.shapes[int(ticket)][1])
         self._check(lib().modap_server_result(self._h, int(ticket), x.ctypes.data_as(C.c_void_p)))
         return x
+
+    def release(self, ticket):
+        """Free the stored result of a finished request (its info stays)."""
+        self._check(lib().modap_server_release(self._h, int(ticket)))
 
     def set_max_live(self, k):
         self._check(lib().modap_server_set_max_live(self._h, int(k)))

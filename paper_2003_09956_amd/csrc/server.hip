@@ -61,6 +61,7 @@ struct Req {
     std::string error;
     std::vector<double> x;
     uint64_t trace = 0;   // the request's range on the tracing timeline, open until it ends
+    bool released = false;  // the caller released the result (x is freed)
 };
 
 void end_trace(Req &r) {
@@ -559,7 +560,18 @@ modap_status modap_server_result(modap_server *s, int64_t ticket, double *x) {
     if (ticket < 0 || ticket >= (int64_t)s->reqs.size() || !x) return fail(s, MODAP_E_INVAL, "unknown ticket");
     const Req &r = s->reqs[(size_t)ticket];
     if (r.state != RQ_DONE) return fail(s, MODAP_E_STATE, "the request has not finished");
+    if (r.released) return fail(s, MODAP_E_STATE, "the request's result was released");
     for (size_t i = 0; i < r.x.size(); ++i) x[i] = r.x[i];
+    return MODAP_OK;
+}
+
+modap_status modap_server_release(modap_server *s, int64_t ticket) {
+    if (!s) return MODAP_E_INVAL;
+    if (ticket < 0 || ticket >= (int64_t)s->reqs.size()) return fail(s, MODAP_E_INVAL, "unknown ticket");
+    Req &r = s->reqs[(size_t)ticket];
+    if (r.state != RQ_DONE && r.state != RQ_FAILED) return fail(s, MODAP_E_STATE, "the request has not finished");
+    std::vector<double>().swap(r.x);
+    r.released = true;
     return MODAP_OK;
 }
 

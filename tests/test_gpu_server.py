@@ -229,3 +229,33 @@ def test_server_errors(P):
             S.update(t, translate=np.zeros(30))   # not admitted yet
         with pytest.raises(P.ModapError, match="E_STATE"):
             S.result(t)
+        with pytest.raises(P.ModapError, match="E_STATE"):
+            S.release(t)                          # queued: nothing to release
+        with pytest.raises(P.ModapError, match="E_INVAL"):
+            S.release(t + 7)
+
+
+def test_server_release_frees_a_result_and_keeps_its_info(P):
+    """A finished request's result is read, then released: reading it again
+    is refused, its statistics stay, releasing twice is a no-op, and the
+    requests after it are served as before."""
+    prm = P.params(lam=0.2, eps=1e-6, max_iters=5000)
+    systems = [W.gaussian(n, 3 * n, seed=n, dtype="bf16") for n in (40, 90, 150)]
+    with P.Server("bf16", budget_bytes=1e9, prm=prm, iters_per_round=32) as S:
+        tickets = [S.submit(s_.A, s_.b, x0=s_.z + 0.5) for s_ in systems]
+        for k in range(400):
+            say(f"server release round {k}")
+            if S.round(float(k)) == 0:
+                break
+        infos = [S.info(t) for t in tickets]
+        assert all(i["state_name"] == "done" for i in infos)
+        x0 = S.result(tickets[0])
+        S.release(tickets[0])
+        S.release(tickets[0])
+        with pytest.raises(P.ModapError, match="E_STATE"):
+            S.result(tickets[0])
+        assert S.info(tickets[0]) == infos[0]
+        for t, s_ in zip(tickets[1:], systems[1:]):
+            x = S.result(t)
+            assert x.shape == (s_.n,) and np.all(np.isfinite(x))
+        assert x0.shape == (systems[0].n,)
