@@ -873,6 +873,7 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8, 
     gen = torch.Generator(device="cuda")
     gen.manual_seed(args.seed + 17)
     reqs = {}
+    active = set()      # tickets not yet finished: the only ones an update tick looks at
     i = 0
     t0 = time.perf_counter()
     next_tick = tick
@@ -884,8 +885,9 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8, 
             t_arr, n, m, sd = arrivals[i]
             A, b, z = W.gaussian_device(n, m, seed=sd, dtype=storage)
             torch.cuda.current_stream().synchronize()
-            tk = S.submit(A, b, now=t_arr)      # the binding holds A and b until admission
+            tk = S.submit(A, b, now=t_arr)
             reqs[tk] = {"n": n, "m": m, "z": z}
+            active.add(tk)
             i += 1
         if now >= next_tick:
             # every tick that has elapsed since the last update counts: k ticks
@@ -893,7 +895,15 @@ def serve_pass(args, P, W, torch, arrivals, storage, max_live, wall_cap, ipr=8, 
             # replacement of k times 1% of the rows, so the systems move at the
             # same rate per second however long a round takes
             k = 1 + int((now - next_tick) / tick)
-            live = [tk for tk in reqs if S.info(tk)["state"] == 1]
+            live = []
+            for tk in sorted(active):
+                state = S.info(tk)["state"]
+                if state == 1:
+                    live.append(tk)
+                elif state >= 2:          # finished: its result is not needed here
+                    active.discard(tk)
+                    reqs[tk].pop("z", None)
+                    S.release(tk)
             for tk in live:
                 r = reqs[tk]
                 v = torch.randn(r["n"], generator=gen, device="cuda", dtype=torch.float64) * (
