@@ -69,6 +69,33 @@ def test_certified_stop_is_eps_feasible_on_the_exact_data(P, dtype):
     assert st.eps_abs == pytest.approx(1e-6 * o.binf, rel=1e-12)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_certified_stop_through_the_split_row_form(P, dtype):
+    """The same moving system solved through the two-phase split-row sweep
+    (forced): the stop it finds is certified and eps-feasible on the exact
+    data, as through the one-pass sweep."""
+    n, m = 400, 1000
+    sys_ = W.gaussian(n, m, seed=81, dtype=dtype)
+    V = W.drift(n, 600, sigma=1e-3, seed=81)
+    blk, lpr, ch = {"f32": (256, 256, 8), "bf16": (256, 256, 4)}[dtype]
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype=dtype)
+        s.set_tile(blk, lpr, ch, 0, 1, kind=1)
+        assert s.get_tile()["kind"] == 1
+        s.set_drift(V)
+        say(f"certified split-row solve dtype={dtype}")
+        st, code = s.solve(P.params(lam=0.05, eps=1e-6, max_iters=600))
+        x, bq, _ = s.query(want_b=True)
+    assert code == 0 and st.converged == 1 and st.certified == 1 and st.resident == 0
+    b = exact_rhs(sys_.A, dtype, sys_.b, V, st.iters)
+    o = oracle.sweep(sys_.A, dtype, b, x)
+    say(f"  steps {st.iters}, oracle dmax {o.dmax:.3e}, certificate {st.max_viol:.3e}")
+    assert o.dmax <= 1e-6 * o.binf * (1 + 1e-12)
+    assert o.dmax <= st.max_viol * (1 + 1e-12) + 1e-300
+    scale = np.abs(W.stored_to_f64(sys_.A, dtype)) @ np.abs(V[:st.iters]).sum(axis=0) + np.abs(sys_.b)
+    assert np.max(np.abs(bq - b) / scale) <= 1e-12
+
+
 def rounding_trap(dtype, n=64):
     """A box |x_j| <= 1000 and a point 3e-5 outside its face x_0 <= 1000.
     x is staged in FP32 by the FP32/BF16 sweep, and 1000 + 3e-5 rounds to 1000
