@@ -192,7 +192,7 @@ def measured_traffic(dt, n, m, tile):
 
 def time_to_feasible(P, W, seeds):
     """FP64 stationary box-plus-sum system: solve from x0 = 400 + U(0,100)."""
-    out, iters = [], []
+    out, iters, forms = [], [], set()
     prm = P.params(lam=1.0, eps=1e-6, max_iters=100000)
     with P.Solver(0) as s:
         for seed in seeds:
@@ -203,7 +203,8 @@ def time_to_feasible(P, W, seeds):
                 raise RuntimeError(f"box-sum seed {seed}: solve status {code}")
             out.append(st.seconds * 1e3)
             iters.append(st.iters)
-    return out, iters
+            forms.add("resident" if st.resident else "two-kernel")
+    return out, iters, ",".join(sorted(forms))
 
 
 def cpu_baseline(sys_, V, seconds_budget):
@@ -356,10 +357,10 @@ def main():
             extra_fp32.pop(key, None)
         line["fp32_n8192_m16384"] = extra_fp32
     if not args.no_ttf:
-        ms, its = time_to_feasible(P, W, range(20))
+        ms, its, form = time_to_feasible(P, W, range(20))
         line["time_to_feasible"] = {
             "box_sum_f64_n256_m513": {"p50_ms": round(percentile(ms, 50), 3), "p99_ms": round(percentile(ms, 99), 3),
-                                      "seeds": 20, "steps_p50": percentile(its, 50)},
+                                      "seeds": 20, "steps_p50": percentile(its, 50), "iteration_form": form},
         }
         if dt == "f32" or extra_fp32 is not None:
             s2 = sys_ if dt == "f32" else s2
