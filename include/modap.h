@@ -43,6 +43,22 @@
  *    onto the exact value.
  *  - Threading: a context is used by one host thread at a time; several
  *    contexts may share a device.
+ *  - Tracing: every working call records a named range on the ROCm tracing
+ *    timeline (rocprofv3 --marker-trace), a served request one from its
+ *    submission to its end.
+ *
+ * Environment variables the library reads (all optional):
+ *   MODAP_TUNE_CACHE=path        file of autotuned sweep shapes (modap_autotune)
+ *   MODAP_RESIDENT=0             small systems iterate in two kernels per
+ *                                iteration instead of the resident form
+ *   MODAP_RESIDENT_ROWS=k        rows per workgroup the resident form aims for
+ *                                (default 32, at least 4)
+ *   MODAP_RESIDENT_TIMEOUT_TICKS=t  longest wait of a resident launch at its grid
+ *                                barrier, in ticks of the 100 MHz constant clock
+ *                                (default 1e8: one second); a longer wait ends the
+ *                                launch, and the call reports E_DEVICE
+ *   MODAP_BATCH_SHORT=0          batches sweep short rows one to a wavefront
+ *                                instead of four
  */
 #ifndef MODAP_H
 #define MODAP_H
