@@ -385,7 +385,13 @@ def main():
             a2 = copy.copy(args)
             a2.workload, a2.batch_tile = wl, None
             log(f"--- {wl} ---")
-            sub = fn(a2, P, W, torch, emit=False)
+            try:
+                sub = fn(a2, P, W, torch, emit=False)
+            except Exception as e:     # the headline stands on its own: record the failure, go on
+                log(f"{wl} failed: {e!r}")
+                line[key] = {"error": repr(e)}
+                torch.cuda.empty_cache()
+                continue
             for k in ("metric", "unit", "n_gpus", "higher_is_better", "scaling", "vs_baseline"):
                 sub.pop(k, None)
             line[key] = sub
