@@ -49,6 +49,35 @@ def test_traffic_is_reported_only_for_the_current_kernel_source(tmp_path, monkey
     assert bench.measured_traffic("f32", 8192, 16384, other) is None         # another launch shape
 
 
+def test_batch_tile_string_and_counter_lookup(tmp_path, monkeypatch):
+    """The batch tile names its item sizes and grid, then the least items per
+    system when it is not the library's choice; a batch counter file counts
+    only for its family, its tile and the current batch kernel and plan."""
+    t0 = {"item_kib": [512, 2048, 4096, 8192], "grid": 0, "min_items": 0}
+    t2 = dict(t0, item_kib=[16384, 2048, 4096, 8192], min_items=2)
+    assert bench.batch_tile_str(t0) == "512,2048,4096,8192,0"
+    assert bench.batch_tile_str(t2) == "16384,2048,4096,8192,0,2"
+    assert bench.batch_counters_path("16384,2048,4096,8192,0,2", "batch-f32-512-n256").endswith(
+        os.path.join("profiles", "sweep_batch_f32_512x256_tile16384-2048-4096-8192-0-2_counters.txt"))
+    real = bench.batch_counters_path
+    monkeypatch.setattr(bench, "batch_counters_path",
+                        lambda tile, wl="batch-f32-512": os.path.join(tmp_path, os.path.basename(real(tile, wl))))
+    path = bench.batch_counters_path("16384,2048,4096,8192,0,2", "batch-f32-512-n256")
+
+    def put(tile, h):
+        open(path, "w").write(f"tile = {tile}\nsource_hash = {h}\nbytes_per_launch = 1103400000\n")
+    assert bench.measured_batch_traffic(t2, "batch-f32-512-n256") is None            # no file
+    put("16384,2048,4096,8192,0,2", bench.batch_source_hash())
+    assert bench.measured_batch_traffic(t2, "batch-f32-512-n256") == 1103400000
+    assert bench.measured_batch_traffic(t0, "batch-f32-512-n256") is None            # another tile
+    assert bench.measured_batch_traffic(t2, "batch-f32-512") is None                 # another family
+    put("16384,2048,4096,8192,0,2", "0" * 16)
+    assert bench.measured_batch_traffic(t2, "batch-f32-512-n256") is None            # sources changed
+    # the hash covers the batch kernel and the rules that cut systems into items
+    assert any(p.endswith("batch_plan.hpp") for p in bench.BATCH_SOURCES)
+    assert not any(p.endswith("batch.hip") for p in bench.BATCH_SOURCES)
+
+
 def test_kernel_source_hash_depends_on_the_storage_table():
     assert bench.kernel_source_hash("f32") != bench.kernel_source_hash("bf16")
     assert len(bench.kernel_source_hash("f64")) == 16
