@@ -1010,8 +1010,7 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
     bool present[4] = {false, false, false, false};
     for (const BSys &s : c->sys)
         if (s.alive) present[bucket_of(s.C)] = true;
-    hipEvent_t e0 = event_at(c, 0), e1 = event_at(c, 1);
-    if (!e0 || !e1) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
+    if (!event_at(c, 2 * (size_t)reps + 1)) return fail(c, MODAP_E_DEVICE, "hipEventCreate failed");
     // one timing: `reps` stateless sweeps (no decision, no b written)
     auto time_sweeps = [&](float *ms) -> modap_status {
         modap_status s2;
@@ -1020,19 +1019,23 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
         if ((s2 = launch(c, prime_fn(c->dt), a.nsys, 256, a, nullptr, nullptr))) return s2;
         a.check_status = 0;
         a.write_b = 0;
-        std::vector<float> t;
+        // one untimed sweep, then `reps` timed ones back to back (as the
+        // iterations run; a host wait after each would leave the device idle
+        // between them), the host waiting once; the shortest counts, the
+        // work being the same each time
         for (int r = 0; r <= reps; ++r) {
             HIP_TRY(c, hipMemsetAsync(c->queue, 0, sizeof(int32_t), c->stream));
-            if ((s2 = launch(c, sweep_fn(c->dt), c->grid, 256, a, r ? e0 : nullptr, r ? e1 : nullptr))) return s2;
-            if (r) {
-                HIP_TRY(c, hipEventSynchronize(e1));
-                float x = 0.f;
-                HIP_TRY(c, hipEventElapsedTime(&x, e0, e1));
-                t.push_back(x);
-            }
+            hipEvent_t b0 = r ? event_at(c, 2 * (size_t)r) : nullptr, b1 = r ? event_at(c, 2 * (size_t)r + 1) : nullptr;
+            if ((s2 = launch(c, sweep_fn(c->dt), c->grid, 256, a, b0, b1))) return s2;
         }
-        std::sort(t.begin(), t.end());
-        *ms = t[t.size() / 2];
+        HIP_TRY(c, hipEventSynchronize(event_at(c, 2 * (size_t)reps + 1)));
+        float best = 0.f;
+        for (int r = 1; r <= reps; ++r) {
+            float x = 0.f;
+            HIP_TRY(c, hipEventElapsedTime(&x, event_at(c, 2 * (size_t)r), event_at(c, 2 * (size_t)r + 1)));
+            if (r == 1 || x < best) best = x;
+        }
+        *ms = best;
         return MODAP_OK;
     };
     // Starting from the built-in tile, each bucket's item size and then the
@@ -1045,6 +1048,16 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
         c->dirty = true;
         return time_sweeps(ms);
     };
+    // the cut of every live system under a tile: a candidate that cuts them
+    // all as the incumbent does is the same work, and is not timed (its
+    // timing could only differ by noise)
+    auto cut_of = [&](const modap_batch_tile &t) {
+        std::vector<int64_t> v;
+        for (const BSys &s : c->sys)
+            if (s.alive) v.push_back(plan_rows_per_item(s.m, s.ldA, (int64_t)c->es, t.item_kib[bucket_of(s.C)],
+                                                         t.min_items, kBatchWaves));
+        return v;
+    };
     // a work item costs a few microseconds beyond its rows (queue, state,
     // staging, partial): large items pay it rarely, small ones balance better
     const int sizes[] = {64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384};
@@ -1055,15 +1068,18 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
             modap_status s2;
             if ((s2 = time_tile(cur, &win))) return s2;
             int pick = cur.item_kib[q];
+            std::vector<int64_t> cut = cut_of(cur);
             for (int kib : sizes) {
                 if (kib == cur.item_kib[q]) continue;
                 modap_batch_tile t = cur;
                 t.item_kib[q] = kib;
+                if (cut_of(t) == cut) continue;
                 float ms = 0.f;
                 if ((s2 = time_tile(t, &ms))) return s2;
                 if (ms < win * kMargin) {
                     win = ms;
                     pick = kib;
+                    cut = cut_of(t);
                 }
             }
             cur.item_kib[q] = pick;
@@ -1075,8 +1091,12 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
     // batch run faster in fewer, larger items.  The counts are compared with
     // every present bucket's item size lifted to the largest, so that the
     // count is what cuts the small systems; if another count wins, the sizes
-    // are tuned again under it.
+    // are tuned again under it, and the result is kept only if it beats the
+    // tile this stage started from.
     {
+        const modap_batch_tile before = cur;
+        float t_before = 0.f;
+        if ((st = time_tile(before, &t_before))) return st;
         modap_batch_tile lifted = cur;
         for (int q = 0; q < 4; ++q)
             if (present[q]) lifted.item_kib[q] = sizes[sizeof(sizes) / sizeof(sizes[0]) - 1];
@@ -1084,21 +1104,27 @@ modap_status modap_batch_autotune(modap_batch *c, int reps, modap_batch_tile *be
         float win = 0.f;
         if ((st = time_tile(lifted, &win))) return st;
         int pick = inc;
+        std::vector<int64_t> cut = cut_of(lifted);
         for (int mi : {1, 2, 4, 8, 16}) {
             if (mi == inc) continue;
             modap_batch_tile t = lifted;
             t.min_items = mi;
+            if (cut_of(t) == cut) continue;
             float ms = 0.f;
             if ((st = time_tile(t, &ms))) return st;
             if (ms < win * kMargin) {
                 win = ms;
                 pick = mi;
+                cut = cut_of(t);
             }
         }
         if (pick != inc) {
             cur = lifted;
             cur.min_items = pick;
             if ((st = tune_sizes())) return st;
+            float t_after = 0.f;
+            if ((st = time_tile(cur, &t_after))) return st;
+            if (!(t_after < t_before * kMargin)) cur = before;
         }
     }
     float win = 0.f;
