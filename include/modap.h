@@ -258,9 +258,10 @@ modap_status modap_get_tile(modap_ctx *ctx, modap_tile *tile);
 
 /* Autotuner: time every compiled sweep shape that covers the loaded rows, at
  * one and two workgroups per CU and at full occupancy, in both row orders,
- * with `reps` stateless sweeps each (the context's state is not changed),
- * and return the choice in *best (may be NULL).  The built-in shape is timed
- * first and is kept unless another is at least 2% faster.
+ * with `reps` stateless sweeps each, run back to back after an untimed one
+ * (the context's state is not changed; the shortest counts), and return the
+ * choice in *best (may be NULL).  The built-in shape is timed first and is
+ * kept unless another is at least 2% faster.
  * When the environment variable MODAP_TUNE_CACHE names a file, results are
  * appended to it (one line per storage type, padded row length and m) and
  * modap_set_system uses a cached shape for the same key.  Synchronises.
@@ -367,10 +368,14 @@ modap_status modap_batch_set_tile(modap_batch *batch, const modap_batch_tile *ti
 modap_status modap_batch_get_tile(modap_batch *batch, modap_batch_tile *tile);
 
 /* Autotuner of the batch: for each row-length bucket present, the item size
- * (KiB of A per work item, from 64 to 16384) and then the grid are chosen by
- * timing `reps` stateless batch sweeps of the current systems (their state
- * is not changed); the result is kept and returned in *best (may be NULL).
- * Synchronises.  Errors: E_STATE (empty batch), E_INVAL, E_DEVICE. */
+ * (KiB of A per work item, from 64 to 16384), then the least number of items
+ * per system (1 to 16) and then the grid are chosen by timing `reps`
+ * stateless batch sweeps of the current systems, run back to back after an
+ * untimed one (their state is not changed; the shortest counts).  A candidate
+ * that cuts every system as the incumbent does is not timed, and a challenger
+ * must be at least 2% faster.  The result is kept and returned in *best (may
+ * be NULL); on failure the batch keeps its tile.  Synchronises.  Errors:
+ * E_STATE (empty batch), E_INVAL, E_DEVICE. */
 modap_status modap_batch_autotune(modap_batch *batch, int reps, modap_batch_tile *best);
 
 /* Message describing the last failing call on the batch. */
