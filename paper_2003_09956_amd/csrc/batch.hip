@@ -153,11 +153,6 @@ void release_sys(BSys &s) {
     s.T = 0;
 }
 
-modap_status check_batch(modap_batch *c) {
-    if (!c) return MODAP_E_INVAL;
-    return MODAP_OK;
-}
-
 BSys *find_sys(modap_batch *c, int64_t id) {
     if (id < 0 || id >= (int64_t)c->sys.size() || !c->sys[(size_t)id].alive) return nullptr;
     return &c->sys[(size_t)id];
