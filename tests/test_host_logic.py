@@ -160,3 +160,29 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_step_line_keeps_the_benchmark_contract():
+    """The line of a single-system workload carries every field the driver
+    reads, value is whole-step bytes over wall time, and the roofline object
+    is the sweep kernel's achieved rate over the HBM peak."""
+    import argparse
+    args = argparse.Namespace(steps=200, warmup=20, device_warmup=0.3)
+    bps = 16384 * 65536 * 2 + 24 * 65536
+    res = {"tile": dict(TILE, kind=0), "wall": 200 * 322e-6, "wall_profiled": 200 * 337e-6,
+           "sweep_us": 315.0, "reduce_us": 5.5, "profiled": 200, "upload_s": 0.0, "host_bytes": 0,
+           "feasible_steps": 0, "bytes_per_step": bps, "on_host": False, "warm_sweeps": 800}
+    line = bench.step_line(args, "bf16", 16384, 65536, "BF16 test system", res)
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                "scaling", "vs_baseline", "dtype", "data", "config", "roofline"):
+        assert key in line, key
+    assert line["metric"] == bench.METRIC and line["unit"] == "GB/s" and line["n_gpus"] == 1
+    assert line["steps"] == 200 and line["warmup"] == 20 and line["higher_is_better"] is True
+    assert line["vs_baseline"] is None and line["dtype"] == "bf16" and "workload" in line["config"]
+    assert line["value"] == pytest.approx(bps * 200 / (200 * 322e-6) / 1e9, rel=1e-4)
+    assert line["ms_per_step"] == pytest.approx(0.322, rel=1e-4)
+    r = line["roofline"]
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == bench.HBM_PEAK_GBS == 8000.0
+    assert r["achieved"] == pytest.approx(bps / 315e-6 / 1e9, rel=1e-4)
+    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], abs=1e-4)
+    assert "traffic" in r and line["device_warmup"]["stateless_sweeps"] == 800
