@@ -1,11 +1,12 @@
-"""Seeded random shapes: one sweep and one step of each against the oracle.
+"""Seeded random shapes and batches, against the oracle.
 
 The shapes are drawn log-uniformly (n from 1 to 20000, m from 1 to 6000) with
 every storage type, so that row lengths fall anywhere relative to the tile
 widths of the one-pass, short-row, split-row and resident forms.  Each case
 compares a stateless sweep at a point with violated rows element by element
 (r, y, h, dmax), then one iteration against the oracle's step from the same
-point.
+point.  Random batches (3 to 9 systems of any row length the batch covers,
+with random tiles) take two steps of every system against the oracle.
 """
 import sys
 
@@ -66,3 +67,64 @@ def test_random_shape_sweep_and_step_match_oracle(P, n, m, dtype):
     s_y = np.linalg.norm(weighted_abs_rows(sys_.A, dtype, np.where(near, o.t / o.nu, 0)))
     bound = tol * (np.linalg.norm(x) + lam * s_y / np.linalg.norm(o.y))
     assert np.linalg.norm(x1 - xo) <= bound, (np.linalg.norm(x1 - xo), bound)
+
+
+ROW_LIMIT = {"f32": 2048, "bf16": 4096, "f64": 1024}
+
+
+def draw_batch(k):
+    rng = np.random.default_rng(np.random.SeedSequence([2003, 9956, 1000 + k]))
+    dtype = ("f64", "f32", "bf16")[k % 3]
+    count = int(rng.integers(3, 10))
+    shapes = []
+    for _ in range(count):
+        n = int(np.exp(rng.uniform(0.0, np.log(ROW_LIMIT[dtype]))))
+        m = int(np.exp(rng.uniform(0.0, np.log(3000.0))))
+        shapes.append((max(n, 1), max(m, 1)))
+    kib = [int(2 ** rng.integers(5, 15)) for _ in range(4)]
+    min_items = int((0, 1, 2, 4, 16)[int(rng.integers(5))])
+    return dtype, shapes, kib, min_items
+
+
+@pytest.mark.parametrize("k", range(24))
+def test_random_batch_mix_follows_oracle(P, k):
+    """A seeded random batch (3 to 9 systems of any row length the batch
+    covers, a random tile): two steps of every system against the oracle,
+    and one system alone against the mix at the same tile and call
+    boundaries."""
+    dtype, shapes, kib, min_items = draw_batch(k)
+    systems = [W.gaussian(n, m, seed=k * 101 + i, dtype=dtype) for i, (n, m) in enumerate(shapes)]
+    lam, tol = 0.4, TOL[dtype]
+    prm = P.params(lam=lam, eps=1e-12)
+    xs = [s_.z + np.random.default_rng(i).normal(scale=1.5 / np.sqrt(s_.n) + 0.1, size=s_.n)
+          for i, s_ in enumerate(systems)]
+    x_first = xs[-1].copy()
+    stopped = [False] * len(systems)
+    with P.Batch(dtype) as B:
+        B.set_tile(item_kib=kib, min_items=min_items)
+        ids = [B.add(s_.A, s_.b, x0=x) for s_, x in zip(systems, xs)]
+        for step in range(2):
+            say(f"random batch k={k} {dtype} shapes={shapes} tile={B.get_tile()} step={step}")
+            B.iterate(1, prm)
+            for i, (s_, sid) in enumerate(zip(systems, ids)):
+                x1, _, q = B.query(sid)
+                if stopped[i]:
+                    assert np.array_equal(x1, xs[i])
+                    continue
+                o = oracle.sweep(s_.A, dtype, s_.b, xs[i])
+                xo, status = oracle.step(o.y, o.h, 0, lam, xs[i])
+                if status != 0:
+                    assert q.converged == 1 and np.array_equal(x1, xs[i]), (i, step)
+                    stopped[i] = True
+                    continue
+                near = o.r > -tol * o.t
+                s_y = np.linalg.norm(weighted_abs_rows(s_.A, dtype, np.where(near, o.t / o.nu, 0)))
+                bound = tol * (np.linalg.norm(xs[i]) + lam * s_y / np.linalg.norm(o.y))
+                assert q.iters == step + 1 and np.linalg.norm(x1 - xo) <= bound, (i, step)
+                xs[i] = x1
+    with P.Batch(dtype) as B:
+        B.set_tile(item_kib=kib, min_items=min_items)
+        sid = B.add(systems[-1].A, systems[-1].b, x0=x_first)
+        B.iterate(1, prm)
+        B.iterate(1, prm)
+        assert np.array_equal(B.query(sid)[0], xs[-1])
