@@ -128,3 +128,52 @@ def test_random_batch_mix_follows_oracle(P, k):
         B.iterate(1, prm)
         B.iterate(1, prm)
         assert np.array_equal(B.query(sid)[0], xs[-1])
+
+
+@pytest.mark.parametrize("k", range(24))
+def test_random_shape_data_updates_follow_oracle(P, k):
+    """One step under the drift schedule, then rows replaced and a one-shot
+    translation, then a second step: the second step against the oracle's on
+    the data as the update rules define them (the replaced rows exactly as
+    given on the data after the drift row already due; the translation on
+    every row), and the right-hand side read back against the exact data."""
+    rng = np.random.default_rng(np.random.SeedSequence([2003, 9956, 2000 + k]))
+    n = max(1, int(np.exp(rng.uniform(0.0, np.log(20000.0)))))
+    m = max(2, int(np.exp(rng.uniform(np.log(2.0), np.log(4000.0)))))
+    dtype = ("f64", "f32", "bf16")[k % 3]
+    sys_ = W.gaussian(n, m, seed=7 * n + m, dtype=dtype)
+    V = W.drift(n, 3, sigma=1e-3, seed=k)
+    v = rng.normal(scale=1e-2, size=n)
+    idx, rows, nb = W.replacement_rows(sys_, max(1, m // 10), seed=k)
+    x0 = sys_.z + rng.normal(scale=1.5 / np.sqrt(n) + 0.1, size=n)
+    lam, tol = 0.3, TOL[dtype]
+    prm = P.params(lam=lam, eps=1e-12)
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, x0=x0, dtype=dtype)
+        s.set_drift(V)
+        say(f"random updates k={k} n={n} m={m} dtype={dtype} tile={s.get_tile()}")
+        s.iterate(1, prm)
+        x1, _, st1 = s.query()
+        if st1.converged:          # the start is feasible: no step, so no drift row was applied
+            return
+        s.update_coeffs(rows=idx, new_rows=rows, new_b=nb, translate=v)
+        st2 = s.iterate(1, prm)
+        x2, bq, st = s.query(want_b=True)
+    b1 = oracle.translate(sys_.A, dtype, sys_.b, V[0])
+    A2, b2 = oracle.replace_rows(sys_.A, dtype, b1, idx, rows, nb)
+    b3 = oracle.translate(A2, dtype, b2, v)
+    o = oracle.sweep(A2, dtype, b3, x1)
+    xo, status = oracle.step(o.y, o.h, 0, lam, x1)
+    if status != 0 or st.converged:
+        # a feasible point stays where it is (and the last translation waits)
+        assert np.array_equal(x2, x1)
+        return
+    assert st1.iters == 1 and st.iters == 2
+    near = o.r > -tol * o.t
+    s_y = np.linalg.norm(weighted_abs_rows(A2, dtype, np.where(near, o.t / o.nu, 0)))
+    bound = tol * (np.linalg.norm(x1) + lam * s_y / np.linalg.norm(o.y))
+    assert np.linalg.norm(x2 - xo) <= bound, (np.linalg.norm(x2 - xo), bound)
+    b4 = oracle.translate(A2, dtype, b3, V[1])
+    scale = (np.abs(W.stored_to_f64(A2, dtype)) @ (np.abs(V[0]) + np.abs(V[1]) + np.abs(v))
+             + np.abs(sys_.b) + np.abs(b2))
+    assert np.max(np.abs(bq - b4) / scale) <= 1e-12
