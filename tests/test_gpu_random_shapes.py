@@ -6,7 +6,10 @@ widths of the one-pass, short-row, split-row and resident forms.  Each case
 compares a stateless sweep at a point with violated rows element by element
 (r, y, h, dmax), then one iteration against the oracle's step from the same
 point.  Random batches (3 to 9 systems of any row length the batch covers,
-with random tiles) take two steps of every system against the oracle.
+with random tiles) take two steps of every system against the oracle;
+random data-update sequences (drift, row replacement, translation) take a
+step on the data the update rules define; random served request streams end
+eps-feasible, each request the same bits alone as in the stream.
 """
 import sys
 
@@ -177,3 +180,52 @@ def test_random_shape_data_updates_follow_oracle(P, k):
     scale = (np.abs(W.stored_to_f64(A2, dtype)) @ (np.abs(V[0]) + np.abs(V[1]) + np.abs(v))
              + np.abs(sys_.b) + np.abs(b2))
     assert np.max(np.abs(bq - b4) / scale) <= 1e-12
+
+
+@pytest.mark.parametrize("k", range(6))
+def test_random_server_mix_results_equal_alone(P, k):
+    """A seeded random stream of requests (short and long rows, with or
+    without drift schedules, rounds between some submissions, a random limit
+    on long requests): every request ends eps-feasible on its final data,
+    and a chosen one takes the same bits and steps as served alone."""
+    rng = np.random.default_rng(np.random.SeedSequence([2003, 9956, 3000 + k]))
+    dtype = ("bf16", "f32", "f64")[k % 3]
+    count = int(rng.integers(3, 7))
+    reqs = []
+    for i in range(count):
+        n = int(np.exp(rng.uniform(np.log(16.0), np.log(3000.0))))
+        m = int(n * rng.uniform(2.0, 4.0))
+        sys_ = W.gaussian(n, m, seed=k * 97 + i, dtype=dtype)
+        V = W.drift(n, 400, sigma=1e-5, seed=k * 97 + i) if rng.random() < 0.5 else None
+        reqs.append((sys_, V, bool(rng.random() < 0.5)))
+    max_long = int(rng.integers(0, 2))
+    target = int(rng.integers(count))
+    prm = P.params(lam=0.1, eps=1e-6, max_iters=5000)
+
+    def serve(items):
+        with P.Server(dtype, budget_bytes=20e9, prm=prm, iters_per_round=8) as S:
+            S.set_max_long(max_long)
+            tickets = []
+            for sys_, V, round_after in items:
+                tickets.append(S.submit(sys_.A, sys_.b, V=V))
+                if round_after:
+                    S.round()
+            for _ in range(20000):
+                if S.round() == 0:
+                    break
+            infos = [S.info(t) for t in tickets]
+            return infos, [S.result(t) for t in tickets]
+
+    say(f"random server k={k} {dtype} shapes={[r[0].A.shape for r in reqs]} max_long={max_long}")
+    infos, xs = serve(reqs)
+    for (sys_, V, _), info, x in zip(reqs, infos, xs):
+        assert info["state"] == 2 and info["status"] == 1, info
+        b = sys_.b.copy()
+        if V is not None:
+            for q in range(min(info["iters"], V.shape[0])):
+                b = oracle.translate(sys_.A, dtype, b, V[q])
+        o = oracle.sweep(sys_.A, dtype, b, x)
+        assert o.dmax <= 1e-6 * o.binf * (1 + 1e-12), (sys_.A.shape, o.dmax, o.binf)
+    alone_infos, alone_xs = serve([reqs[target][:2] + (False,)])
+    assert alone_infos[0]["iters"] == infos[target]["iters"]
+    assert np.array_equal(alone_xs[0], xs[target])
