@@ -11,8 +11,13 @@ Stability of Numerical Algorithms, ch. 3):
   y:     ||y_G - y_O|| <= tol * max(||y_O||, s_y),
          s_y = || sum over rows with r_O > -tol t_i of (t_i/||a_i||^2) |a_i| ||
   dmax:  |dmax_G - dmax_O| <= tol * max over the same rows of t_i/||a_i||
-  and the plain normwise relative error of y is also required to pass when no
-  row lies in the ambiguous band.
+
+The plain normwise relative error of y is logged but not required: a
+residual outside the ambiguous band can still be small against its rounding
+scale (r_i << t_i), and its weight r_i/||a_i||^2 then carries a relative error
+up to about u t_i / r_i (u the unit roundoff of the accumulation), which the
+bound on the scale s_y covers and a plain relative bound does not.  Without
+such cancellation s_y is close to ||y|| and the two bounds agree.
 """
 from __future__ import annotations
 
@@ -52,8 +57,6 @@ def check_sweep(A, dtype, o, y_g, h_g, dmax_g, r_g=None, tol=None, label=""):
            "y_rel": dy / ynorm if ynorm > 0 else dy,
            "band_rows": int(band.sum())}
     assert err["y_scaled"] <= tol, (label, err)
-    if band.sum() == 0 and ynorm > 0:
-        assert err["y_rel"] <= tol, (label, err)
     # h: equal up to the ambiguous rows
     assert abs(int(h_g) - o.h) <= int(band.sum()), (label, h_g, o.h, int(band.sum()))
     if band.sum() == 0:
