@@ -110,12 +110,23 @@ _lib = None
 
 
 def lib():
-    """Load libmodap.so (raises when it has not been built)."""
+    """Load libmodap.so (raises when it has not been built).
+
+    PyTorch, when it is installed, is imported first: its wheel carries a HIP
+    runtime of its own, which it loads by path.  Loaded after the library
+    (whose runtime is found by soname), it would map a second HIP runtime into
+    the process, and the two would not share devices, streams or memory.
+    Imported first, its runtime is the one the library's dependency resolves to.
+    """
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               f"`python -m paper_2003_09956_amd._build` (no CPU fallback exists)")
+        try:
+            import torch  # noqa: F401  (one HIP runtime in the process: see above)
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i64, i32, dp = C.c_void_p, C.c_int64, C.c_int, C.c_void_p
         L.modap_create.argtypes = [i32, vp, C.POINTER(vp)]

@@ -7,6 +7,7 @@ import ctypes as C
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -144,3 +145,16 @@ def test_library_records_its_tracing_ranges():
     und = subprocess.run(["nm", "-D", "--undefined-only", P.LIB_PATH], capture_output=True, text=True).stdout
     for sym in ("roctxRangePushA", "roctxRangePop", "roctxRangeStartA", "roctxRangeStop"):
         assert sym in und, sym
+
+
+def test_loading_the_library_first_maps_one_hip_runtime():
+    """Loading the library before anything imports torch leaves a single HIP
+    runtime mapped in the process (torch brings its own copy; two runtimes in
+    one process share no device state)."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_2003_09956_amd as P; P.lib(); import torch\n"
+            "maps = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(maps))" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "1", r.stdout
