@@ -43,6 +43,11 @@
  *    onto the exact value.
  *  - Threading: a context is used by one host thread at a time; several
  *    contexts may share a device.
+ *  - One HIP runtime per process: the library needs libamdhip64.so.7.  In a
+ *    process that also uses PyTorch, load PyTorch first (its wheel loads a
+ *    HIP runtime of its own by path; loaded after this library it would map
+ *    a second one, with which nothing is shared, and calls fail with
+ *    E_DEVICE).  The Python binding does this itself.
  *  - Tracing: every working call records a named range on the ROCm tracing
  *    timeline (rocprofv3 --marker-trace), a served request one from its
  *    submission to its end.
