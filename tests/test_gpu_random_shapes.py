@@ -9,7 +9,9 @@ point.  Random batches (3 to 9 systems of any row length the batch covers,
 with random tiles) take two steps of every system against the oracle;
 random data-update sequences (drift, row replacement, translation) take a
 step on the data the update rules define; random served request streams end
-eps-feasible, each request the same bits alone as in the stream.
+eps-feasible, each request the same bits alone as in the stream; randomly
+forced one-pass tiles sweep as the oracle does; random certified solves end
+eps-feasible on the exact data.
 """
 import sys
 
@@ -229,3 +231,66 @@ def test_random_server_mix_results_equal_alone(P, k):
     alone_infos, alone_xs = serve([reqs[target][:2] + (False,)])
     assert alone_infos[0]["iters"] == infos[target]["iters"]
     assert np.array_equal(alone_xs[0], xs[target])
+
+
+@pytest.mark.parametrize("k", range(48))
+def test_random_forced_tile_sweep_matches_oracle(P, k):
+    """A compiled one-pass sweep shape drawn at random, forced on a row it
+    covers with a ragged tail, at a random grid and row order, with or
+    without a pending translation: the sweep against the oracle's."""
+    from test_gpu_parity import ALL_SHAPES, VEC
+    from parity import check_sweep
+    rng = np.random.default_rng(np.random.SeedSequence([2003, 9956, 5000 + k]))
+    dtype = ("f64", "f32", "bf16")[k % 3]
+    shapes = ALL_SHAPES[dtype]
+    blk, lpr, ch, rs, pd = shapes[int(rng.integers(len(shapes)))]
+    cover = lpr * VEC[dtype] * ch
+    n = int(rng.integers(max(1, cover // 4), cover + 1))
+    m = max(1, int(np.exp(rng.uniform(0.0, np.log(5000.0)))))
+    grid = int((0, 1, 2, 3, 7, 64, 256)[int(rng.integers(7))])
+    il = int(rng.integers(2))
+    translate = bool(rng.random() < 0.5)
+    sys_ = W.gaussian(n, m, seed=k, dtype=dtype)
+    x = sys_.z + rng.normal(scale=1.5 / np.sqrt(n) + 0.1, size=n)
+    v = rng.normal(scale=1e-2, size=n)
+    label = f"{dtype} n={n} m={m} tile={blk}/{lpr}/{ch}/{rs}/{pd} grid={grid} il={il} v={translate}"
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype=dtype)
+        s.set_tile(blk, lpr, ch, grid, rs, depth=pd, interleave=il)
+        say(f"random tile {label}")
+        if translate:
+            s.update_coeffs(translate=v)
+        g = s.eval_sweep(x)
+    b = oracle.translate(sys_.A, dtype, sys_.b, v) if translate else sys_.b
+    o = oracle.sweep(sys_.A, dtype, b, x)
+    check_sweep(sys_.A, dtype, o, g.y, g.h, g.max_viol, g.r, label=label)
+
+
+@pytest.mark.parametrize("k", range(12))
+def test_random_certified_solve_is_feasible_on_the_exact_data(P, k):
+    """A random system solved under a random drift: the certified stop is
+    eps-feasible on the exact data (the system translated by the exact sum of
+    the drift rows applied), bounded by the certificate's reported violation,
+    and the right-hand side read back is that of the exact data."""
+    import math
+    rng = np.random.default_rng(np.random.SeedSequence([2003, 9956, 7000 + k]))
+    dtype = ("f32", "bf16", "f64")[k % 3]
+    n = int(np.exp(rng.uniform(np.log(8.0), np.log(3000.0))))
+    m = int(n * rng.uniform(1.5, 4.0))
+    sys_ = W.gaussian(n, m, seed=k + 91, dtype=dtype)
+    V = W.drift(n, 3000, sigma=float(10 ** rng.uniform(-6, -3.5)), seed=k)
+    lam = float(rng.choice([0.05, 0.1, 0.2]))
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, dtype=dtype)
+        s.set_drift(V)
+        say(f"random certified solve k={k} {dtype} n={n} m={m} lam={lam}")
+        st, code = s.solve(P.params(lam=lam, eps=1e-6, max_iters=3000))
+        x, bq, _ = s.query(want_b=True)
+    assert code == 0 and st.converged == 1 and st.certified == 1
+    w = np.array([math.fsum(V[:st.iters, j]) for j in range(n)])
+    b = oracle.translate(sys_.A, dtype, sys_.b, w)
+    o = oracle.sweep(sys_.A, dtype, b, x)
+    assert o.dmax <= 1e-6 * o.binf * (1 + 1e-12)
+    assert o.dmax <= st.max_viol * (1 + 1e-12) + 1e-300
+    scale = np.abs(W.stored_to_f64(sys_.A, dtype)) @ np.abs(V[:st.iters]).sum(axis=0) + np.abs(sys_.b)
+    assert np.max(np.abs(bq - b) / scale) <= 1e-12
