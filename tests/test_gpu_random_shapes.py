@@ -11,7 +11,8 @@ random data-update sequences (drift, row replacement, translation) take a
 step on the data the update rules define; random served request streams end
 eps-feasible, each request the same bits alone as in the stream; randomly
 forced one-pass tiles sweep as the oracle does; random certified solves end
-eps-feasible on the exact data.
+eps-feasible on the exact data; a context reloaded with random systems and a
+batch whose systems come and go at random keep stepping as the oracle does.
 """
 import sys
 
@@ -294,3 +295,77 @@ def test_random_certified_solve_is_feasible_on_the_exact_data(P, k):
     assert o.dmax <= st.max_viol * (1 + 1e-12) + 1e-300
     scale = np.abs(W.stored_to_f64(sys_.A, dtype)) @ np.abs(V[:st.iters]).sum(axis=0) + np.abs(sys_.b)
     assert np.max(np.abs(bq - b) / scale) <= 1e-12
+
+
+def _step_matches(A, dtype, b, x, x1, lam):
+    o = oracle.sweep(A, dtype, b, x)
+    xo, status = oracle.step(o.y, o.h, 0, lam, x)
+    if status != 0:
+        return np.array_equal(x1, x)
+    tol = TOL[dtype]
+    near = o.r > -tol * o.t
+    s_y = np.linalg.norm(weighted_abs_rows(A, dtype, np.where(near, o.t / o.nu, 0)))
+    return np.linalg.norm(x1 - xo) <= tol * (np.linalg.norm(x) + lam * s_y / np.linalg.norm(o.y))
+
+
+def test_one_context_reloaded_with_random_systems(P):
+    """One context loaded 30 times with systems of random size and storage
+    (its buffers grow and shrink, the resident plan and the sweep shape are
+    chosen again): each load sweeps and steps as the oracle does."""
+    rng = np.random.default_rng(np.random.SeedSequence([2003, 9956, 8000]))
+    with P.Solver() as s:
+        for k in range(30):
+            dtype = ("f64", "f32", "bf16")[int(rng.integers(3))]
+            n = max(1, int(np.exp(rng.uniform(0.0, np.log(20000.0)))))
+            m = max(1, int(np.exp(rng.uniform(0.0, np.log(5000.0)))))
+            label = f"reload k={k} {dtype} n={n} m={m}"
+            say(label)
+            sys_ = W.gaussian(n, m, seed=k, dtype=dtype)
+            x = sys_.z + rng.normal(scale=1.5 / np.sqrt(n) + 0.1, size=n)
+            s.set_system(sys_.A, sys_.b, x0=x, dtype=dtype)
+            g = s.eval_sweep(x)
+            o = oracle.sweep(sys_.A, dtype, sys_.b, x)
+            check_sweep(sys_.A, dtype, o, g.y, g.h, g.max_viol, g.r, label=label)
+            s.iterate(1, P.params(lam=0.5, eps=1e-12))
+            assert _step_matches(sys_.A, dtype, sys_.b, x, s.query()[0], 0.5), label
+
+
+@pytest.mark.parametrize("trial", range(6))
+def test_random_batch_membership_churn(P, trial):
+    """Systems of random size join and leave a batch at random between
+    iterations: every live system steps as the oracle does from its own
+    point, and a system that stopped stays where it is."""
+    rng = np.random.default_rng(np.random.SeedSequence([2003, 9956, 9000 + trial]))
+    dtype = ("f64", "f32", "bf16")[trial % 3]
+    limit = ROW_LIMIT[dtype]
+    live = {}
+    with P.Batch(dtype) as B:
+        for it in range(12):
+            for sid in list(live):
+                if rng.random() < 0.3:
+                    B.remove(sid)
+                    del live[sid]
+            for _ in range(int(rng.integers(0, 4))):
+                n = max(1, int(np.exp(rng.uniform(0.0, np.log(limit)))))
+                m = max(1, int(np.exp(rng.uniform(0.0, np.log(3000.0)))))
+                sys_ = W.gaussian(n, m, seed=trial * 100 + it * 7 + len(live), dtype=dtype)
+                x = sys_.z + rng.normal(scale=1.5 / np.sqrt(n) + 0.1, size=n)
+                live[B.add(sys_.A, sys_.b, x0=x)] = [sys_, x, False]
+            if not live:
+                continue
+            say(f"churn trial={trial} it={it} {dtype} live={len(live)}")
+            B.iterate(1, P.params(lam=0.4, eps=1e-12))
+            for sid, rec in live.items():
+                sys_, x, stopped = rec
+                x1, _, q = B.query(sid)
+                if stopped:
+                    assert np.array_equal(x1, x), (it, sid)
+                    continue
+                o = oracle.sweep(sys_.A, dtype, sys_.b, x)
+                _, status = oracle.step(o.y, o.h, 0, 0.4, x)
+                if status != 0:
+                    assert q.converged == 1 and np.array_equal(x1, x), (it, sid)
+                    rec[2] = True
+                    continue
+                assert _step_matches(sys_.A, dtype, sys_.b, x, x1, 0.4), (it, sid, sys_.A.shape)
+                rec[1] = x1
