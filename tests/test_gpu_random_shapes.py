@@ -12,7 +12,8 @@ step on the data the update rules define; random served request streams end
 eps-feasible, each request the same bits alone as in the stream; randomly
 forced one-pass tiles sweep as the oracle does; random certified solves end
 eps-feasible on the exact data; a context reloaded with random systems and a
-batch whose systems come and go at random keep stepping as the oracle does.
+batch whose systems come and go at random keep stepping as the oracle does;
+served requests receiving random updates end eps-feasible on their final data.
 """
 import sys
 
@@ -369,3 +370,62 @@ def test_random_batch_membership_churn(P, trial):
                     continue
                 assert _step_matches(sys_.A, dtype, sys_.b, x, x1, 0.4), (it, sid, sys_.A.shape)
                 rec[1] = x1
+
+
+@pytest.mark.parametrize("trial", range(6))
+def test_random_server_updates_end_feasible(P, trial):
+    """A random stream of requests that receive random row replacements and
+    translations between rounds, from host or device memory at random: each
+    request ends eps-feasible on its final data (the updates applied in
+    order by the oracle)."""
+    import torch
+    dev = torch.device("cuda:0")
+
+    def to_dev(a):
+        if a is None:
+            return None
+        if a.dtype == np.uint16:
+            return torch.from_numpy(a.view(np.int16).copy()).to(dev)
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    rng = np.random.default_rng(np.random.SeedSequence([2003, 9956, 11000 + trial]))
+    dtype = ("bf16", "f32", "f64")[trial % 3]
+    systems = []
+    for i in range(int(rng.integers(3, 6))):
+        n = int(np.exp(rng.uniform(np.log(16.0), np.log(5000.0))))
+        systems.append(W.gaussian(n, int(n * rng.uniform(2.0, 4.0)), seed=trial * 31 + i, dtype=dtype))
+    prm = P.params(lam=0.1, eps=1e-6, max_iters=6000)
+    with P.Server(dtype, budget_bytes=40e9, prm=prm, iters_per_round=8) as S:
+        S.set_max_long(int(rng.integers(0, 2)))
+        tickets = [S.submit(s_.A, s_.b) for s_ in systems]
+        data = {t: (s_.A.copy(), s_.b.copy(), s_) for t, s_ in zip(tickets, systems)}
+        say(f"random server updates trial={trial} {dtype} shapes={[s_.A.shape for s_ in systems]}")
+        for r in range(3000):
+            if S.round() == 0:
+                break
+            for t in tickets:
+                if S.info(t)["state"] != 1 or rng.random() > 0.2:
+                    continue
+                A, b, s_ = data[t]
+                v = rng.normal(scale=1e-5, size=s_.n) if rng.random() < 0.7 else None
+                k = int(rng.integers(0, max(1, s_.m // 20) + 1))
+                idx = rows = nb = None
+                if k:
+                    idx, rows, nb = W.replacement_rows(W.System(A, b, s_.x0, dtype, s_.z, {}), k,
+                                                       seed=trial * 10007 + r)
+                if rng.random() < 0.5:
+                    S.update(t, rows=to_dev(idx), new_rows=to_dev(rows), new_b=to_dev(nb), translate=to_dev(v))
+                else:
+                    S.update(t, rows=idx, new_rows=rows, new_b=nb, translate=v)
+                if k:
+                    A, b = oracle.replace_rows(A, dtype, b, idx, rows, nb)
+                if v is not None:
+                    b = oracle.translate(A, dtype, b, v)
+                data[t] = (A, b, s_)
+        infos = [S.info(t) for t in tickets]
+        xs = [S.result(t) for t in tickets]
+    for t, x, info in zip(tickets, xs, infos):
+        assert info["state"] == 2 and info["status"] == 1, info
+        A, b, _ = data[t]
+        o = oracle.sweep(A, dtype, b, x)
+        assert o.dmax <= 1e-6 * o.binf * (1 + 1e-12)
