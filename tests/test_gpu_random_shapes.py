@@ -13,7 +13,8 @@ eps-feasible, each request the same bits alone as in the stream; randomly
 forced one-pass tiles sweep as the oracle does; random certified solves end
 eps-feasible on the exact data; a context reloaded with random systems and a
 batch whose systems come and go at random keep stepping as the oracle does;
-served requests receiving random updates end eps-feasible on their final data.
+served requests receiving random updates end eps-feasible on their final data;
+the relaxed step of Algorithm 1 matches the oracle's on random shapes.
 """
 import sys
 
@@ -429,3 +430,37 @@ def test_random_server_updates_end_feasible(P, trial):
         A, b, _ = data[t]
         o = oracle.sweep(A, dtype, b, x)
         assert o.dmax <= 1e-6 * o.binf * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("k", range(48))
+def test_random_shape_relaxed_step_matches_oracle(P, k):
+    """Algorithm 1 with relaxation (x <- x - (lambda/h) y) on a random shape:
+    one step against the oracle's.  h is the step's divisor, so the points
+    are compared where no row is in the ambiguous band (h then agrees
+    exactly); otherwise h must agree up to the band's rows."""
+    rng = np.random.default_rng(np.random.SeedSequence([2003, 9956, 13000 + k]))
+    n = max(1, int(np.exp(rng.uniform(0.0, np.log(20000.0)))))
+    m = max(1, int(np.exp(rng.uniform(0.0, np.log(6000.0)))))
+    dtype = ("f64", "f32", "bf16")[k % 3]
+    lam = float(rng.uniform(0.2, 1.9))
+    sys_ = W.gaussian(n, m, seed=n * 13 + m, dtype=dtype)
+    x = sys_.z + rng.normal(scale=1.5 / np.sqrt(n) + 0.1, size=n)
+    tol = TOL[dtype]
+    with P.Solver() as s:
+        s.set_system(sys_.A, sys_.b, x0=x, dtype=dtype)
+        say(f"relaxed step k={k} n={n} m={m} dtype={dtype} lam={lam:.3f}")
+        st = s.iterate(1, P.params(lam=lam, eps=1e-12, step=P.STEP_AVG))
+        x1, _, st = s.query()
+    o = oracle.sweep(sys_.A, dtype, sys_.b, x)
+    xo, status = oracle.step(o.y, o.h, 1, lam, x)
+    if status != 0:
+        assert st.converged == 1 and np.array_equal(x1, x)
+        return
+    band = int((np.abs(o.r) <= tol * o.t).sum())
+    assert abs(int(st.h) - o.h) <= band
+    if band:
+        return
+    near = o.r > -tol * o.t
+    s_y = np.linalg.norm(weighted_abs_rows(sys_.A, dtype, np.where(near, o.t / o.nu, 0)))
+    bound = tol * (np.linalg.norm(x) + lam * s_y / o.h)
+    assert np.linalg.norm(x1 - xo) <= bound, (np.linalg.norm(x1 - xo), bound)
