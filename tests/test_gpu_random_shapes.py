@@ -14,7 +14,8 @@ forced one-pass tiles sweep as the oracle does; random certified solves end
 eps-feasible on the exact data; a context reloaded with random systems and a
 batch whose systems come and go at random keep stepping as the oracle does;
 served requests receiving random updates end eps-feasible on their final data;
-the relaxed step of Algorithm 1 matches the oracle's on random shapes.
+the relaxed step of Algorithm 1 matches the oracle's on random shapes;
+contexts driven concurrently from threads give the bits of sequential runs.
 """
 import sys
 
@@ -464,3 +465,47 @@ def test_random_shape_relaxed_step_matches_oracle(P, k):
     s_y = np.linalg.norm(weighted_abs_rows(sys_.A, dtype, np.where(near, o.t / o.nu, 0)))
     bound = tol * (np.linalg.norm(x) + lam * s_y / o.h)
     assert np.linalg.norm(x1 - xo) <= bound, (np.linalg.norm(x1 - xo), bound)
+
+
+def test_contexts_driven_from_threads_equal_sequential_runs(P):
+    """Eight contexts, each driven by its own host thread on its own stream
+    (their kernels overlap on the device; small systems take the resident
+    form, larger ones two kernels per iteration): sweeps, queued iterations
+    under drift and solves give the same bits as the same work run one
+    context after another."""
+    import threading
+    import torch
+
+    def job(k, stream, out):
+        rng = np.random.default_rng(np.random.SeedSequence([2003, 9956, 14000 + k]))
+        dtype = ("f64", "f32", "bf16")[k % 3]
+        n = int(np.exp(rng.uniform(np.log(16.0), np.log(6000.0))))
+        m = int(n * rng.uniform(1.5, 3.0))
+        sys_ = W.gaussian(n, m, seed=k, dtype=dtype)
+        V = W.drift(n, 400, sigma=1e-5, seed=k)
+        x0 = sys_.z + rng.normal(scale=1.5 / np.sqrt(n) + 0.1, size=n)
+        with P.Solver(0, stream=stream.cuda_stream if stream is not None else None) as s:
+            s.set_system(sys_.A, sys_.b, x0=x0, dtype=dtype)
+            g = s.eval_sweep(x0)
+            s.set_drift(V)
+            s.iterate(20, P.params(lam=0.2, eps=1e-9))
+            x20 = s.query()[0]
+            st, code = s.solve(P.params(lam=0.2, eps=1e-6, max_iters=3000), raise_on_stop=False)
+            out[k] = (g.y.copy(), g.h, x20, int(code), int(st.iters), s.query()[0], int(st.resident))
+
+    seq, par = {}, {}
+    for k in range(8):
+        job(k, None, seq)
+    streams = [torch.cuda.Stream() for _ in range(8)]
+    threads = [threading.Thread(target=job, args=(k, streams[k], par)) for k in range(8)]
+    say("eight contexts from eight threads")
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=300)
+    assert sorted(par) == list(range(8))
+    assert {par[k][6] for k in range(8)} == {0, 1}      # both iteration forms ran
+    for k in range(8):
+        a, b = seq[k], par[k]
+        assert np.array_equal(a[0], b[0]) and a[1] == b[1] and np.array_equal(a[2], b[2]), k
+        assert a[3] == b[3] and a[4] == b[4] and np.array_equal(a[5], b[5]), k
