@@ -705,7 +705,7 @@ modap_status plan_resident(modap_ctx *c) {
     const size_t lds = resident_lds_bytes(c->dt, (int)rows, (int)ldR);
     int max_lds = 0;
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess ||
-        lds + 1024 > (size_t)max_lds)
+        lds + kResidentStaticLds > (size_t)max_lds)
         return MODAP_OK;
     const size_t acc = acc_size(c->dt);
     HIP_TRY(c, hipMalloc(&c->res_part, 2 * (size_t)kResidentMaxGrid * (size_t)ldR * acc));

@@ -107,6 +107,7 @@ constexpr int kResidentMaxGrid = 32;    // workgroups of a resident launch at mo
 constexpr int kResidentThreads = 512;   // threads of a resident workgroup (8 wavefronts)
 constexpr int kResidentWaves = kResidentThreads / 64;
 constexpr int kResidentRowsAtOnce = 4;  // rows a wavefront sweeps at once
+constexpr int kResidentStaticLds = 1024; // bytes of static LDS a resident workgroup uses at most
 
 // CPL = columns per lane (the LDS row length is 64 CPL); a template
 // parameter, so that a row's loads are issued together and its values stay in
@@ -151,6 +152,9 @@ __global__ __launch_bounds__(kResidentThreads) void resident_iterate(const Resid
     off += up16((size_t)ldR * sizeof(Acc));
     Acc *yw = reinterpret_cast<Acc *>(lds + off);   // [NW][ldR]
     __shared__ double hw[NW * RA], dw[NW * RA], bw[NW * RA], qw[NW];
+    __shared__ State st_shared;   // the decision, taken by the last wavefront
+    static_assert((3 * NW * RA + NW) * sizeof(double) + sizeof(State) <= kResidentStaticLds,
+                  "static LDS within what the host plans for");
 
     // the band, the committed state and the vectors
     const T *Ag = reinterpret_cast<const T *>(a.A);
@@ -320,14 +324,20 @@ __global__ __launch_bounds__(kResidentThreads) void resident_iterate(const Resid
             break;
         }
         // every workgroup: y as the sum of the G partials in workgroup order,
-        // FP64; ||y||^2 in a fixed order; the totals (an integer sum and two
-        // maxima, exact in any order) in every wavefront.  Every load is
-        // issued before the first use (no branches: slots and lanes past G
-        // read slot G-1 and are masked out of the sums).
+        // FP64, and ||y||^2 in a fixed order, by the threads that hold a
+        // column; the totals (an integer sum and two maxima, exact in any
+        // order) and the decision by the last wavefront, once, shared through
+        // LDS.  Every load is issued before the first use (slots past G are
+        // not read; lanes past G read slot G-1 and are masked out).
+        const bool decider = wave == NW - 1;
         const int gl = min(lane, G - 1);
-        const int64_t hr = a.h_part[par * G + gl];
-        const double dr = a.dmax_part[par * G + gl];
-        const double br = a.binf_part[par * G + gl];
+        int64_t hr = 0;
+        double dr = 0.0, br = 0.0;
+        if (decider) {
+            hr = a.h_part[par * G + gl];
+            dr = a.dmax_part[par * G + gl];
+            br = a.binf_part[par * G + gl];
+        }
         double q = 0.0;
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
@@ -336,26 +346,29 @@ __global__ __launch_bounds__(kResidentThreads) void resident_iterate(const Resid
             const Acc *pc = part + (int64_t)par * kResidentMaxGrid * ldR + c;
             Acc t[kResidentMaxGrid];
 #pragma unroll
-            for (int gg = 0; gg < kResidentMaxGrid; ++gg) t[gg] = pc[(int64_t)min(gg, G - 1) * ldR];
+            for (int gg = 0; gg < kResidentMaxGrid; ++gg) t[gg] = gg < G ? pc[(int64_t)gg * ldR] : (Acc)0;
             double s = 0.0;
 #pragma unroll
             for (int gg = 0; gg < kResidentMaxGrid; ++gg) s += gg < G ? (double)t[gg] : 0.0;
             y64[c] = s;
             q += s * s;
         }
-        q = wave_total(q);
+        if (wave * 64 < ldR) q = wave_total(q);   // (the other wavefronts hold no column)
         if (lane == 0) qw[wave] = q;
-        Totals t{};
-        t.h = (int64_t)wave_total(lane < G ? (double)hr : 0.0);   // integers below 2^53: exact
-        t.dmax = wave_max_nan(lane < G ? dr : 0.0);
-        t.binf = wave_max_nan(lane < G ? br : 0.0);
         __syncthreads();
-        {
+        if (decider) {
+            Totals t{};
+            t.h = (int64_t)wave_total(lane < G ? (double)hr : 0.0);   // integers below 2^53: exact
+            t.dmax = wave_max_nan(lane < G ? dr : 0.0);
+            t.binf = wave_max_nan(lane < G ? br : 0.0);
             double qq = qw[0];
 #pragma unroll
             for (int w = 1; w < NW; ++w) qq += qw[w];
-            st = decide(st, t, sqrt(qq), a.dp, step_limit, sched_len);
+            const State s = decide(st, t, sqrt(qq), a.dp, step_limit, sched_len);
+            if (lane == 0) st_shared = s;
         }
+        __syncthreads();
+        st = st_shared;
         // the step (x <- x - s y, one rounding) and the translation due at the
         // next sweep (the row requested before the barrier, when one is due)
         const double step = st.s;
