@@ -286,6 +286,10 @@ __global__ __launch_bounds__(kResidentThreads) void resident_iterate(const Resid
             bw[wave * RA + lane] = binf;
         }
         __syncthreads();
+        // the workgroup's partial y and totals, stored as agent-scope atomics:
+        // they are written through to where every workgroup reads them as
+        // they are stored, so the release at the barrier finds nothing left
+        // to write back
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             const int c = tid + NT * k;
@@ -293,7 +297,8 @@ __global__ __launch_bounds__(kResidentThreads) void resident_iterate(const Resid
                 Acc sum = yw[c];
 #pragma unroll
                 for (int w = 1; w < NW; ++w) sum += yw[w * ldR + c];
-                part[((int64_t)par * kResidentMaxGrid + g) * ldR + c] = sum;
+                __hip_atomic_store(&part[((int64_t)par * kResidentMaxGrid + g) * ldR + c], sum, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         if (wave == NW - 1) {   // the workgroup's shares of h, dmax, ||b||inf
@@ -302,9 +307,9 @@ __global__ __launch_bounds__(kResidentThreads) void resident_iterate(const Resid
             const double dd = wave_max_nan(in ? dw[lane] : 0.0);
             const double bm = wave_max_nan(in ? bw[lane] : 0.0);
             if (lane == 0) {
-                a.h_part[par * G + g] = (int64_t)hh;
-                a.dmax_part[par * G + g] = dd;
-                a.binf_part[par * G + g] = bm;
+                __hip_atomic_store(&a.h_part[par * G + g], (int64_t)hh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&a.dmax_part[par * G + g], dd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&a.binf_part[par * G + g], bm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         // Before the barrier (they depend on the state this sweep ran under
@@ -355,12 +360,14 @@ __global__ __launch_bounds__(kResidentThreads) void resident_iterate(const Resid
         }
         if (wave * 64 < ldR) q = wave_total(q);   // (the other wavefronts hold no column)
         if (lane == 0) qw[wave] = q;
-        __syncthreads();
-        if (decider) {
-            Totals t{};
+        Totals t{};
+        if (decider) {   // (while the other wavefronts wait for their loads)
             t.h = (int64_t)wave_total(lane < G ? (double)hr : 0.0);   // integers below 2^53: exact
             t.dmax = wave_max_nan(lane < G ? dr : 0.0);
             t.binf = wave_max_nan(lane < G ? br : 0.0);
+        }
+        __syncthreads();
+        if (decider) {
             double qq = qw[0];
 #pragma unroll
             for (int w = 1; w < NW; ++w) qq += qw[w];
