@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_y(const ReduceArgs a) {
     constexpr int RPW = 64 / LPRR;              // partial rows per wavefront load
     constexpr int NWR = kReduceThreads / 64;    // wavefronts per workgroup
     constexpr int RG = NWR * RPW;               // row groups per workgroup
-    constexpr int U = 8;                        // loads in flight per lane
+    constexpr int U = 16;                       // loads in flight per lane
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_y(const ReduceArgs a) {
             a.y[col] = yv;
             sq = yv * yv;
         }
-        sq = wave_sum(sq);
+        sq = wave_total(sq);
         if (tid == 0) a.ynp[blockIdx.x] = sq;
     }
     if (blockIdx.x != 0) return;
@@ -177,12 +177,11 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_y(const ReduceArgs a) {
         dm = max_nan(dm, a.dmax_part[g]);
         bm = max_nan(bm, a.binf_part[g]);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        h += __shfl_xor(h, o, 64);
-        dm = max_nan(dm, __shfl_xor(dm, o, 64));
-        bm = max_nan(bm, __shfl_xor(bm, o, 64));
-    }
+    // across each wavefront with DPP moves (no permute round trips): h as an
+    // FP64 sum of integers below 2^53 (exact), the maxima in any order
+    h = (int64_t)wave_total((double)h);
+    dm = wave_max_nan(dm);
+    bm = wave_max_nan(bm);
     __shared__ int64_t hw[NWR];
     __shared__ double dw[NWR], bw[NWR];
     if (lane == 0) {

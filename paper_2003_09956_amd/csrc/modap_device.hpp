@@ -317,7 +317,7 @@ __device__ __forceinline__ double wave_max_nan(double v) {
 __device__ __forceinline__ double ynorm_of(const double *ynp, int R, int lane) {
     double s = 0.0;
     for (int r = lane; r < R; r += 64) s += load_global(ynp + r);
-    s = wave_sum(s);
+    s = wave_total(s);   // DPP moves: no permute round trips before the decision
     return sqrt(s);
 }
 
