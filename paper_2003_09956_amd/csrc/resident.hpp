@@ -102,6 +102,39 @@ __device__ __forceinline__ typename Store<DT>::Acc widen(typename Store<DT>::T v
         return v;
 }
 
+// Totals of four per-lane values over the 64 lanes of a wavefront whose lanes
+// are all active: the total of d_j in lanes 16j .. 16j+15.  The lane swaps of
+// gfx950 pair the halves and then the quarters of the wavefront (value j and
+// j+2 share a swap across the halves, j and j+1 across the quarters), each
+// pair added lower lane first, and a DPP sum inside each row of 16 lanes
+// finishes: three exchanges for the four values instead of one full sum each.
+template <typename T>
+__device__ __forceinline__ T swap_add(T a, T b, bool halves) {
+    if constexpr (sizeof(T) == 4) {
+        const auto r = halves ? __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, a),
+                                                                 __builtin_bit_cast(uint32_t, b), false, false)
+                              : __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(uint32_t, a),
+                                                                 __builtin_bit_cast(uint32_t, b), false, false);
+        return __builtin_bit_cast(T, (uint32_t)r[0]) + __builtin_bit_cast(T, (uint32_t)r[1]);
+    } else {
+        const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+        const uint32_t al = (uint32_t)ua, ah = (uint32_t)(ua >> 32), bl = (uint32_t)ub, bh = (uint32_t)(ub >> 32);
+        const auto lo = halves ? __builtin_amdgcn_permlane32_swap(al, bl, false, false)
+                               : __builtin_amdgcn_permlane16_swap(al, bl, false, false);
+        const auto hi = halves ? __builtin_amdgcn_permlane32_swap(ah, bh, false, false)
+                               : __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
+        const T a2 = __builtin_bit_cast(T, ((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0]);
+        const T b2 = __builtin_bit_cast(T, ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1]);
+        return a2 + b2;
+    }
+}
+template <typename T>
+__device__ __forceinline__ T quad_total(T d0, T d1, T d2, T d3) {
+    const T e02 = swap_add(d0, d2, true);    // lanes 0-31: d0, lanes 32-63: d2
+    const T e13 = swap_add(d1, d3, true);    // lanes 0-31: d1, lanes 32-63: d3
+    return row_total(swap_add(e02, e13, false));
+}
+
 constexpr int kResidentMaxCols = 512;   // LDS row length limit (8 columns per lane)
 constexpr int kResidentMaxGrid = 32;    // workgroups of a resident launch at most
 constexpr int kResidentThreads = 512;   // threads of a resident workgroup (8 wavefronts)
@@ -208,9 +241,11 @@ __global__ __launch_bounds__(kResidentThreads) void resident_iterate(const Resid
             vr[k] = apply ? va[lane + 64 * k] : (Acc)0;
             yacc[k] = (Acc)0;
         }
-        // lane j < RA of a wavefront settles row j of each of its batches and
+        // lane 16j of a wavefront settles row j of each of its batches and
         // keeps that row's share of h, dmax and ||b||inf
-        const int jl = lane & (RA - 1);
+        static_assert(RA == 4, "the four rows of a batch are reduced together");
+        const int jl = lane >> 4;
+        const bool settler = (lane & 15) == 0;
         double h = 0.0, dmax = 0.0, binf = 0.0;
         // (compiled with and without the translation of the data)
         auto sweep_band = [&](auto with_translation) {
@@ -237,21 +272,11 @@ __global__ __launch_bounds__(kResidentThreads) void resident_iterate(const Resid
                         if constexpr (AP) tdot[j] = fma(vr[k], av[j][k], tdot[j]);
                     }
                 }
-#pragma unroll
-                for (int j = 0; j < RA; ++j) {
-                    dot[j] = wave_total(dot[j]);
-                    if constexpr (AP) tdot[j] = wave_total(tdot[j]);
-                }
-                double dj = dot[0], tj = AP ? (double)tdot[0] : 0.0;
-#pragma unroll
-                for (int j = 1; j < RA; ++j) {
-                    if (jl == j) {
-                        dj = dot[j];
-                        if constexpr (AP) tj = tdot[j];
-                    }
-                }
+                const double dj = quad_total(dot[0], dot[1], dot[2], dot[3]);
+                double tj = 0.0;
+                if constexpr (AP) tj = quad_total(tdot[0], tdot[1], tdot[2], tdot[3]);
                 const int rj = base + wave + NW * jl;
-                const bool okj = lane < RA && rj < nr;
+                const bool okj = settler && rj < nr;
                 const int rc = okj ? rj : 0;
                 double bb = bs[rc];
                 if constexpr (AP) bb += tj;
@@ -267,7 +292,7 @@ __global__ __launch_bounds__(kResidentThreads) void resident_iterate(const Resid
                 const Acc w = pos ? (Acc)(rr / nus[rc]) : (Acc)0;
 #pragma unroll
                 for (int j = 0; j < RA; ++j) {
-                    const Acc wj = lane_value(w, j);
+                    const Acc wj = lane_value(w, 16 * j);
 #pragma unroll
                     for (int k = 0; k < CPL; ++k) yacc[k] = fma(wj, av[j][k], yacc[k]);
                 }
@@ -280,10 +305,10 @@ __global__ __launch_bounds__(kResidentThreads) void resident_iterate(const Resid
         // the wavefronts' partials, summed in wavefront order
 #pragma unroll
         for (int k = 0; k < CPL; ++k) yw[wave * ldR + lane + 64 * k] = yacc[k];
-        if (lane < RA) {
-            hw[wave * RA + lane] = h;
-            dw[wave * RA + lane] = dmax;
-            bw[wave * RA + lane] = binf;
+        if (settler) {
+            hw[wave * RA + jl] = h;
+            dw[wave * RA + jl] = dmax;
+            bw[wave * RA + jl] = binf;
         }
         __syncthreads();
         // the workgroup's partial y and totals, stored as agent-scope atomics:
