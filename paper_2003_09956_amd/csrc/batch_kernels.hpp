@@ -505,10 +505,12 @@ __device__ void batch_item_short(const BatchArgs &a, const BatchSys &Sref, int64
         for (int e = 0; e < VEC; ++e) {
             Acc v = yacc[c][e];
 #pragma unroll
-            for (int o = LPR; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+            for (int o = LPR; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+            if constexpr (LPR <= 16) v = xor_add<16>(v);
+            if constexpr (LPR <= 32) v = xor_add<32>(v);
             yacc[c][e] = v;
         }
-    h = wave_sum(h);
+    h = (decltype(h))wave_total((double)h);   // an integer below 2^53: exact
     dmax = wave_max_nan(dmax);
     binf = wave_max_nan(binf);
     batch_item_end<DT, C>(a, S, k, band, yacc, h, dmax, binf, lds, hsh, dsh, bsh, col_of, g == 0);
@@ -601,12 +603,11 @@ __global__ __launch_bounds__(256) void reduce_batch(const BatchArgs a, const Bat
     __shared__ int64_t hw[kBatchWaves];
     __shared__ double dw[kBatchWaves], bw[kBatchWaves];
     if (cb.blk == 0) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            h += __shfl_xor(h, o, 64);
-            dm = max_nan(dm, __shfl_xor(dm, o, 64));
-            bm = max_nan(bm, __shfl_xor(bm, o, 64));
-        }
+        // DPP moves, no permute round trips: h an FP64 sum of integers below
+        // 2^53 (exact), the maxima in any order
+        h = (int64_t)wave_total((double)h);
+        dm = wave_max_nan(dm);
+        bm = wave_max_nan(bm);
         if (lane == 0) {
             hw[wave] = h;
             dw[wave] = dm;

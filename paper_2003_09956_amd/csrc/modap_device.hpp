@@ -296,6 +296,40 @@ __device__ __forceinline__ T wave_total(T v) {
     return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
+// The gfx950 lane swaps.  With halves, lanes 32-63 of a trade places with
+// lanes 0-31 of b; without, in each half of the wavefront the upper 16 lanes
+// of a trade places with the lower 16 of b.  Returns the sum of the two
+// results: lanes 0-31 hold a(l) + a(l+32) and lanes 32-63 b(l-32) + b(l)
+// (halves), or lanes 16q .. 16q+15 the same pattern of quarters.  With a == b
+// every lane gets v(l) + v(l ^ 32) (or ^ 16): the bits of a shuffle and an
+// add, without the permute unit.
+template <typename T>
+__device__ __forceinline__ T lane_swap_add(T a, T b, bool halves) {
+    if constexpr (sizeof(T) == 4) {
+        const auto r = halves ? __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, a),
+                                                                 __builtin_bit_cast(uint32_t, b), false, false)
+                              : __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(uint32_t, a),
+                                                                 __builtin_bit_cast(uint32_t, b), false, false);
+        return __builtin_bit_cast(T, (uint32_t)r[0]) + __builtin_bit_cast(T, (uint32_t)r[1]);
+    } else {
+        const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+        const uint32_t al = (uint32_t)ua, ah = (uint32_t)(ua >> 32), bl = (uint32_t)ub, bh = (uint32_t)(ub >> 32);
+        const auto lo = halves ? __builtin_amdgcn_permlane32_swap(al, bl, false, false)
+                               : __builtin_amdgcn_permlane16_swap(al, bl, false, false);
+        const auto hi = halves ? __builtin_amdgcn_permlane32_swap(ah, bh, false, false)
+                               : __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
+        const T a2 = __builtin_bit_cast(T, ((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0]);
+        const T b2 = __builtin_bit_cast(T, ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1]);
+        return a2 + b2;
+    }
+}
+// v(l) + v(l ^ O) in every lane, O = 16 or 32 (all lanes active).
+template <int O, typename T>
+__device__ __forceinline__ T xor_add(T v) {
+    static_assert(O == 16 || O == 32, "swaps of quarters or halves");
+    return lane_swap_add(v, v, O == 32);
+}
+
 // NaN-propagating maximum (fmax would drop a NaN).
 __device__ __forceinline__ double max_nan(double a, double b) {
     return (b > a || b != b) ? b : a;

@@ -103,36 +103,16 @@ __device__ __forceinline__ typename Store<DT>::Acc widen(typename Store<DT>::T v
 }
 
 // Totals of four per-lane values over the 64 lanes of a wavefront whose lanes
-// are all active: the total of d_j in lanes 16j .. 16j+15.  The lane swaps of
-// gfx950 pair the halves and then the quarters of the wavefront (value j and
-// j+2 share a swap across the halves, j and j+1 across the quarters), each
-// pair added lower lane first, and a DPP sum inside each row of 16 lanes
-// finishes: three exchanges for the four values instead of one full sum each.
-template <typename T>
-__device__ __forceinline__ T swap_add(T a, T b, bool halves) {
-    if constexpr (sizeof(T) == 4) {
-        const auto r = halves ? __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, a),
-                                                                 __builtin_bit_cast(uint32_t, b), false, false)
-                              : __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(uint32_t, a),
-                                                                 __builtin_bit_cast(uint32_t, b), false, false);
-        return __builtin_bit_cast(T, (uint32_t)r[0]) + __builtin_bit_cast(T, (uint32_t)r[1]);
-    } else {
-        const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
-        const uint32_t al = (uint32_t)ua, ah = (uint32_t)(ua >> 32), bl = (uint32_t)ub, bh = (uint32_t)(ub >> 32);
-        const auto lo = halves ? __builtin_amdgcn_permlane32_swap(al, bl, false, false)
-                               : __builtin_amdgcn_permlane16_swap(al, bl, false, false);
-        const auto hi = halves ? __builtin_amdgcn_permlane32_swap(ah, bh, false, false)
-                               : __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
-        const T a2 = __builtin_bit_cast(T, ((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0]);
-        const T b2 = __builtin_bit_cast(T, ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1]);
-        return a2 + b2;
-    }
-}
+// are all active: the total of d_j in lanes 16j .. 16j+15.  The lane swaps
+// pair the halves and then the quarters of the wavefront (value j and j+2
+// share a swap across the halves, j and j+1 across the quarters), each pair
+// added lower lane first, and a DPP sum inside each row of 16 lanes finishes:
+// three exchanges for the four values instead of one full sum each.
 template <typename T>
 __device__ __forceinline__ T quad_total(T d0, T d1, T d2, T d3) {
-    const T e02 = swap_add(d0, d2, true);    // lanes 0-31: d0, lanes 32-63: d2
-    const T e13 = swap_add(d1, d3, true);    // lanes 0-31: d1, lanes 32-63: d3
-    return row_total(swap_add(e02, e13, false));
+    const T e02 = lane_swap_add(d0, d2, true);   // lanes 0-31: d0, lanes 32-63: d2
+    const T e13 = lane_swap_add(d1, d3, true);   // lanes 0-31: d1, lanes 32-63: d3
+    return row_total(lane_swap_add(e02, e13, false));
 }
 
 constexpr int kResidentMaxCols = 512;   // LDS row length limit (8 columns per lane)

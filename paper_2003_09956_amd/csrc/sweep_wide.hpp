@@ -55,12 +55,12 @@ __device__ __forceinline__ uint4 load_row_vec(__amdgpu_buffer_rsrc_t r, uint32_t
 
 // Sum over each group of LPR = 16 or 32 consecutive lanes (every lane of a
 // group holds the same bits): the DPP stages of a 16-lane row, then for 32
-// lanes one exchange with the partner row.
+// lanes one lane swap with the partner row.
 template <int LPR, typename T>
 __device__ __forceinline__ T group_total(T v) {
     static_assert(LPR == 16 || LPR == 32, "groups of 16 or 32 lanes");
     v = row_total(v);
-    if constexpr (LPR == 32) v += __shfl_xor(v, 16, 64);
+    if constexpr (LPR == 32) v = xor_add<16>(v);
     return v;
 }
 
