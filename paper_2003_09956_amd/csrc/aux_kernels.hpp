@@ -301,6 +301,7 @@ __global__ void ctl_init(Ctrl *c) {
     c->sched_len = 0;
     c->barrier = 0;
     c->fault = 0;
+    c->exits = 0;
 }
 
 // A new approximation: counters restart, no step is pending.

@@ -732,7 +732,8 @@ bool use_resident(const modap_ctx *c, const modap_params *p) {
 // every check it makes, so no stage kernel follows).
 modap_status launch_resident(modap_ctx *c, const modap_params *p, int track, int64_t K, double *bytes) {
     const bool hv = translation_possible(c);
-    HIP_TRY(c, hipMemsetAsync(&c->ctl->barrier, 0, sizeof(uint32_t), c->stream));   // the fault flag stays raised
+    // (the arrival counters were cleared by the last workgroup of the previous
+    // launch, or by set_system; the fault flag stays raised)
     ResidentArgs r{};
     r.A = c->A;
     r.ldA = c->ldA;

@@ -48,7 +48,9 @@ struct alignas(128) Ctrl {
     int64_t sched_len;    // rows in the drift schedule
     uint32_t barrier;     // arrivals at the grid barriers of a resident launch (zero before each)
     uint32_t fault;       // a resident launch gave up waiting at a grid barrier
-    int64_t pad[13];
+    uint32_t exits;       // workgroups of a resident launch that have left it (zero before each)
+    uint32_t pad32;
+    int64_t pad[12];
 };
 
 // Totals of the sweep's per-workgroup scalars, formed by the reduction.

@@ -395,6 +395,18 @@ __global__ __launch_bounds__(kResidentThreads) void resident_iterate(const Resid
         }
         __syncthreads();
     }
+    // The last workgroup to leave clears the arrival counters for the next
+    // launch on this stream (a kernel, not a memory set, so that the stream's
+    // work stays kernels only).  Every workgroup has then left its loop, so
+    // none is still reading them; a fault stays raised in ctl->fault.
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t out = __hip_atomic_fetch_add(&a.ctl->exits, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (out == (uint32_t)G - 1) {
+            __hip_atomic_store(&a.ctl->barrier, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.ctl->exits, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
     if (failed) return;
 
     // write back: the band's b; workgroup 0 the vectors and the state
